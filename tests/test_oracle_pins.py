@@ -1,0 +1,434 @@
+"""Pins of the CPU oracle against facts other than the oracle itself.
+
+Each test fixes part of the oracle by mathematics or by an independent
+routine: the kernel's defining properties (compact support, C^2 smoothness,
+unit normalisation), exact lattice shell sums in 50-digit arithmetic,
+closed-form roots, Poisson statistics, brute force against the k-d tree,
+NumPy's stable sort, finite differences and exact invariants of the adjoint.
+A plausible slip anywhere in the oracle (a dropped term, a wrong sign, a
+wrong constant, a missed periodic image, a transposed operand) fails one of
+them.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+
+import oracle
+import sphgen
+
+# ----------------------------------------------------------------- kernel
+
+
+def test_kernel_normalisation_exact():
+    # 4 pi int_0^h r^2 W(r,h) dr = 32 int_0^1 q^2 f(q) dq = 1.  q^2 f(q) is a
+    # quintic on each branch, so 4-point Gauss-Legendre per branch is exact.
+    xg, wg = np.polynomial.legendre.leggauss(4)
+    tot = 0.0
+    for a, b in ((0.0, 0.5), (0.5, 1.0)):
+        q = 0.5 * (b - a) * xg + 0.5 * (b + a)
+        tot += 0.5 * (b - a) * sum(w * qq * qq * oracle.kernel_f(qq) for qq, w in zip(q, wg))
+    assert abs(32.0 * tot - 1.0) < 1e-15
+    # the same through W(r, h) at a non-trivial h
+    h = 0.37
+    tot = 0.0
+    for a, b in ((0.0, 0.5 * h), (0.5 * h, h)):
+        r = 0.5 * (b - a) * xg + 0.5 * (b + a)
+        tot += 0.5 * (b - a) * sum(w * rr * rr * oracle.kernel_W(rr, h) for rr, w in zip(r, wg))
+    assert abs(4.0 * math.pi * tot - 1.0) < 1e-14
+
+
+def test_kernel_defining_properties():
+    # A piecewise cubic on [0,1/2] and [1/2,1] is fixed by: f(0)=1, f'(0)=0,
+    # C^2 at 1/2, and f = f' = f'' = 0 at q = 1 (8 conditions, 8 coefficients).
+    f, fp = oracle.kernel_f, oracle.kernel_dfdq
+    assert f(0.0) == 1.0
+    assert fp(0.0) == 0.0
+    for q in (1.0, 1.0 + 1e-12, 1.5, 7.0):
+        assert f(q) == 0.0 and fp(q) == 0.0
+    eps = 1e-5
+    # first derivative of f matches dfdq (central difference, O(eps^2))
+    for q in np.linspace(0.01, 0.99, 37):
+        fd = (f(q + eps) - f(q - eps)) / (2 * eps)
+        assert abs(fd - fp(q)) < 1e-8, q
+    # continuity of f, f', f'' at q = 1/2 and q = 1 (one-sided differences)
+    for q0 in (0.5, 1.0):
+        e = 1e-7
+        assert abs(f(q0 - e) - f(q0 + e)) < 1e-6
+        assert abs(fp(q0 - e) - fp(q0 + e)) < 1e-5
+        d2l = (fp(q0 - e) - fp(q0 - 2 * e)) / e
+        d2r = (fp(q0 + 2 * e) - fp(q0 + e)) / e if q0 < 1.0 else 0.0
+        assert abs(d2l - d2r) < 1e-4
+    assert abs(fp(1.0 - 1e-7)) < 1e-12
+    # monotone non-increasing on [0, 1]
+    qs = np.linspace(0.0, 1.0, 2001)
+    vals = np.array([f(q) for q in qs])
+    assert np.all(np.diff(vals) <= 0.0)
+
+
+# ----------------------------------------------------------- keys & sort
+
+
+def test_morton_hand_keys():
+    # q = floor(x * 2^21 / L); x bit k -> key bit 3k+2, y -> 3k+1, z -> 3k.
+    L = 1.0
+    x = np.array([0.5, 0.0, 0.0, 0.0, 1.0 - 2.0 ** -21, 0.75, 0.999999999999])
+    y = np.array([0.25, 0.5, 0.0, 0.0, 1.0 - 2.0 ** -21, 0.0, 0.0])
+    z = np.array([0.0, 0.0, 0.5, 2.0 ** -21, 1.0 - 2.0 ** -21, 0.0, 0.0])
+    k = oracle.morton_periodic(x, y, z, L)
+    assert int(k[0]) == (1 << 62) | (1 << 58)      # qx = 2^20, qy = 2^19
+    assert int(k[1]) == 1 << 61                     # qy = 2^20
+    assert int(k[2]) == 1 << 60                     # qz = 2^20
+    assert int(k[3]) == 1                           # qz = 1
+    assert int(k[4]) == (1 << 63) - 1               # all 63 bits set
+    assert int(k[5]) == (1 << 62) | (1 << 59)      # qx = 2^20 + 2^19
+    assert int(k[6]) == sum(1 << (3 * b + 2) for b in range(21))  # qx = 2^21-1
+    # box scaling: x = 3.0 in a box of 4 -> qx = 3 * 2^19
+    k2 = oracle.morton_periodic(np.array([3.0]), np.array([0.0]), np.array([0.0]), 4.0)
+    assert int(k2[0]) == (1 << (3 * 20 + 2)) | (1 << (3 * 19 + 2))
+    # clamps: x = L -> 2^21-1, NaN and negatives -> 0
+    k3 = oracle.morton_periodic(np.array([1.0, np.nan, -0.1]), np.zeros(3), np.zeros(3), 1.0)
+    assert int(k3[0]) == sum(1 << (3 * b + 2) for b in range(21))
+    assert int(k3[1]) == 0 and int(k3[2]) == 0
+
+
+def test_morton_group_keys():
+    # group g in bits 48..63; 16 bits per axis on the group's bounding cube
+    off = np.array([0, 2, 5], dtype=np.int64)
+    x = np.array([1.0, 3.0, 0.0, 0.5, 1.0])
+    y = np.array([2.0, 2.0, 0.0, 0.25, 0.0])
+    z = np.array([0.0, 1.0, 0.0, 0.0, 0.0])
+    k = oracle.morton_groups(off, x, y, z)
+    # group 0: lo = (1,2,0), extent 2 -> scale 2^15; particle 1 -> qx = 2^16 (clamped
+    # to 2^16-1), qy = 0, qz = 2^15
+    assert int(k[0]) == 0
+    qx = (1 << 16) - 1
+    want = sum(((qx >> b) & 1) << (3 * b + 2) for b in range(16)) | (1 << (3 * 15))
+    assert int(k[1]) == want
+    # group 1: extent 1 -> scale 2^16; (0.5, 0.25, 0) -> qx = 2^15, qy = 2^14
+    assert int(k[2]) == 1 << 48
+    assert int(k[3]) == (1 << 48) | (1 << (3 * 15 + 2)) | (1 << (3 * 14 + 1))
+    assert int(k[4]) == (1 << 48) | sum(1 << (3 * b + 2) for b in range(16))
+
+
+def test_stable_sort_matches_numpy():
+    rng = np.random.default_rng(7)
+    keys = rng.integers(0, 50, size=5000).astype(np.uint64) << np.uint64(40)
+    srt, perm = oracle.stable_sort(keys)
+    ref = np.argsort(keys, kind="stable")
+    assert np.array_equal(perm, ref.astype(np.int32))
+    assert np.array_equal(srt, keys[ref])
+
+
+def test_cell_table_matches_unique():
+    ps = sphgen.config("uniform4096")
+    s = oracle.sort(ps)
+    assert s["level"] == 3
+    shift = np.uint64(3 * (21 - 3))
+    u, idx, cnt = np.unique(s["sorted_keys"] >> shift, return_index=True, return_counts=True)
+    assert np.array_equal(s["cell_id"], u)
+    assert np.array_equal(s["cell_start"], idx.astype(np.int32))
+    assert np.array_equal(s["cell_count"], cnt.astype(np.int32))
+    assert int(s["cell_count"].sum()) == ps.n
+
+
+def test_cell_level_rule():
+    assert oracle.cell_level(4096, False) == 3
+    assert oracle.cell_level(1 << 20, False) == 6
+    assert oracle.cell_level(1 << 24, False) == 7
+    assert oracle.cell_level(1, False) == 1
+    assert oracle.cell_level(100, False) == 2
+    assert oracle.cell_level(1 << 60, True) == 16
+
+
+def test_sort_conserves_mass():
+    ps = sphgen.plummer_mixture(20000, 20, seed=11)
+    ps.m = np.random.default_rng(3).random(ps.n)
+    s = oracle.sort(ps)
+    perm = s["perm"]
+    assert np.array_equal(np.sort(perm), np.arange(ps.n))
+    ms = ps.m[perm]
+    back = np.empty_like(ms)
+    back[perm] = ms
+    assert np.array_equal(back, ps.m)
+    assert np.sum(back) == np.sum(ps.m)
+    assert np.all(np.diff(s["sorted_keys"].astype(np.float64)) >= 0)
+
+
+# -------------------------------------------------------- neighbour sums
+
+
+@pytest.mark.parametrize("kind", ["uniform", "clustered", "corners", "groups"])
+def test_kdtree_matches_brute_force(kind):
+    rng = np.random.default_rng(5)
+    if kind == "uniform":
+        ps = sphgen.uniform(3000, seed=5)
+        h = rng.uniform(0.05, 0.2, ps.n)
+    elif kind == "clustered":
+        ps = sphgen.plummer_mixture(3000, 6, seed=6)
+        h = rng.uniform(0.002, 0.12, ps.n)
+    elif kind == "corners":
+        # particles hugging faces, edges and corners of the periodic box
+        ps = sphgen.uniform(2000, seed=8)
+        p = rng.random((ps.n, 3))
+        p = np.where(p < 0.5, p * 0.05, 1.0 - p * 0.05)
+        p = np.minimum(p, np.nextafter(1.0, 0))
+        ps.x, ps.y, ps.z = (np.ascontiguousarray(p[:, a]) for a in range(3))
+        h = rng.uniform(0.05, 0.45, ps.n)
+    else:
+        ps = sphgen.groups(40, seed=9, lo=5, hi=300)
+        h = rng.uniform(0.001, 0.05, ps.n)
+    a = oracle.eval_at_h(ps, h, search=0)
+    b = oracle.eval_at_h(ps, h, search=1)
+    assert np.array_equal(a["nngb"], b["nngb"])
+    for key in ("rho", "nw"):
+        np.testing.assert_allclose(b[key], a[key], rtol=1e-13, atol=1e-300)
+    # dn/dh and drho/dh sum terms of both signs: compare on the sum's scale
+    for key in ("dndh", "drhodh"):
+        np.testing.assert_allclose(b[key], a[key], rtol=1e-13,
+                                   atol=1e-13 * np.abs(a[key]).max())
+
+
+def test_lattice_shells_exact():
+    # Simple cubic lattice, spacing a = 1/8, h = 2a: the neighbours inside h are
+    # the point itself and shells of 6 (r=a), 12 (r=a sqrt2) and 8 (r=a sqrt3);
+    # the 6 at r = 2a = h are excluded by the strict test.  50-digit sums.
+    nside = 8
+    a = 1.0 / nside
+    ps = sphgen.lattice(nside, h=2 * a, jitter_seed=1)
+    e = oracle.eval_at_h(ps, ps.h_init, search=0)
+    mpmath.mp.dps = 50
+
+    def f(q):
+        q = mpmath.mpf(q)
+        if q <= mpmath.mpf(1) / 2:
+            return 1 - 6 * q ** 2 + 6 * q ** 3
+        return 2 * (1 - q) ** 3
+
+    shells = [(1, 0), (6, 1), (12, 2), (8, 3)]  # (multiplicity, r^2 / a^2)
+    S0 = sum(k * f(mpmath.sqrt(r2) / 2) for k, r2 in shells)
+    n_exact = mpmath.mpf(32) / 3 * S0
+    h = mpmath.mpf(2) / nside
+    rho_exact = mpmath.mpf(8) / (mpmath.pi * h ** 3) * S0 / nside ** 3
+    assert np.all(e["nngb"] == 27)
+    np.testing.assert_allclose(e["nw"], float(n_exact), rtol=1e-14)
+    np.testing.assert_allclose(e["rho"], float(rho_exact), rtol=1e-14)
+
+
+@pytest.mark.parametrize("ha", [4.0, 5.0, 6.0])
+def test_lattice_riemann_limit(ha):
+    # For h >> a the lattice sum of m W tends to the integral of W times the
+    # number density: rho -> m / a^3 = 1 (unit box, total mass 1).
+    nside = 12
+    ps = sphgen.lattice(nside, h=ha / nside)
+    e = oracle.eval_at_h(ps, ps.h_init, search=1)
+    assert np.ptp(e["rho"]) < 1e-13  # all sites equal (translation symmetry)
+    assert abs(e["rho"].mean() - 1.0) < 2e-4
+
+
+def test_self_only():
+    # h below the nearest-neighbour distance: only j = i, f(0) = 1.
+    ps = sphgen.lattice(4, h=0.1)
+    ps.m = np.linspace(0.5, 2.0, ps.n)
+    e = oracle.eval_at_h(ps, ps.h_init, search=0)
+    assert np.all(e["nngb"] == 1)
+    assert np.all(e["nw"] == 32.0 / 3.0)
+    np.testing.assert_allclose(e["rho"], ps.m * 8.0 / (math.pi * 0.1 ** 3), rtol=1e-15)
+    assert np.all(e["dndh"] == 0.0)
+
+
+def test_poisson_statistics():
+    # Uniform points: E[n_i] = 32/3 + (4 pi / 3) h^3 (N - 1) because the mean
+    # of f over the unit ball is 3/32; E[N_i] = 1 + (4 pi/3) h^3 (N-1).
+    ps = sphgen.uniform(20000, seed=12)
+    h = np.full(ps.n, 0.06)
+    e = oracle.eval_at_h(ps, h, search=1)
+    vol = 4.0 * math.pi / 3.0 * 0.06 ** 3 * (ps.n - 1)
+    assert abs(e["nw"].mean() - (32.0 / 3.0 + vol)) < 0.01 * vol
+    assert abs(e["nngb"].mean() - (1.0 + vol)) < 0.01 * vol
+
+
+# ------------------------------------------------------------ h iteration
+
+
+def _two_particles(d, nt):
+    off = np.array([0, 2], dtype=np.int64)
+    return sphgen.ParticleSet(
+        x=np.array([0.1, 0.1 + d]), y=np.array([0.2, 0.2]), z=np.array([0.3, 0.3]),
+        m=np.array([1.0, 1.0]), h_init=np.array([0.5, 0.25]), periodic=False, box=1.0,
+        n_target=nt, n_tol=1.0, offsets=off)
+
+
+@pytest.mark.parametrize("y", [0.05, 0.2, 0.4, 0.8])
+def test_two_particle_root_closed_form(y):
+    # n(h) = (32/3)(1 + f(d/h)) for h > d.  Target N_t = (32/3)(1 + y):
+    # outer branch (y < 1/4): 2 (1-q)^3 = y -> q = 1 - (y/2)^(1/3);
+    # inner branch: 1 - 6 q^2 + 6 q^3 = y, the root in (0, 1/2).
+    d = 0.3
+    nt = 32.0 / 3.0 * (1.0 + y)
+    if y < 0.25:
+        q = 1.0 - (y / 2.0) ** (1.0 / 3.0)
+    else:
+        r = np.roots([6.0, -6.0, 0.0, 1.0 - y])
+        r = [v.real for v in r if abs(v.imag) < 1e-12 and 0.0 < v.real <= 0.5]
+        assert len(r) == 1
+        q = r[0]
+    h_exact = d / q
+    ps = _two_particles(d, nt)
+    s = oracle.solve(ps, mode=oracle.ROOT, root_tol=1e-15, search=0)
+    assert np.all((s["status"] >> 16) == 0)
+    np.testing.assert_allclose(s["h"], h_exact, rtol=1e-13)
+    np.testing.assert_allclose(s["nw"], nt, rtol=1e-13)
+
+
+def test_band_solve_uniform_config():
+    ps = sphgen.config("uniform4096")
+    s = oracle.solve(ps, search=1)
+    assert np.all((s["status"] >> 16) == 0)
+    assert np.all(np.abs(s["nw"] - 64.0) <= 2.0)
+    # re-evaluating at the returned h reproduces n and the counts
+    e = oracle.eval_at_h(ps, s["h"], search=0)
+    np.testing.assert_allclose(e["nw"], s["nw"], rtol=1e-14)
+    assert np.array_equal(e["nngb"], s["nngb"].astype(np.int64))
+    # expected scale: (4 pi/3) h^3 N ~ 53 neighbours -> h ~ 0.146
+    assert 0.14 < np.median(s["h"]) < 0.155
+    # warm start from the converged h needs no update
+    w = oracle.solve(ps, h_init=s["h"], search=1)
+    assert np.all((w["status"] & 0xFFFF) == 0)
+    np.testing.assert_array_equal(w["h"], s["h"])
+
+
+def test_active_set_shrinks():
+    # the number of particles still iterating drops pass after pass
+    ps = sphgen.config("uniform4096")
+    s = oracle.solve(ps, search=1)
+    it = s["status"] & 0xFFFF
+    alive = [(it >= k).sum() for k in range(it.max() + 1)]
+    assert all(b <= a for a, b in zip(alive, alive[1:]))
+    assert alive[-1] < alive[0] / 4
+
+
+def test_failure_flags():
+    # max_iter = 1: particles still outside the band after one update -> NOCONV
+    ps = sphgen.config("uniform4096")
+    s = oracle.solve(ps, max_iter=1, search=1)
+    noconv = (s["status"] & oracle.ST_NOCONV) != 0
+    assert noconv.any()
+    assert np.all(np.abs(s["nw"][~noconv] - 64.0) <= 2.0)
+    # a 3-particle isolated group can never reach 64 neighbours
+    g = sphgen.ParticleSet(x=np.array([0.0, 0.1, 0.2]), y=np.zeros(3), z=np.zeros(3),
+                           m=np.ones(3), h_init=np.full(3, 0.05), periodic=False, box=1.0,
+                           n_target=64.0, n_tol=2.0, offsets=np.array([0, 3]))
+    s = oracle.solve(g, search=0)
+    assert np.all((s["status"] & oracle.ST_UNREACHABLE) != 0)
+    # 4 particles in a periodic box: h hits L/2 first -> H_TOO_LARGE
+    p = sphgen.uniform(4, seed=3)
+    s = oracle.solve(p, search=0)
+    assert np.all((s["status"] & oracle.ST_HTOOLARGE) != 0)
+    assert np.all(s["h"] == 0.5 * (1.0 - 2.0 ** -20))
+
+
+def test_bad_input_excluded():
+    ps = sphgen.uniform(500, seed=4)
+    ref = oracle.solve(ps, search=0)
+    bad = sphgen.uniform(500, seed=4)
+    x = bad.x.copy()
+    x = np.concatenate([x, [np.nan, 0.5]])
+    bad.x = x
+    bad.y = np.concatenate([bad.y, [0.5, 1.5]])  # second extra: outside the box
+    bad.z = np.concatenate([bad.z, [0.5, 0.5]])
+    bad.m = np.concatenate([bad.m, [1.0, 1.0]])
+    bad.h_init = np.concatenate([bad.h_init, [0.1, 0.1]])
+    s = oracle.solve(bad, search=0)
+    assert np.all((s["status"][-2:] & oracle.ST_BADINPUT) != 0)
+    np.testing.assert_array_equal(s["h"][:-2], ref["h"])
+    np.testing.assert_array_equal(s["rho"][:-2], ref["rho"])
+
+
+# --------------------------------------------------------------- adjoint
+
+
+def _loss(ps, gr, gh, pos=None, m=None):
+    q = sphgen.ParticleSet(**{**ps.__dict__})
+    if pos is not None:
+        q.x, q.y, q.z = (np.ascontiguousarray(pos[:, a]) for a in range(3))
+    if m is not None:
+        q.m = m
+    s = oracle.solve(q, mode=oracle.ROOT, root_tol=1e-15, search=0, max_iter=200)
+    assert np.all((s["status"] >> 16) == 0)
+    return float(np.dot(gr, s["rho"]) + np.dot(gh, s["h"])), s
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_adjoint_matches_central_differences(periodic):
+    rng = np.random.default_rng(21)
+    n = 100
+    if periodic:
+        ps = sphgen.uniform(n, seed=22, n_target=16.0, n_tol=1.0)
+    else:
+        ps = sphgen.groups(1, seed=23, sizes=np.array([n]), n_target=16.0, n_tol=1.0)
+    ps.m = rng.uniform(0.5, 1.5, n)
+    gr = rng.standard_normal(n)
+    gh = rng.standard_normal(n)
+    L0, s0 = _loss(ps, gr, gh)
+    g = oracle.backward(ps, s0["h"], gr, gh, search=0)
+    pos = ps.pos.copy()
+    eps = 1e-6
+    scale = np.abs(np.concatenate([g["gx"], g["gy"], g["gz"]])).max()
+    for k in rng.choice(n, 12, replace=False):
+        for a, key in enumerate(("gx", "gy", "gz")):
+            pp = pos.copy()
+            pm = pos.copy()
+            pp[k, a] += eps
+            pm[k, a] -= eps
+            fd = (_loss(ps, gr, gh, pos=pp)[0] - _loss(ps, gr, gh, pos=pm)[0]) / (2 * eps)
+            assert abs(fd - g[key][k]) < 2e-6 * scale, (k, a, fd, g[key][k])
+    mscale = np.abs(g["gm"]).max()
+    for k in rng.choice(n, 8, replace=False):
+        mp = ps.m.copy()
+        mm = ps.m.copy()
+        mp[k] += eps
+        mm[k] -= eps
+        fd = (_loss(ps, gr, gh, m=mp)[0] - _loss(ps, gr, gh, m=mm)[0]) / (2 * eps)
+        assert abs(fd - g["gm"][k]) < 2e-6 * mscale
+
+
+def test_adjoint_invariants():
+    rng = np.random.default_rng(31)
+    ps = sphgen.groups(3, seed=32, sizes=np.array([200, 150, 90]), n_target=32.0, n_tol=1.0)
+    ps.m = rng.uniform(0.5, 1.5, ps.n)
+    s = oracle.solve(ps, mode=oracle.ROOT, root_tol=1e-14, search=1)
+    gr = rng.standard_normal(ps.n)
+    gh = rng.standard_normal(ps.n)
+    g = oracle.backward(ps, s["h"], gr, gh, search=1)
+    gx = np.stack([g["gx"], g["gy"], g["gz"]], axis=1)
+    scale = np.abs(gx).max() * ps.n
+    # translation invariance within each isolated group: sum_k dL/dx_k = 0
+    for a, b in zip(ps.offsets[:-1], ps.offsets[1:]):
+        assert np.all(np.abs(gx[a:b].sum(axis=0)) < 1e-12 * scale)
+    # mass linearity: sum_j m_j dL/dm_j = sum_i gr_i rho_i
+    lhs = float(np.dot(ps.m, g["gm"]))
+    rhs = float(np.dot(gr, s["rho"]))
+    assert abs(lhs - rhs) < 1e-12 * np.abs(gr * s["rho"]).sum()
+    # homogeneity about each group's centre: rho ~ s^-3, h ~ s under x -> s x
+    tot = 0.0
+    for a, b in zip(ps.offsets[:-1], ps.offsets[1:]):
+        c = ps.pos[a:b].mean(axis=0)
+        tot += float(np.sum((ps.pos[a:b] - c) * gx[a:b]))
+    want = -3.0 * float(np.dot(gr, s["rho"])) + float(np.dot(gh, s["h"]))
+    assert abs(tot - want) < 1e-9 * (np.abs(gr * s["rho"]).sum() + np.abs(gh * s["h"]).sum())
+
+
+def test_adjoint_lattice_site_symmetry():
+    # on a perfect lattice, d rho_i / d x_i = 0 and the gradient sums to zero
+    ps = sphgen.lattice(6, h=0.3, n_target=40.0, n_tol=1.0)
+    s = oracle.solve(ps, mode=oracle.ROOT, root_tol=1e-14, search=0)
+    i = 17
+    gr = np.zeros(ps.n)
+    gr[i] = 1.0
+    g = oracle.backward(ps, s["h"], gr, None, search=0)
+    scale = max(abs(g["gx"]).max(), 1e-300)
+    assert abs(g["gx"][i]) < 1e-10 * scale and abs(g["gy"][i]) < 1e-10 * scale
+    assert abs(g["gz"][i]) < 1e-10 * scale
+    assert abs(g["gx"].sum()) < 1e-10 * scale * ps.n
