@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Benchmark of the SPH density hot path on one MI355X.
+
+A step is one full pass of the path over the 2^20-particle clustered set
+(200 Plummer spheres + 30% uniform background, periodic unit cube, equal
+masses, N_t = 64 +- 2, h_init = 2 N^(-1/3)): Morton keys, radix sort,
+cell tables, and the FP32-compensated density + smoothing-length solve.
+The same input is also timed with the plain FP64 solve, reported beside it.
+
+Prints ONE JSON line.  ``value`` = in-range particle-neighbour pairs
+evaluated per second over the whole step (every trial h counts);
+``roofline`` is the density kernel's algorithmic FLOP rate (8 FLOP per
+candidate pair tested, 31 per in-range pair in FP32C / 22 in FP64) over
+its own duration, measured with HIP events on the launch stream, against
+the MI355X FP32 vector peak.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-neighbour interactions/s and particles/s for density+h solve, FP32 vs FP64"
+PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed) FLOP/s
+PEAK_FP64 = 78.6e12    # MI355X vector FP64 FLOP/s
+FLOP_CAND = 8.0        # 3 differences + r^2 (two FMA) + compare
+FLOP_PAIR = {"fp32c": 31.0, "fp64": 22.0}
+
+
+class HipEvents:
+    """hipEvent_t pairs through the HIP runtime (timing only)."""
+
+    def __init__(self):
+        self.hip = C.CDLL("libamdhip64.so")
+        self.hip.hipEventCreate.argtypes = [C.POINTER(C.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        self.hip.hipEventSynchronize.argtypes = [C.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [C.c_void_p]
+
+    def create(self):
+        e = C.c_void_p()
+        rc = self.hip.hipEventCreate(C.byref(e))
+        if rc != 0:
+            raise RuntimeError(f"hipEventCreate failed: {rc}")
+        return e
+
+    def elapsed_ms(self, a, b):
+        self.hip.hipEventSynchronize(b)
+        ms = C.c_float()
+        rc = self.hip.hipEventElapsedTime(C.byref(ms), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed: {rc}")
+        return float(ms.value)
+
+
+def run_form(sph, torch, d, ps, precision, steps, warmup, ev):
+    p = sph.default_params(periodic=1, box=ps.box, n_target=ps.n_target, n_tol=ps.n_tol,
+                           precision=precision)
+    n = ps.n
+    ws = sph.workspace(p, n, 0, d["x"].device)
+    outs = None
+    for _ in range(warmup):
+        outs = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, stats=True,
+                                 ws=ws)
+    torch.cuda.synchronize()
+    pairs = [(ev.create(), ev.create()) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        p.prof_events[0] = pairs[k][0]
+        p.prof_events[1] = pairs[k][1]
+        outs = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, stats=True,
+                                 ws=ws)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kern_ms = [ev.elapsed_ms(a, b) for a, b in pairs]
+    st = outs["stats"].cpu().numpy().astype(np.int64)
+    status = outs["status"].cpu().numpy()
+    nngb = outs["nngb"].cpu().numpy()
+    for a, b in pairs:
+        ev.hip.hipEventDestroy(a)
+        ev.hip.hipEventDestroy(b)
+    return dict(ms_per_step=1e3 * wall / steps, kernel_ms=float(np.mean(kern_ms)),
+                pairs=int(st[0]), cands=int(st[1]), passes=int(st[2]),
+                final_pairs=int(nngb.astype(np.int64).sum()),
+                flagged=int(((status >> 16) != 0).sum()))
+
+
+def cpu_baseline(ps, budget_s=15.0):
+    """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
+    import oracle
+    rng = np.random.default_rng(12345)
+    cores = oracle.max_threads()
+    t0 = time.perf_counter()
+    probe = rng.choice(ps.n, 2000, replace=False)
+    r = oracle.solve(ps, subset=probe)
+    t_probe = time.perf_counter() - t0
+    k = int(min(ps.n, max(2000, 2000 * budget_s / max(t_probe, 1e-3))))
+    sub = rng.choice(ps.n, k, replace=False)
+    t0 = time.perf_counter()
+    r = oracle.solve(ps, subset=sub)
+    dt = time.perf_counter() - t0
+    pairs = int(r["pairs"].sum())
+    return {"value": pairs / dt, "unit": "interactions/s", "cores": cores, "kind": "oracle",
+            "sample": f"{k} particles drawn uniformly from the {ps.n}-particle clustered set, "
+                      f"each solved to convergence against the full set (FP64 k-d tree, "
+                      f"{dt:.1f} s incl. tree build); particles/s = {k / dt:.4g}",
+            "particles_per_s": k / dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is "
+              "single-GPU in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1612_06090_amd as sph
+    import sphgen
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    sph.load()
+    ps = sphgen.config("clustered2^20")
+    d = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+         for k in ("x", "y", "z", "m", "h_init")}
+    ev = HipEvents()
+    print(f"[bench] n={ps.n} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    f32 = run_form(sph, torch, d, ps, sph.FP32C, args.steps, args.warmup, ev)
+    print(f"[bench] fp32c {f32}", file=sys.stderr, flush=True)
+    f64 = None
+    if not args.no_fp64:
+        f64 = run_form(sph, torch, d, ps, sph.FP64, max(3, args.steps // 2), 1, ev)
+        print(f"[bench] fp64 {f64}", file=sys.stderr, flush=True)
+
+    def roof(r, form):
+        flop = FLOP_CAND * r["cands"] + FLOP_PAIR[form] * r["pairs"]
+        ach = flop / (r["kernel_ms"] * 1e-3)
+        peak = PEAK_FP32 if form == "fp32c" else PEAK_FP64
+        return {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+                "frac": ach / peak, "traffic": None, "kernel": "k_solve",
+                "kernel_ms": r["kernel_ms"], "flop_per_launch": flop}
+
+    value = f32["pairs"] / (f32["ms_per_step"] * 1e-3)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "clustered2^20: 2^20 particles, 200 Plummer spheres (a log-uniform "
+                               "0.005-0.05, mass slope -2) + 30% uniform background, periodic "
+                               "unit cube, equal masses, M4 spline, N_t = 64 +- 2, "
+                               "h_init = 2 N^-1/3, sort + FP32-compensated solve per step",
+                   "n": ps.n, "precision": "fp32c", "parallelism": "single-gpu"},
+        "particles_per_s": ps.n / (f32["ms_per_step"] * 1e-3),
+        "final_pairs_per_s": f32["final_pairs"] / (f32["ms_per_step"] * 1e-3),
+        "pairs_per_step": f32["pairs"],
+        "candidates_per_step": f32["cands"],
+        "passes_per_step": f32["passes"],
+        "roofline": roof(f32, "fp32c"),
+    }
+    if f64 is not None:
+        line["fp64"] = {
+            "value": f64["pairs"] / (f64["ms_per_step"] * 1e-3), "unit": "interactions/s",
+            "ms_per_step": f64["ms_per_step"],
+            "particles_per_s": ps.n / (f64["ms_per_step"] * 1e-3),
+            "roofline": roof(f64, "fp64"),
+        }
+        line["fp32c_speedup_over_fp64"] = f64["ms_per_step"] / f32["ms_per_step"]
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(ps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) SPH density library, libsph.so.
+ *
+ * The library computes, for every particle i, the SPH density
+ *     rho_i = sum_j m_j W(|r_i - r_j|, h_i)
+ * (Baruffa et al., arXiv:1612.06090, Sec. II-B, Eq. 1, evaluated in gather
+ * form with the particle's own smoothing length, over the neighbours "within
+ * a smoothing length" of Listing 1, self term included) together with the
+ * smoothing length h_i, which is adjusted per particle until its weighted
+ * neighbour count n_i = (4 pi/3) h_i^3 sum_j W(r_ij, h_i) reaches the target
+ * (the recompute loop of Sec. IV-A, Listings 2 and 3).  W is the M4 cubic
+ * spline with compact support h: W = 8/(pi h^3) f(r/h),
+ * f(q) = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1), 0 beyond.
+ *
+ * Conventions shared by every entry point:
+ *  - All array arguments are DEVICE pointers on the current HIP device,
+ *    except `params` and `bytes`, which are host pointers.
+ *  - Particle arrays are structure-of-arrays (the SoA layout of Sec. IV-B):
+ *    x[n], y[n], z[n], m[n], ... of element type io_dtype (double or float).
+ *  - The caller owns every buffer, including the workspace `ws` of at least
+ *    sph_workspace_size() bytes (256-byte aligned).  No call allocates or
+ *    frees device memory, synchronises the host, or prints.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  Argument errors are detected on the host and returned
+ *    synchronously before anything is enqueued.  Per-particle conditions
+ *    detected on the device never fail the call: they set bits of
+ *    status_out[i] (below), readable after the stream completes.
+ *  - Outputs of sph_density_solve / sph_density_backward are in the
+ *    caller's original particle order.  sph_sort returns sorted order.
+ *  - One workspace must not be used by two calls that may run concurrently.
+ *    The library holds no other state; calls on different workspaces are
+ *    thread-safe.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPH_ABI_VERSION 1u
+
+/* return codes */
+#define SPH_OK            0
+#define SPH_E_INVALID    (-1)  /* bad argument: null pointer, n out of range, bad enum, ... */
+#define SPH_E_WORKSPACE  (-2)  /* ws_bytes smaller than sph_workspace_size() */
+#define SPH_E_HIP        (-3)  /* a HIP launch failed; see sph_last_hip_error() */
+#define SPH_E_UNSUPPORTED (-4) /* valid but not supported combination */
+
+/* precision: arithmetic of the pair loop */
+#define SPH_FP64   0   /* IEEE binary64 throughout; pair distances bit-identical to a
+                          plain (dx*dx + dy*dy) + dz*dz evaluation without FMA */
+#define SPH_FP32C  1   /* pair distances and kernel sums in binary32 from positions
+                          stored relative to Morton-cell origins, compensated (Kahan)
+                          sums; h iteration and convergence test in binary64 */
+
+/* io_dtype: element type of caller arrays x, y, z, m, h_init, rho, h, nw, grads */
+#define SPH_F64    0
+#define SPH_F32    1
+
+/* mode: stopping rule of the h iteration */
+#define SPH_BAND   0   /* stop when |n - n_target| <= n_tol */
+#define SPH_ROOT   1   /* stop when |n - n_target| <= root_tol * n_target, or when the
+                          bracket [lo, hi] has shrunk to 4 ulp(h) */
+
+/* status_out[i]: low 16 bits = number of h updates made, high bits = flags */
+#define SPH_ST_ITER_MASK   0xFFFF
+#define SPH_ST_NOCONV      (1 << 16)  /* max_iter updates without meeting the stopping rule */
+#define SPH_ST_HTOOLARGE   (1 << 17)  /* periodic: h needed >= box/2 (h is left at
+                                         box/2 (1 - 2^-20), the largest allowed) */
+#define SPH_ST_BADINPUT    (1 << 18)  /* non-finite x, y, z, m or h_init, h_init <= 0, or
+                                         (periodic) a coordinate outside [0, box).  Such a
+                                         particle is never anyone's neighbour; its rho and
+                                         nw are NaN, h = h_init, nngb = 0. */
+#define SPH_ST_UNREACHABLE (1 << 19)  /* isolated group of n_g particles with
+                                         (32/3) n_g < n_target - n_tol: evaluated at
+                                         h_init only */
+
+/* Parameters.  Initialise with sph_default_params() and override fields. */
+typedef struct {
+    uint32_t abi_version;   /* must be SPH_ABI_VERSION */
+    int32_t  precision;     /* SPH_FP64 | SPH_FP32C */
+    int32_t  io_dtype;      /* SPH_F64 | SPH_F32 */
+    int32_t  mode;          /* SPH_BAND | SPH_ROOT */
+    int32_t  periodic;      /* 1: one periodic cube [0, box)^3 (n_groups must be 0);
+                               0: isolated groups given by group_offsets */
+    int32_t  max_iter;      /* h updates allowed per particle, 0..65535 (default 64);
+                               0 = evaluate at h_init only */
+    double   box;           /* periodic box side L > 0 */
+    double   n_target;      /* N_t > 0: target weighted neighbour count (e.g. 64) */
+    double   n_tol;         /* dN >= 0: band half-width (e.g. 2) */
+    double   root_tol;      /* SPH_ROOT relative tolerance (default 1e-12) */
+    int32_t  cell_level;    /* level of the cell table returned by sph_sort;
+                               -1 = max(1, ceil((ceil(log2 n) - 3) / 3)) */
+    int32_t  tile_cell;     /* tuning: neighbour-cell side in units of the tile's largest
+                               h, as a power of two exponent in {-1, 0} (default 0);
+                               results do not depend on it */
+    int32_t  waves_per_cu;  /* tuning: persistent grid = 256 CUs x this (default 8) */
+    int32_t  segment;       /* tuning: sorted particles per work item (multiple of 64;
+                               default 64) */
+    void    *prof_events[2];/* optional hipEvent_t pair recorded on `stream` immediately
+                               before and after the density kernel (NULL: none) */
+    int32_t  reserved[8];   /* must be zero */
+} sph_params;
+
+/* Fill *p with the defaults: FP64 compute and io, band mode, periodic unit
+ * box, n_target 64, n_tol 2, root_tol 1e-12, max_iter 64, cell_level -1. */
+void sph_default_params(sph_params *p);
+
+/* Host only.  Bytes of workspace needed by sph_sort, sph_density_solve and
+ * sph_density_backward for n particles in n_groups groups (0 = one periodic
+ * set).  The size is monotone in n.  Returns SPH_OK or SPH_E_INVALID. */
+int sph_workspace_size(const sph_params *params, int64_t n, int32_t n_groups, size_t *bytes);
+
+/* The spatial sort that precedes the density loop (no counterpart in the
+ * paper, whose Barnes-Hut tree is given; Sec. II-A).
+ *   Keys: periodic -- q = floor(x * (2^21/box)) per axis clamped to
+ *   [0, 2^21 - 1]; key bit 3k+2 = bit k of qx, 3k+1 of qy, 3k of qz.
+ *   Groups -- key = (g << 48) | the same interleave of 16-bit
+ *   q = floor((x - lo_g) * (2^16 / E_g)) on the group's bounding cube
+ *   (lower corner lo_g, side E_g = largest extent, 1 if 0).
+ *   Sort: ascending by key, stable (equal keys keep caller order).
+ * Outputs (device, capacity n each):
+ *   keys_out[s]  sorted keys;   perm_out[s] = caller index of sorted slot s;
+ *   cell_id_out[c], cell_start_out[c], cell_count_out[c] for the occupied
+ *   cells at level L = params->cell_level (or the default rule): cell id =
+ *   key >> 3(21 - L) (groups: 3(16 - L)), in ascending order;
+ *   *n_cells_out (device int32) = number of occupied cells.
+ * group_offsets: device int64[n_groups + 1], non-decreasing, offsets[0] = 0,
+ * offsets[n_groups] = n; NULL iff n_groups == 0.  Requires n_groups < 65536.
+ * Any output pointer except keys_out and perm_out may be NULL. */
+int sph_sort(const sph_params *params, int64_t n, int32_t n_groups,
+             const int64_t *group_offsets,
+             const void *x, const void *y, const void *z,
+             uint64_t *keys_out, int32_t *perm_out,
+             uint64_t *cell_id_out, int32_t *cell_start_out, int32_t *cell_count_out,
+             int32_t *n_cells_out,
+             void *ws, size_t ws_bytes, void *stream);
+
+/* Density and smoothing-length solve (Eq. 1 with the recompute loop of
+ * Sec. IV-A).  Per particle, starting from h = h_init (NULL: every particle
+ * starts at 2 (V/n)^(1/3), V = box^3 periodic or the group's bounding-box
+ * volume), repeat: evaluate at h the sums over neighbours j (r_ij^2 < h^2,
+ * minimum image when periodic, same group when isolated)
+ *     S0 = sum f(q), S1 = sum q f'(q), R = sum m_j f(q),   q = r_ij / h,
+ * giving rho = 8R/(pi h^3), n = (32/3) S0, dn/dh = -(32/3) S1/h; stop per
+ * `mode`; else set lo = h if n < N_t, else hi = h, and take the Newton step
+ * h + (N_t - n)/(dn/dh) when dn/dh > 0 and the step lands strictly inside
+ * (lo, hi) and within [h/2, 2h], otherwise 2h (no upper bracket yet), h/2 (no
+ * lower bracket yet) or (lo + hi)/2.  Periodic h is capped at
+ * box/2 (1 - 2^-20).
+ * Outputs (device, caller order, io_dtype unless noted): rho_out, h_out,
+ * nw_out (the weighted count n at the returned h), nngb_out (int32: number
+ * of j with r_ij^2 < h^2, i included), status_out (int32, bits above).
+ * Any output may be NULL except rho_out and h_out.
+ * stats_out: NULL or device uint64[4], overwritten: [0] in-range pairs
+ * evaluated over all trial h, [1] candidate pairs tested, [2] density
+ * passes made (sum over particles of updates + 1), [3] reserved (0). */
+int sph_density_solve(const sph_params *params, int64_t n, int32_t n_groups,
+                      const int64_t *group_offsets,
+                      const void *x, const void *y, const void *z, const void *m,
+                      const void *h_init,
+                      void *rho_out, void *h_out, void *nw_out,
+                      int32_t *nngb_out, int32_t *status_out, uint64_t *stats_out,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of sph_density_solve.  Given the forward's h (h_out) and
+ * cotangents grad_rho (and optionally grad_h, NULL = 0), writes
+ *   grad_x/y/z[k] = d/dx_k sum_i (grad_rho_i rho_i + grad_h_i h_i)
+ *   grad_m[k]     = d/dm_k of the same,
+ * with each h_i held on its implicit root n_i(h_i, x) = n_i(achieved):
+ *   lambda_i = -(grad_rho_i drho_i/dh_i + grad_h_i) / (dn_i/dh_i)
+ *   (0 when dn_i/dh_i = 0), and for each pair j in N(i), j != i, with
+ *   q = r_ij/h_i and unit vector u = (x_i - x_j)/r_ij:
+ *     c_ij = grad_rho_i m_j 8 f'(q)/(pi h_i^4) + lambda_i (32/3) f'(q)/h_i,
+ *     grad_x_i += c_ij u,  grad_x_j -= c_ij u,
+ *     grad_m_j += grad_rho_i W(r_ij, h_i)   (self term included).
+ * Computed in gather form (no floating-point atomics; bitwise reproducible).
+ * Outputs are in caller order, io_dtype, and are overwritten. */
+int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
+                         const int64_t *group_offsets,
+                         const void *x, const void *y, const void *z, const void *m,
+                         const void *h, const void *grad_rho, const void *grad_h,
+                         void *grad_x, void *grad_y, void *grad_z, void *grad_m,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/* Static text for a return code. */
+const char *sph_status_string(int code);
+
+/* The HIP error code of the last SPH_E_HIP returned on the calling thread
+ * (0 if none), and its text. */
+int sph_last_hip_error(void);
+const char *sph_last_hip_error_string(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

@@ -1,0 +1,600 @@
+// Density and smoothing-length solve: Eq. (1) of the paper evaluated in
+// gather form with each particle's own h, inside the per-particle recompute
+// loop of Sec. IV-A (Listings 2 and 3).
+//
+// GPU design (one wavefront = one tile of up to 64 Morton-consecutive
+// particles, one particle per lane):
+//  * Work sharing: a persistent grid pulls tiles from a device work queue
+//    with one atomic per tile -- the lock-free dynamic schedule of Listing 3,
+//    without the single hot lock of Listing 2.
+//  * Neighbour search: instead of the paper's tree walk (Sec. IV-B), the
+//    tile's active particles define a region; the Morton cells covering it at
+//    a level whose cell side is at least the tile's largest h are culled
+//    against every active particle's sphere, and the surviving cells'
+//    contiguous runs of the sorted arrays are streamed through LDS in
+//    coalesced chunks of 64 candidates.  Every lane then reads each candidate
+//    by broadcast and tests it against its own h.  Tiles that straddle a
+//    large jump of the Morton curve are split in halves until the region is
+//    small.
+//  * The in-support test (Listing 1, line 3) is an exact r^2 < h^2 compare;
+//    the kernel sums run only on in-range pairs.
+//  * h iteration: after each pass every lane updates its own h (safeguarded
+//    Newton on the weighted count, FP64); a ballot gives the lanes still
+//    iterating and only they define the next pass's region.  This replaces the
+//    "todo" list of Sec. IV-A: converged lanes drop out of the region.
+//
+// Precision forms:
+//  FP64  -- positions, distances and sums in binary64; r^2 is evaluated as
+//           (dx*dx + dy*dy) + dz*dz without contraction, so neighbour sets at a
+//           given h are bit-identical to a plain CPU evaluation.
+//  FP32C -- positions held as integer Morton-grid coordinates plus binary32
+//           fractions; each tile works relative to an integer origin, so
+//           pair differences carry the precision of the local separation, not
+//           of the box.  Kernel sums in binary32 with Kahan compensation; the
+//           convergence test and the h update stay binary64.
+#include "sph_internal.h"
+
+namespace sph {
+
+constexpr int kMaxRegionCells = 512;  // split tiles whose region needs more cells
+
+struct SolveArgs {
+    int64_t n;
+    int32_t G;
+    const int64_t *goff;
+    const uint64_t *skeys;
+    const int32_t *perm;
+    const double *sx, *sy, *sz, *sm, *sh0;
+    const int32_t *qx, *qy, *qz;
+    const float *fx, *fy, *fz, *fm;
+    const int32_t *table;
+    int32_t Ld;
+    const double *frame;
+    const int32_t *gitems;
+    int64_t n_items;
+    int32_t seg;
+    double box;
+    int32_t bits;
+    double Nt, dN, root_tol;
+    int32_t mode, max_iter, cell_exp;
+    int32_t out_f32;
+    void *rho, *h, *nw;
+    int32_t *nngb, *status;
+    int32_t *queue;
+    uint64_t *stats;
+};
+
+struct HState {
+    double h, lo, hi;
+    int it, flags;
+    bool fixed;
+};
+
+// One update of the h iteration.  Returns true when the particle is finished.
+__device__ inline bool h_step(HState &s, double nwv, double dndh, const SolveArgs &a,
+                              double hmax) {
+    if (s.fixed) return true;
+    bool conv;
+    if (a.mode == SPH_BAND) {
+        conv = fabs(nwv - a.Nt) <= a.dN;
+    } else {
+        conv = fabs(nwv - a.Nt) <= a.root_tol * a.Nt;
+        if (!conv && s.lo > 0.0 && s.hi < INFINITY &&
+            s.hi - s.lo <= 4.0 * (nextafter(s.h, INFINITY) - s.h))
+            conv = true;
+    }
+    if (conv) return true;
+    if (s.it >= a.max_iter) {
+        s.flags |= SPH_ST_NOCONV;
+        return true;
+    }
+    if (nwv < a.Nt) s.lo = s.h; else s.hi = s.h;
+    double hn = 0.0;
+    bool ok = false;
+    if (dndh > 0.0) {
+        hn = s.h + (a.Nt - nwv) / dndh;
+        ok = hn > s.lo && hn < s.hi && hn >= 0.5 * s.h && hn <= 2.0 * s.h;
+    }
+    if (!ok) {
+        if (s.hi == INFINITY) hn = 2.0 * s.h;
+        else if (s.lo == 0.0) hn = 0.5 * s.h;
+        else hn = 0.5 * (s.lo + s.hi);
+    }
+    if (hn >= hmax) {
+        if (s.h == hmax) {
+            s.flags |= SPH_ST_HTOOLARGE;
+            return true;
+        }
+        hn = hmax;
+    }
+    s.h = hn;
+    s.it += 1;
+    return false;
+}
+
+__device__ inline void write_out(const SolveArgs &a, int64_t i, double rho, double h, double nw,
+                                 int32_t nngb, int32_t status) {
+    if (a.out_f32) {
+        st<float>(a.rho, i, rho);
+        st<float>(a.h, i, h);
+        if (a.nw) st<float>(a.nw, i, nw);
+    } else {
+        st<double>(a.rho, i, rho);
+        st<double>(a.h, i, h);
+        if (a.nw) st<double>(a.nw, i, nw);
+    }
+    if (a.nngb) a.nngb[i] = nngb;
+    if (a.status) a.status[i] = status;
+}
+
+// Smallest level-L cell side 2^e (grid units) with 2^e >= v, e >= 0.
+__device__ inline int ceil_log2_pos(double v) {
+    if (!(v > 1.0)) return 0;
+    int ex;
+    const double m = frexp(v, &ex);  // v = m 2^ex, m in [0.5, 1)
+    return m == 0.5 ? ex - 1 : ex;
+}
+
+// Sorted-slot range of the level-L cell with Morton code cm (periodic set).
+__device__ inline void cell_range_periodic(const SolveArgs &a, uint64_t cm, int L, int32_t &st_,
+                                           int32_t &en_) {
+    const int Ld = a.Ld;
+    if (L <= Ld) {
+        const int sh = 3 * (Ld - L);
+        st_ = a.table[cm << sh];
+        en_ = a.table[(cm + 1) << sh];
+        return;
+    }
+    const uint64_t anc = cm >> (3 * (L - Ld));
+    int32_t lo = a.table[anc], hi = a.table[anc + 1];
+    const int ks = 3 * (a.bits - L);
+    const uint64_t k0 = cm << ks, k1 = (cm + 1) << ks;
+    // lower_bound(k0) and lower_bound(k1) inside [lo, hi)
+    int32_t b = lo, e = hi;
+    while (b < e) {
+        const int32_t mid = (b + e) >> 1;
+        if (a.skeys[mid] < k0) b = mid + 1; else e = mid;
+    }
+    st_ = b;
+    e = hi;
+    while (b < e) {
+        const int32_t mid = (b + e) >> 1;
+        if (a.skeys[mid] < k1) b = mid + 1; else e = mid;
+    }
+    en_ = b;
+}
+
+// Same for a cell of group g: binary search inside the group's sorted range.
+__device__ inline void cell_range_group(const SolveArgs &a, int32_t g, uint64_t cm, int L,
+                                        int32_t &st_, int32_t &en_) {
+    const int ks = 3 * (a.bits - L);
+    const uint64_t gb = (uint64_t)(uint32_t)g << 48;
+    const uint64_t k0 = gb + (cm << ks), k1 = gb + ((cm + 1) << ks);
+    int32_t lo = (int32_t)a.goff[g], hi = (int32_t)a.goff[g + 1];
+    int32_t b = lo, e = hi;
+    while (b < e) {
+        const int32_t mid = (b + e) >> 1;
+        if (a.skeys[mid] < k0) b = mid + 1; else e = mid;
+    }
+    st_ = b;
+    e = hi;
+    while (b < e) {
+        const int32_t mid = (b + e) >> 1;
+        if (a.skeys[mid] < k1) b = mid + 1; else e = mid;
+    }
+    en_ = b;
+}
+
+template <int PREC>
+struct CandLDS;
+
+template <>
+struct CandLDS<SPH_FP64> {
+    double x[64], y[64], z[64], m[64], shx[64], shy[64], shz[64];
+};
+
+template <>
+struct CandLDS<SPH_FP32C> {
+    float x[64], y[64], z[64], m[64];
+};
+
+struct Sums {
+    // FP64: s0, s1, r.  FP32C: float sums with Kahan compensations.
+    double d0, d1, dr;
+    float f0, f1, fr, c0, c1, cr;
+    int32_t n;
+};
+
+__device__ inline void kahan(float &s, float &c, float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <int PREC, bool GROUPED>
+__global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
+    __shared__ double act_t[3][64];
+    __shared__ double act_H[64];
+    __shared__ int32_t rg_start[64], rg_excl[64], rg_code[64];
+    __shared__ CandLDS<PREC> cd;
+
+    const int l = threadIdx.x;
+    const int B = a.bits;
+    uint64_t cnt_pairs = 0, cnt_cands = 0, cnt_passes = 0;
+
+    for (;;) {
+        int item = 0;
+        if (l == 0) item = atomicAdd(a.queue, 1);
+        item = __shfl(item, 0, 64);
+        const int64_t n_items = GROUPED ? (int64_t)a.gitems[a.G] : a.n_items;
+        if (item >= n_items) break;
+
+        int64_t b, e;
+        int32_t g = 0;
+        double org0 = 0.0, org1 = 0.0, org2 = 0.0, sc;
+        if (!GROUPED) {
+            b = (int64_t)item * a.seg;
+            e = b + a.seg < a.n ? b + a.seg : a.n;
+            sc = 2097152.0 / a.box;
+        } else {
+            int32_t lo = 0, hi = a.G - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (a.gitems[mid] <= item) lo = mid; else hi = mid - 1;
+            }
+            g = lo;
+            b = a.goff[g] + (int64_t)(item - a.gitems[g]) * a.seg;
+            e = b + a.seg < a.goff[g + 1] ? b + a.seg : a.goff[g + 1];
+            const double *f = a.frame + 8 * (int64_t)g;
+            org0 = f[0]; org1 = f[1]; org2 = f[2];
+            sc = f[6];
+        }
+        const double hmax = GROUPED ? INFINITY : 0.5 * a.box * (1.0 - 0x1p-20);
+
+        const int64_t s = b + l;
+        const bool mine = s < e;
+        // this lane's particle
+        double xi = 0.0, yi = 0.0, zi = 0.0;  // FP64 absolute position
+        int32_t qxi = 0, qyi = 0, qzi = 0;    // FP32C grid coordinates
+        float fxi = 0.f, fyi = 0.f, fzi = 0.f;
+        double tx = 0.0, ty = 0.0, tz = 0.0;  // grid-unit position (culling)
+        HState hs;
+        hs.h = mine ? a.sh0[s] : 1.0;
+        hs.lo = 0.0;
+        hs.hi = INFINITY;
+        hs.it = 0;
+        hs.flags = 0;
+        hs.fixed = a.max_iter == 0;
+        bool valid = false;
+        if (mine) {
+            if (PREC == SPH_FP64) {
+                xi = a.sx[s]; yi = a.sy[s]; zi = a.sz[s];
+                valid = !isnan(xi);
+                tx = (xi - org0) * sc; ty = (yi - org1) * sc; tz = (zi - org2) * sc;
+            } else {
+                qxi = a.qx[s]; qyi = a.qy[s]; qzi = a.qz[s];
+                fxi = a.fx[s]; fyi = a.fy[s]; fzi = a.fz[s];
+                valid = !isnan(fxi);
+                tx = (double)qxi + (double)fxi;
+                ty = (double)qyi + (double)fyi;
+                tz = (double)qzi + (double)fzi;
+            }
+        }
+        const int64_t oi = mine ? (int64_t)a.perm[s] : 0;
+        if (mine && !valid) {
+            write_out(a, oi, NAN, hs.h, NAN, 0, SPH_ST_BADINPUT);
+        }
+        if (GROUPED && mine && valid) {
+            const double ng = (double)(a.goff[g + 1] - a.goff[g]);
+            if ((32.0 / 3.0) * ng < a.Nt - a.dN) {
+                hs.flags |= SPH_ST_UNREACHABLE;
+                hs.fixed = true;
+            }
+        }
+        if (hs.h > hmax) hs.h = hmax;
+        bool done = !(mine && valid);
+
+        for (;;) {
+            const uint64_t am = __ballot(!done);
+            if (am == 0) break;
+            const double hq = hs.h * sc;  // h in grid units
+            const double Hs = hq * (1.0 + 0x1p-20) + 0x1p-20;
+            act_t[0][l] = tx;
+            act_t[1][l] = ty;
+            act_t[2][l] = tz;
+            act_H[l] = done ? -1.0 : Hs;
+            const double h2 = hs.h * hs.h;
+            const float ih2 = (float)(1.0 / (hq * hq));
+            Sums sm;
+            sm.d0 = sm.d1 = sm.dr = 0.0;
+            sm.f0 = sm.f1 = sm.fr = sm.c0 = sm.c1 = sm.cr = 0.f;
+            sm.n = 0;
+            uint64_t my_cands = 0;
+            __syncthreads();
+
+            // sub-tiles: lane ranges [la, lb) of the active set
+            int stk_a[7], stk_b[7];
+            int sp = 0;
+            stk_a[sp] = 0;
+            stk_b[sp] = 64;
+            ++sp;
+            while (sp > 0) {
+                --sp;
+                const int la = stk_a[sp], lb = stk_b[sp];
+                const uint64_t rmask = (lb == 64 ? ~0ull : ((1ull << lb) - 1ull)) &
+                                       ~((1ull << la) - 1ull);
+                const uint64_t sub = am & rmask;
+                if (sub == 0) continue;
+                const bool in_sub = ((sub >> l) & 1ull) != 0;
+                double mn0 = wave_min(in_sub ? tx : INFINITY);
+                double mn1 = wave_min(in_sub ? ty : INFINITY);
+                double mn2 = wave_min(in_sub ? tz : INFINITY);
+                double mx0 = wave_max(in_sub ? tx : -INFINITY);
+                double mx1 = wave_max(in_sub ? ty : -INFINITY);
+                double mx2 = wave_max(in_sub ? tz : -INFINITY);
+                const double Hm = wave_max(in_sub ? Hs : 0.0);
+                int ex = ceil_log2_pos(ldexp(Hm, a.cell_exp));
+                int L = B - ex;
+                const int Lmin = GROUPED ? 0 : 1;
+                if (L < Lmin) { L = Lmin; ex = B - L; }
+                const double side = ldexp(1.0, ex);
+                const double inv = ldexp(1.0, -ex);
+                int64_t clo0 = (int64_t)floor((mn0 - Hm) * inv), chi0 = (int64_t)floor((mx0 + Hm) * inv);
+                int64_t clo1 = (int64_t)floor((mn1 - Hm) * inv), chi1 = (int64_t)floor((mx1 + Hm) * inv);
+                int64_t clo2 = (int64_t)floor((mn2 - Hm) * inv), chi2 = (int64_t)floor((mx2 + Hm) * inv);
+                const int64_t ncell = (int64_t)1 << L;
+                if (GROUPED) {
+                    clo0 = clo0 < 0 ? 0 : clo0; clo1 = clo1 < 0 ? 0 : clo1; clo2 = clo2 < 0 ? 0 : clo2;
+                    chi0 = chi0 >= ncell ? ncell - 1 : chi0;
+                    chi1 = chi1 >= ncell ? ncell - 1 : chi1;
+                    chi2 = chi2 >= ncell ? ncell - 1 : chi2;
+                }
+                const int64_t nx = chi0 - clo0 + 1, ny = chi1 - clo1 + 1, nz = chi2 - clo2 + 1;
+                if (nx <= 0 || ny <= 0 || nz <= 0) continue;
+                const int64_t K = nx * ny * nz;
+                if (K > kMaxRegionCells && __popcll(sub) > 1) {
+                    // split the active lanes of this range into two halves
+                    int cnt = __popcll(sub) / 2;
+                    uint64_t t = sub;
+                    for (int k = 0; k < cnt; ++k) t &= t - 1;  // drop the lowest cnt lanes
+                    const int mid = __ffsll((unsigned long long)t) - 1;
+                    stk_a[sp] = mid; stk_b[sp] = lb; ++sp;
+                    stk_a[sp] = la; stk_b[sp] = mid; ++sp;
+                    continue;
+                }
+                // FP32C tile origin: grid coordinates of the first active lane
+                const int first = __ffsll((unsigned long long)sub) - 1;
+                const int32_t o0 = readlane_i(qxi, first), o1 = readlane_i(qyi, first),
+                              o2 = readlane_i(qzi, first);
+                const float pix = (float)(qxi - o0) + fxi;
+                const float piy = (float)(qyi - o1) + fyi;
+                const float piz = (float)(qzi - o2) + fzi;
+
+                for (int64_t kb = 0; kb < K; kb += 64) {
+                    const int64_t k = kb + l;
+                    bool pass = false;
+                    int32_t c_st = 0, c_en = 0, code = 0;
+                    if (k < K) {
+                        const int64_t c0 = clo0 + k % nx;
+                        const int64_t c1 = clo1 + (k / nx) % ny;
+                        const int64_t c2 = clo2 + k / (nx * ny);
+                        const double lo0 = (double)c0 * side - 0x1p-20, hi0 = (double)(c0 + 1) * side + 0x1p-20;
+                        const double lo1 = (double)c1 * side - 0x1p-20, hi1 = (double)(c1 + 1) * side + 0x1p-20;
+                        const double lo2 = (double)c2 * side - 0x1p-20, hi2 = (double)(c2 + 1) * side + 0x1p-20;
+                        uint64_t it = sub;
+                        while (it) {
+                            const int q = __ffsll((unsigned long long)it) - 1;
+                            it &= it - 1;
+                            const double p0 = act_t[0][q], p1 = act_t[1][q], p2 = act_t[2][q];
+                            const double H = act_H[q];
+                            const double g0 = fmax(0.0, fmax(lo0 - p0, p0 - hi0));
+                            const double g1 = fmax(0.0, fmax(lo1 - p1, p1 - hi1));
+                            const double g2 = fmax(0.0, fmax(lo2 - p2, p2 - hi2));
+                            if (g0 * g0 + g1 * g1 + g2 * g2 <= H * H) { pass = true; break; }
+                        }
+                        if (pass) {
+                            int64_t w0 = c0, w1 = c1, w2 = c2;
+                            int s0 = 0, s1 = 0, s2 = 0;
+                            if (!GROUPED) {
+                                s0 = (int)(c0 >> L); s1 = (int)(c1 >> L); s2 = (int)(c2 >> L);
+                                w0 = c0 & (ncell - 1); w1 = c1 & (ncell - 1); w2 = c2 & (ncell - 1);
+                            }
+                            const uint64_t cm = morton3((uint64_t)w0, (uint64_t)w1, (uint64_t)w2);
+                            if (!GROUPED) cell_range_periodic(a, cm, L, c_st, c_en);
+                            else cell_range_group(a, g, cm, L, c_st, c_en);
+                            code = (s0 + 1) | ((s1 + 1) << 2) | ((s2 + 1) << 4);
+                            pass = c_en > c_st;
+                        }
+                    }
+                    const uint64_t pm = __ballot(pass);
+                    if (pm == 0) continue;
+                    const int cnt = pass ? c_en - c_st : 0;
+                    const int incl = wave_incl_scan(cnt);
+                    const int total = __shfl(incl, 63, 64);
+                    const int nr = __popcll(pm);
+                    __syncthreads();
+                    if (pass) {
+                        const int slot = (int)mbcnt(pm);
+                        rg_start[slot] = c_st;
+                        rg_excl[slot] = incl - cnt;
+                        rg_code[slot] = code;
+                    }
+                    __syncthreads();
+                    if (in_sub) my_cands += (uint64_t)total;
+                    for (int cbase = 0; cbase < total; cbase += 64) {
+                        const int gidx = cbase + l;
+                        if (gidx < total) {
+                            int lo = 0, hi = nr - 1;
+                            while (lo < hi) {
+                                const int mid = (lo + hi + 1) >> 1;
+                                if (rg_excl[mid] <= gidx) lo = mid; else hi = mid - 1;
+                            }
+                            const int64_t j = (int64_t)rg_start[lo] + (gidx - rg_excl[lo]);
+                            const int cc = rg_code[lo];
+                            const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1,
+                                      sh2 = ((cc >> 4) & 3) - 1;
+                            if (PREC == SPH_FP64) {
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
+                                c.x[l] = a.sx[j];
+                                c.y[l] = a.sy[j];
+                                c.z[l] = a.sz[j];
+                                c.m[l] = a.sm[j];
+                                c.shx[l] = (double)sh0 * a.box;
+                                c.shy[l] = (double)sh1 * a.box;
+                                c.shz[l] = (double)sh2 * a.box;
+                            } else {
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
+                                const int32_t W = 1 << B;
+                                c.x[l] = (float)(a.qx[j] + sh0 * W - o0) + a.fx[j];
+                                c.y[l] = (float)(a.qy[j] + sh1 * W - o1) + a.fy[j];
+                                c.z[l] = (float)(a.qz[j] + sh2 * W - o2) + a.fz[j];
+                                c.m[l] = a.fm[j];
+                            }
+                        }
+                        __syncthreads();
+                        const int mc = total - cbase < 64 ? total - cbase : 64;
+                        if (in_sub) {
+                            if (PREC == SPH_FP64) {
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
+                                const double hinv = 1.0 / hs.h;
+                                for (int t = 0; t < mc; ++t) {
+                                    const double dx = (c.x[t] - xi) + c.shx[t];
+                                    const double dy = (c.y[t] - yi) + c.shy[t];
+                                    const double dz = (c.z[t] - zi) + c.shz[t];
+                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                                    if (r2 < h2) {
+                                        const double q = sqrt(r2) * hinv;
+                                        const double q2 = q * q;
+                                        const double u = 1.0 - q;
+                                        const bool inner = q <= 0.5;
+                                        const double f = inner ? 1.0 - 6.0 * q2 + 6.0 * q2 * q
+                                                               : 2.0 * u * u * u;
+                                        const double gq = inner ? q2 * (18.0 * q - 12.0)
+                                                                : -6.0 * q * u * u;
+                                        sm.d0 += f;
+                                        sm.d1 += gq;
+                                        sm.dr += c.m[t] * f;
+                                        sm.n += 1;
+                                    }
+                                }
+                            } else {
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
+                                for (int t = 0; t < mc; ++t) {
+                                    const float dx = c.x[t] - pix;
+                                    const float dy = c.y[t] - piy;
+                                    const float dz = c.z[t] - piz;
+                                    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                                    const float q2 = r2 * ih2;
+                                    if (q2 < 1.0f) {
+                                        const float q = __builtin_sqrtf(q2);
+                                        const float u = 1.0f - q;
+                                        const bool inner = q <= 0.5f;
+                                        const float fin = __builtin_fmaf(q2, __builtin_fmaf(6.0f, q, -6.0f), 1.0f);
+                                        const float fout = 2.0f * u * u * u;
+                                        const float f = inner ? fin : fout;
+                                        const float gin = q2 * __builtin_fmaf(18.0f, q, -12.0f);
+                                        const float gout = -6.0f * q * u * u;
+                                        const float gq = inner ? gin : gout;
+                                        kahan(sm.f0, sm.c0, f);
+                                        kahan(sm.f1, sm.c1, gq);
+                                        kahan(sm.fr, sm.cr, c.m[t] * f);
+                                        sm.n += 1;
+                                    }
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+            }
+
+            if (!done) {
+                double S0, S1, R;
+                if (PREC == SPH_FP64) {
+                    S0 = sm.d0; S1 = sm.d1; R = sm.dr;
+                } else {
+                    S0 = (double)sm.f0 - (double)sm.c0;
+                    S1 = (double)sm.f1 - (double)sm.c1;
+                    R = (double)sm.fr - (double)sm.cr;
+                }
+                const double nwv = (32.0 / 3.0) * S0;
+                const double dndh = -(32.0 / 3.0) * S1 / hs.h;
+                cnt_pairs += (uint64_t)sm.n;
+                cnt_cands += my_cands;
+                cnt_passes += 1;
+                const double hcur = hs.h;
+                if (h_step(hs, nwv, dndh, a, hmax)) {
+                    const double rho = 8.0 * R / (kPi * hcur * hcur * hcur);
+                    write_out(a, oi, rho, hcur, nwv, sm.n, hs.flags | (hs.it & 0xFFFF));
+                    done = true;
+                }
+            }
+        }
+    }
+    if (a.stats) {
+        const uint64_t p = wave_sum(cnt_pairs), c = wave_sum(cnt_cands), q = wave_sum(cnt_passes);
+        if (l == 0) {
+            atomicAdd((unsigned long long *)&a.stats[0], (unsigned long long)p);
+            atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)c);
+            atomicAdd((unsigned long long *)&a.stats[2], (unsigned long long)q);
+        }
+    }
+}
+
+hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw,
+                     int32_t *nngb, int32_t *status, uint64_t *stats, hipStream_t st) {
+    SolveArgs a;
+    a.n = pl.n;
+    a.G = pl.G;
+    a.goff = goff;
+    a.skeys = pl.skeys;
+    a.perm = pl.perm;
+    a.sx = pl.sx; a.sy = pl.sy; a.sz = pl.sz; a.sm = pl.sm; a.sh0 = pl.sh0;
+    a.qx = pl.qx; a.qy = pl.qy; a.qz = pl.qz;
+    a.fx = pl.fx; a.fy = pl.fy; a.fz = pl.fz; a.fm = pl.fm;
+    a.table = pl.table;
+    a.Ld = pl.Ld;
+    a.frame = pl.frame;
+    a.gitems = pl.gitems;
+    a.n_items = pl.n_items;
+    a.seg = pl.prm.segment;
+    a.box = pl.prm.box;
+    a.bits = pl.bits;
+    a.Nt = pl.prm.n_target;
+    a.dN = pl.prm.n_tol;
+    a.root_tol = pl.prm.root_tol;
+    a.mode = pl.prm.mode;
+    a.max_iter = pl.prm.max_iter;
+    a.cell_exp = pl.prm.tile_cell;
+    a.out_f32 = pl.prm.io_dtype == SPH_F32;
+    a.rho = rho; a.h = h; a.nw = nw;
+    a.nngb = nngb; a.status = status;
+    a.queue = pl.ctrl;
+    a.stats = stats;
+    hipError_t e = run_zero_i32(pl.ctrl, 4, st);
+    if (e != hipSuccess) return e;
+    if (stats) {
+        e = run_zero_u64(stats, 4, st);
+        if (e != hipSuccess) return e;
+    }
+    if (pl.prm.prof_events[0]) {
+        e = hipEventRecord((hipEvent_t)pl.prm.prof_events[0], st);
+        if (e != hipSuccess) return e;
+    }
+    const dim3 grid((unsigned)pl.grid), block(64);
+    const bool f32c = pl.prm.precision == SPH_FP32C;
+    if (!pl.grouped) {
+        if (f32c) hipLaunchKernelGGL((k_solve<SPH_FP32C, false>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_solve<SPH_FP64, false>), grid, block, 0, st, a);
+    } else {
+        if (f32c) hipLaunchKernelGGL((k_solve<SPH_FP32C, true>), grid, block, 0, st, a);
+        else hipLaunchKernelGGL((k_solve<SPH_FP64, true>), grid, block, 0, st, a);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (pl.prm.prof_events[1]) e = hipEventRecord((hipEvent_t)pl.prm.prof_events[1], st);
+    return e;
+}
+
+}  // namespace sph

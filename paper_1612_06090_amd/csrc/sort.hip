@@ -1,0 +1,656 @@
+// Spatial sort of the particles: Morton keys, LSD radix sort of (key, index),
+// gather into sorted structure-of-arrays, and the cell tables.
+//
+// The paper's kernel walks a pre-built Barnes-Hut tree (Sec. II-A); on the
+// GPU the particles are instead ordered along a Morton curve, whose key
+// prefixes are exactly the nodes of an octree: a cell at level L is a
+// contiguous run of the sorted array.  The gather into structure-of-arrays
+// follows the SoA redesign of Sec. IV-B (only the fields the density loop
+// reads: positions, mass, smoothing length).
+//
+// Radix sort: least-significant-digit first, 8-bit digits, reduce-then-scan
+// (per-tile digit histograms, a scan of the histograms in digit-major order,
+// then a stable scatter).  Inside a tile each wave ranks 64 consecutive keys
+// per round with 8 ballots (lanes sharing a digit), keeping one running count
+// per digit in LDS, so equal digits keep their input order and every pass is
+// stable.
+#include "sph_internal.h"
+
+#include <limits.h>
+
+namespace sph {
+
+// ------------------------------------------------------------------- keys
+
+template <typename T>
+__global__ void k_keys_periodic(int64_t n, const void *x, const void *y, const void *z,
+                                double box, uint64_t *keys, int32_t *vals) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double s = 2097152.0 / box;
+    const uint32_t qx = quantise(ld<T>(x, i) * s, 1u << 21);
+    const uint32_t qy = quantise(ld<T>(y, i) * s, 1u << 21);
+    const uint32_t qz = quantise(ld<T>(z, i) * s, 1u << 21);
+    keys[i] = morton3(qx, qy, qz);
+    vals[i] = (int32_t)i;
+}
+
+// One block per group: bounding box of the group's finite coordinates.
+// frame[8g + 0..2] = lower corner, [3..5] = extents, [6] = 2^16 / largest
+// extent (largest extent 1 when it is 0), [7] = largest extent.
+template <typename T>
+__global__ __launch_bounds__(256) void k_group_frames(int32_t G, const int64_t *goff,
+                                                      const void *x, const void *y,
+                                                      const void *z, double *frame) {
+    const int g = blockIdx.x;
+    if (g >= G) return;
+    const int64_t b = goff[g], e = goff[g + 1];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+        const double p[3] = {ld<T>(x, i), ld<T>(y, i), ld<T>(z, i)};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (!isfinite(p[a])) continue;
+            lo[a] = fmin(lo[a], p[a]);
+            hi[a] = fmax(hi[a], p[a]);
+        }
+    }
+    __shared__ double red[6][4];
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double vl = wave_min(lo[a]);
+        double vh = wave_max(hi[a]);
+        if (l == 0) { red[a][w] = vl; red[3 + a][w] = vh; }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ext = 0.0;
+        double L[3], E[3];
+        for (int a = 0; a < 3; ++a) {
+            double vl = red[a][0], vh = red[3 + a][0];
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+                vl = fmin(vl, red[a][k]);
+                vh = fmax(vh, red[3 + a][k]);
+            }
+            if (!(vl <= vh)) { vl = 0.0; vh = 0.0; }
+            L[a] = vl;
+            E[a] = vh - vl;
+            if (E[a] > ext) ext = E[a];
+        }
+        if (!(ext > 0.0)) ext = 1.0;
+        double *f = frame + 8 * (int64_t)g;
+        f[0] = L[0]; f[1] = L[1]; f[2] = L[2];
+        f[3] = E[0]; f[4] = E[1]; f[5] = E[2];
+        f[6] = 65536.0 / ext;
+        f[7] = ext;
+    }
+}
+
+// Group of particle i: the largest g with goff[g] <= i.
+__device__ inline int32_t group_of(const int64_t *goff, int32_t G, int64_t i) {
+    int32_t lo = 0, hi = G - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (goff[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename T>
+__global__ void k_keys_groups(int64_t n, int32_t G, const int64_t *goff, const void *x,
+                              const void *y, const void *z, const double *frame,
+                              uint64_t *keys, int32_t *vals) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t g = group_of(goff, G, i);
+    const double *f = frame + 8 * (int64_t)g;
+    const double sc = f[6];
+    const uint32_t qx = quantise((ld<T>(x, i) - f[0]) * sc, 1u << 16);
+    const uint32_t qy = quantise((ld<T>(y, i) - f[1]) * sc, 1u << 16);
+    const uint32_t qz = quantise((ld<T>(z, i) - f[2]) * sc, 1u << 16);
+    keys[i] = ((uint64_t)(uint32_t)g << 48) | morton3(qx, qy, qz);
+    vals[i] = (int32_t)i;
+}
+
+// ------------------------------------------------------------- radix sort
+
+template <int ROUNDS>
+__global__ __launch_bounds__(kSortThreads) void k_radix_up(int64_t n, const uint64_t *keys,
+                                                          int shift, uint32_t *hist,
+                                                          int64_t nb) {
+    __shared__ uint32_t h[4][256];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    for (int k = tid; k < 4 * 256; k += kSortThreads) (&h[0][0])[k] = 0u;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * (256 * ROUNDS) + (int64_t)w * 64 * ROUNDS;
+#pragma unroll 4
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = base + r * 64 + l;
+        if (idx < n) {
+            const uint32_t d = (uint32_t)(keys[idx] >> shift) & 255u;
+            atomicAdd(&h[w][d], 1u);
+        }
+    }
+    __syncthreads();
+    hist[(int64_t)tid * nb + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
+}
+
+// Exclusive scan of 256 per-thread values across a 256-thread block.
+__device__ inline uint32_t block_excl_scan_256(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t wt[4];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(inc, o, 64);
+        if (l >= o) inc += t;
+    }
+    if (l == 63) wt[w] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < w; ++k) off += wt[k];
+    if (total) *total = wt[0] + wt[1] + wt[2] + wt[3];
+    __syncthreads();
+    return off + inc - v;
+}
+
+// One block per digit: exclusive scan of that digit's per-tile counts.
+__global__ __launch_bounds__(kSortThreads) void k_radix_scan(uint32_t *hist, int64_t nb,
+                                                            uint32_t *digit_tot) {
+    uint32_t *row = hist + (int64_t)blockIdx.x * nb;
+    const int tid = threadIdx.x;
+    const int64_t per = (nb + kSortThreads - 1) / kSortThreads;
+    const int64_t b = tid * per;
+    const int64_t e = b + per < nb ? b + per : nb;
+    uint32_t s = 0;
+    for (int64_t k = b; k < e; ++k) s += row[k];
+    uint32_t tot;
+    uint32_t run = block_excl_scan_256(s, &tot);
+    for (int64_t k = b; k < e; ++k) {
+        const uint32_t v = row[k];
+        row[k] = run;
+        run += v;
+    }
+    if (tid == 0) digit_tot[blockIdx.x] = tot;
+}
+
+template <int ROUNDS>
+__global__ __launch_bounds__(kSortThreads) void k_radix_down(int64_t n, const uint64_t *kin,
+                                                            const int32_t *vin, uint64_t *kout,
+                                                            int32_t *vout, int shift,
+                                                            const uint32_t *hist,
+                                                            const uint32_t *digit_tot,
+                                                            int64_t nb) {
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t dbase[256];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    for (int k = tid; k < 4 * 256; k += kSortThreads) (&wcnt[0][0])[k] = 0u;
+    {
+        const uint32_t tot = digit_tot[tid];
+        const uint32_t pre = block_excl_scan_256(tot, nullptr);
+        dbase[tid] = pre + hist[(int64_t)tid * nb + blockIdx.x];
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * (256 * ROUNDS) + (int64_t)w * 64 * ROUNDS;
+    uint64_t key[ROUNDS];
+    int32_t val[ROUNDS];
+    uint32_t rank[ROUNDS];
+    volatile uint32_t *wc = wcnt[w];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = base + r * 64 + l;
+        const bool valid = idx < n;
+        key[r] = valid ? kin[idx] : ~0ull;
+        val[r] = valid ? vin[idx] : 0;
+        const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
+        const uint32_t before = mbcnt(m);
+        const uint32_t cnt0 = wc[d];
+        rank[r] = cnt0 + before;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before == 0) wc[d] = cnt0 + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+        uint32_t s = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t t = wcnt[k][tid];
+            wcnt[k][tid] = s;
+            s += t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = base + r * 64 + l;
+        if (idx < n) {
+            const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+            const uint32_t pos = dbase[d] + wcnt[w][d] + rank[r];
+            kout[pos] = key[r];
+            vout[pos] = val[r];
+        }
+    }
+}
+
+template <int ROUNDS>
+static hipError_t radix_sort_impl(Plan &pl, int passes, hipStream_t st) {
+    const int64_t n = pl.n;
+    const int64_t nb = pl.nb_sort;
+    uint64_t *ka = pl.keysA, *kb = pl.keysB;
+    int32_t *va = pl.valsA, *vb = pl.valsB;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        hipLaunchKernelGGL(k_radix_up<ROUNDS>, dim3((unsigned)nb), dim3(kSortThreads), 0, st, n,
+                           ka, shift, pl.hist, nb);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kSortThreads), 0, st, pl.hist, nb,
+                           pl.digit_tot);
+        hipLaunchKernelGGL(k_radix_down<ROUNDS>, dim3((unsigned)nb), dim3(kSortThreads), 0, st,
+                           n, ka, va, kb, vb, shift, pl.hist, pl.digit_tot, nb);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        int32_t *tv = va; va = vb; vb = tv;
+    }
+    pl.skeys = ka;
+    pl.perm = va;
+    return hipGetLastError();
+}
+
+static hipError_t radix_sort(Plan &pl, int passes, hipStream_t st) {
+    if (pl.sort_rounds == 16) return radix_sort_impl<16>(pl, passes, st);
+    return radix_sort_impl<4>(pl, passes, st);
+}
+
+hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const void *y,
+                             const void *z, hipStream_t st) {
+    const int64_t n = pl.n;
+    const unsigned nbk = (unsigned)ceil_div(n, 256);
+    const bool f32 = pl.prm.io_dtype == SPH_F32;
+    if (!pl.grouped) {
+        if (f32)
+            hipLaunchKernelGGL(k_keys_periodic<float>, dim3(nbk), dim3(256), 0, st, n, x, y, z,
+                               pl.prm.box, pl.keysA, pl.valsA);
+        else
+            hipLaunchKernelGGL(k_keys_periodic<double>, dim3(nbk), dim3(256), 0, st, n, x, y, z,
+                               pl.prm.box, pl.keysA, pl.valsA);
+    } else {
+        if (f32) {
+            hipLaunchKernelGGL(k_group_frames<float>, dim3(pl.G), dim3(256), 0, st, pl.G, goff,
+                               x, y, z, pl.frame);
+            hipLaunchKernelGGL(k_keys_groups<float>, dim3(nbk), dim3(256), 0, st, n, pl.G, goff,
+                               x, y, z, pl.frame, pl.keysA, pl.valsA);
+        } else {
+            hipLaunchKernelGGL(k_group_frames<double>, dim3(pl.G), dim3(256), 0, st, pl.G, goff,
+                               x, y, z, pl.frame);
+            hipLaunchKernelGGL(k_keys_groups<double>, dim3(nbk), dim3(256), 0, st, n, pl.G,
+                               goff, x, y, z, pl.frame, pl.keysA, pl.valsA);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return radix_sort(pl, 8, st);
+}
+
+// ------------------------------------------------------- sorted SoA gather
+
+// Default initial smoothing length 2 (V / n)^(1/3).
+__device__ inline double default_h(bool grouped, double box, int64_t n, const double *frame,
+                                   const int64_t *goff, uint64_t key) {
+    if (!grouped) return 2.0 * cbrt(box * box * box / (double)n);
+    const uint32_t g = (uint32_t)(key >> 48);
+    const double E = frame[8 * (int64_t)g + 7];
+    const double ng = (double)(goff[g + 1] - goff[g]);
+    return 2.0 * cbrt(E * E * E / ng);
+}
+
+__device__ inline bool valid_input(bool periodic, double box, double x, double y, double z,
+                                   double m, double h) {
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z) || !isfinite(m) || !isfinite(h)) return false;
+    if (!(h > 0.0)) return false;
+    if (periodic) {
+        if (!(x >= 0.0 && x < box) || !(y >= 0.0 && y < box) || !(z >= 0.0 && z < box))
+            return false;
+    }
+    return true;
+}
+
+template <typename T>
+__global__ void k_permute64(int64_t n, const int32_t *perm, const uint64_t *skeys,
+                            const void *x, const void *y, const void *z, const void *m,
+                            const void *h0, bool grouped, double box, const double *frame,
+                            const int64_t *goff, double *sx, double *sy, double *sz, double *sm,
+                            double *sh0) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+    double xv = ld<T>(x, i), yv = ld<T>(y, i), zv = ld<T>(z, i), mv = ld<T>(m, i);
+    const double hv = h0 ? ld<T>(h0, i) : default_h(grouped, box, n, frame, goff, skeys[s]);
+    if (!valid_input(!grouped, box, xv, yv, zv, mv, hv)) {
+        xv = NAN; yv = NAN; zv = NAN;
+    }
+    sx[s] = xv; sy[s] = yv; sz[s] = zv; sm[s] = mv; sh0[s] = hv;
+}
+
+// Positions as integer Morton-grid coordinates q (units of the grid spacing:
+// box / 2^21, or the group cube / 2^16) plus a binary32 fraction in [0, 1].
+template <typename T>
+__global__ void k_permute32(int64_t n, const int32_t *perm, const uint64_t *skeys,
+                            const void *x, const void *y, const void *z, const void *m,
+                            const void *h0, bool grouped, double box, const double *frame,
+                            const int64_t *goff, int32_t *qx, int32_t *qy, int32_t *qz,
+                            float *fx, float *fy, float *fz, float *fm, double *sh0) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+    const double xv = ld<T>(x, i), yv = ld<T>(y, i), zv = ld<T>(z, i), mv = ld<T>(m, i);
+    const double hv = h0 ? ld<T>(h0, i) : default_h(grouped, box, n, frame, goff, skeys[s]);
+    double tx, ty, tz;
+    uint32_t nmax;
+    if (!grouped) {
+        const double sc = 2097152.0 / box;
+        tx = xv * sc; ty = yv * sc; tz = zv * sc;
+        nmax = 1u << 21;
+    } else {
+        const double *f = frame + 8 * (int64_t)(uint32_t)(skeys[s] >> 48);
+        tx = (xv - f[0]) * f[6]; ty = (yv - f[1]) * f[6]; tz = (zv - f[2]) * f[6];
+        nmax = 1u << 16;
+    }
+    const uint32_t ux = quantise(tx, nmax), uy = quantise(ty, nmax), uz = quantise(tz, nmax);
+    float ax = (float)(tx - (double)ux), ay = (float)(ty - (double)uy), az = (float)(tz - (double)uz);
+    if (!valid_input(!grouped, box, xv, yv, zv, mv, hv)) { ax = NAN; ay = NAN; az = NAN; }
+    qx[s] = (int32_t)ux; qy[s] = (int32_t)uy; qz[s] = (int32_t)uz;
+    fx[s] = ax; fy[s] = ay; fz[s] = az;
+    fm[s] = (float)mv;
+    sh0[s] = hv;
+}
+
+hipError_t run_permute(Plan &pl, const int64_t *goff, const void *x, const void *y,
+                       const void *z, const void *m, const void *h0, bool fp32c,
+                       hipStream_t st) {
+    const int64_t n = pl.n;
+    const unsigned nbk = (unsigned)ceil_div(n, 256);
+    const bool f32 = pl.prm.io_dtype == SPH_F32;
+    if (!fp32c) {
+        if (f32)
+            hipLaunchKernelGGL(k_permute64<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
+                               pl.skeys, x, y, z, m, h0, pl.grouped, pl.prm.box, pl.frame, goff,
+                               pl.sx, pl.sy, pl.sz, pl.sm, pl.sh0);
+        else
+            hipLaunchKernelGGL(k_permute64<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
+                               pl.skeys, x, y, z, m, h0, pl.grouped, pl.prm.box, pl.frame, goff,
+                               pl.sx, pl.sy, pl.sz, pl.sm, pl.sh0);
+    } else {
+        if (f32)
+            hipLaunchKernelGGL(k_permute32<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
+                               pl.skeys, x, y, z, m, h0, pl.grouped, pl.prm.box, pl.frame, goff,
+                               pl.qx, pl.qy, pl.qz, pl.fx, pl.fy, pl.fz, pl.fm, pl.sh0);
+        else
+            hipLaunchKernelGGL(k_permute32<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
+                               pl.skeys, x, y, z, m, h0, pl.grouped, pl.prm.box, pl.frame, goff,
+                               pl.qx, pl.qy, pl.qz, pl.fx, pl.fy, pl.fz, pl.fm, pl.sh0);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scans
+//
+// Device-wide scans of int32 arrays in three launches: per-tile reductions,
+// a scan of the tile totals in one block, then per-tile scans plus carry.
+// OP 0 = sum, 1 = min.  REV scans from the end of the array backwards.
+
+template <int OP>
+__device__ inline int32_t sop(int32_t a, int32_t b) {
+    if (OP == 0) return a + b;
+    return a < b ? a : b;
+}
+
+template <int OP>
+__device__ inline int32_t sid() {
+    return OP == 0 ? 0 : INT_MAX;
+}
+
+// Exclusive block scan of one value per thread (blockDim.x = kScanThreads or 1024).
+template <int OP, int NT>
+__device__ inline int32_t block_excl(int32_t v, int32_t *total) {
+    __shared__ int32_t wt[NT / 64];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    int32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t t = __shfl_up(inc, o, 64);
+        if (l >= o) inc = sop<OP>(inc, t);
+    }
+    if (l == 63) wt[w] = inc;
+    __syncthreads();
+    int32_t off = sid<OP>();
+    for (int k = 0; k < w; ++k) off = sop<OP>(off, wt[k]);
+    if (total) {
+        int32_t t = sid<OP>();
+        for (int k = 0; k < NT / 64; ++k) t = sop<OP>(t, wt[k]);
+        *total = t;
+    }
+    __syncthreads();
+    int32_t ex = __shfl_up(inc, 1, 64);
+    if (l == 0) ex = sid<OP>();
+    return sop<OP>(off, ex);
+}
+
+template <int OP, bool REV>
+__device__ inline int64_t phys(int64_t li, int64_t cnt) {
+    return REV ? cnt - 1 - li : li;
+}
+
+template <int OP, bool REV>
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t *in, int64_t cnt,
+                                                             int32_t *bsum) {
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t acc = sid<OP>();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t li = b0 + k;
+        if (li < cnt) acc = sop<OP>(acc, in[phys<OP, REV>(li, cnt)]);
+    }
+    int32_t tot;
+    block_excl<OP, kScanThreads>(acc, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+template <int OP>
+__global__ __launch_bounds__(1024) void k_scan_bsum(int32_t *bsum, int64_t nb) {
+    __shared__ int32_t carry_s;
+    int32_t carry = sid<OP>();
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024 * 8) {
+        const int64_t b0 = c0 + (int64_t)threadIdx.x * 8;
+        int32_t v[8];
+        int32_t acc = sid<OP>();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            v[k] = b0 + k < nb ? bsum[b0 + k] : sid<OP>();
+            acc = sop<OP>(acc, v[k]);
+        }
+        int32_t tot;
+        int32_t ex = block_excl<OP, 1024>(acc, &tot);
+        ex = sop<OP>(carry, ex);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (b0 + k < nb) bsum[b0 + k] = ex;
+            ex = sop<OP>(ex, v[k]);
+        }
+        if (threadIdx.x == 0) carry_s = sop<OP>(carry, tot);
+        __syncthreads();
+        carry = carry_s;
+        __syncthreads();
+    }
+}
+
+template <int OP, bool REV, bool INCL>
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t *in, int32_t *out,
+                                                            int64_t cnt, const int32_t *bsum) {
+    const int64_t b0 = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int32_t acc = sid<OP>();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t li = b0 + k;
+        v[k] = li < cnt ? in[phys<OP, REV>(li, cnt)] : sid<OP>();
+        acc = sop<OP>(acc, v[k]);
+    }
+    int32_t ex = block_excl<OP, kScanThreads>(acc, nullptr);
+    ex = sop<OP>(bsum[blockIdx.x], ex);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t li = b0 + k;
+        const int32_t nx = sop<OP>(ex, v[k]);
+        if (li < cnt) out[phys<OP, REV>(li, cnt)] = INCL ? nx : ex;
+        ex = nx;
+    }
+}
+
+template <int OP, bool REV, bool INCL>
+static hipError_t scan(const int32_t *in, int32_t *out, int64_t cnt, int32_t *bsum,
+                       hipStream_t st) {
+    if (cnt <= 0) return hipSuccess;
+    const int64_t nb = ceil_div(cnt, kScanTile);
+    hipLaunchKernelGGL((k_scan_reduce<OP, REV>), dim3((unsigned)nb), dim3(kScanThreads), 0, st,
+                       in, cnt, bsum);
+    hipLaunchKernelGGL(k_scan_bsum<OP>, dim3(1), dim3(1024), 0, st, bsum, nb);
+    hipLaunchKernelGGL((k_scan_apply<OP, REV, INCL>), dim3((unsigned)nb), dim3(kScanThreads), 0,
+                       st, in, out, cnt, bsum);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- cell tables
+
+__global__ void k_cell_flags(int64_t n, const uint64_t *skeys, int shift, int32_t *flags) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    flags[s] = (s == 0 || (skeys[s] >> shift) != (skeys[s - 1] >> shift)) ? 1 : 0;
+}
+
+// idx = inclusive scan of the cell-start flags, so the cell of slot s is
+// idx[s] - 1.  Records each cell's id and first slot; tmp gets the first slots.
+__global__ void k_cell_compact(int64_t n, const uint64_t *skeys, int shift, const int32_t *idx,
+                               uint64_t *cell_id, int32_t *cell_start, int32_t *tmp,
+                               int32_t *n_cells) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const uint64_t c = skeys[s] >> shift;
+    const bool first = s == 0 || c != (skeys[s - 1] >> shift);
+    const int32_t ci = idx[s] - 1;
+    if (first) {
+        tmp[ci] = (int32_t)s;
+        if (cell_id) cell_id[ci] = c;
+        if (cell_start) cell_start[ci] = (int32_t)s;
+    }
+    if (s == n - 1 && n_cells) *n_cells = idx[s];
+}
+
+__global__ void k_cell_counts(int64_t n, const int32_t *idx, const int32_t *tmp,
+                              int32_t *cell_count) {
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int32_t nc = idx[n - 1];
+    if (c >= nc) return;
+    const int32_t e = c + 1 < nc ? tmp[c + 1] : (int32_t)n;
+    cell_count[c] = e - tmp[c];
+}
+
+hipError_t run_contract_cells(Plan &pl, uint64_t *cell_id, int32_t *cell_start,
+                              int32_t *cell_count, int32_t *n_cells, hipStream_t st) {
+    const int64_t n = pl.n;
+    const int shift = 3 * (pl.bits - pl.Lc);
+    const unsigned nbk = (unsigned)ceil_div(n, 256);
+    // the radix sort's second value buffer is free once the sort is done
+    int32_t *tmp = pl.perm == pl.valsA ? pl.valsB : pl.valsA;
+    hipLaunchKernelGGL(k_cell_flags, dim3(nbk), dim3(256), 0, st, n, pl.skeys, shift, pl.scan_a);
+    hipError_t e = scan<0, false, true>(pl.scan_a, pl.scan_a, n, pl.bsum, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_compact, dim3(nbk), dim3(256), 0, st, n, pl.skeys, shift, pl.scan_a,
+                       cell_id, cell_start, tmp, n_cells);
+    if (cell_count)
+        hipLaunchKernelGGL(k_cell_counts, dim3(nbk), dim3(256), 0, st, n, pl.scan_a, tmp,
+                           cell_count);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t cnt) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, int64_t cnt) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < cnt) p[i] = v;
+}
+
+__global__ void k_table_bounds(int64_t n, const uint64_t *skeys, int shift, int32_t *table) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const uint64_t c = skeys[s] >> shift;
+    if (s == 0 || c != (skeys[s - 1] >> shift)) table[c] = (int32_t)s;
+}
+
+// table[c] = first sorted slot whose level-Ld cell is >= c (c = 0 .. 8^Ld).
+hipError_t run_dense_table(Plan &pl, hipStream_t st) {
+    const int64_t tn = pl.table_n;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(tn, 256)), dim3(256), 0, st, pl.table,
+                       (int32_t)pl.n, tn);
+    const int shift = 3 * (pl.bits - pl.Ld);
+    hipLaunchKernelGGL(k_table_bounds, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st, pl.n,
+                       pl.skeys, shift, pl.table);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return scan<1, true, true>(pl.table, pl.table, tn, pl.bsum, st);
+}
+
+// Work items of the batched form: group g owns items [gitems[g], gitems[g+1]),
+// one per `segment` particles; gitems[G] = total.
+__global__ void k_group_ntiles(int32_t G, const int64_t *goff, int32_t seg, int32_t *cnt) {
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g > G) return;
+    if (g == G) { cnt[g] = 0; return; }
+    const int64_t ng = goff[g + 1] - goff[g];
+    cnt[g] = (int32_t)((ng + seg - 1) / seg);
+}
+
+hipError_t run_group_items(Plan &pl, const int64_t *goff, hipStream_t st) {
+    const int64_t cnt = (int64_t)pl.G + 1;
+    hipLaunchKernelGGL(k_group_ntiles, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st,
+                       pl.G, goff, pl.prm.segment, pl.gitems);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return scan<0, false, false>(pl.gitems, pl.gitems, cnt, pl.bsum, st);
+}
+
+__global__ void k_copy_sorted(int64_t n, const uint64_t *k, const int32_t *p, uint64_t *ko,
+                              int32_t *po) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    ko[s] = k[s];
+    po[s] = p[s];
+}
+
+hipError_t run_copy_sorted(Plan &pl, uint64_t *keys_out, int32_t *perm_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy_sorted, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st, pl.n,
+                       pl.skeys, pl.perm, keys_out, perm_out);
+    return hipGetLastError();
+}
+
+hipError_t run_zero_u64(uint64_t *p, int64_t cnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, p, 0ull,
+                       cnt);
+    return hipGetLastError();
+}
+
+hipError_t run_zero_i32(int32_t *p, int64_t cnt, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st, p, 0, cnt);
+    return hipGetLastError();
+}
+
+}  // namespace sph

@@ -1,0 +1,281 @@
+// C ABI of libsph: argument validation, workspace planning and the launch
+// sequence of each entry point.  Declarations and semantics: include/sph.h.
+#include "sph_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+namespace sph {
+
+static thread_local int g_last_hip = 0;
+
+static int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return SPH_E_HIP;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static int ceil_log2_i64(int64_t n) {
+    int lg = 0;
+    while (lg < 62 && ((int64_t)1 << lg) < n) ++lg;
+    return lg;
+}
+
+int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
+    Plan &pl = *out;
+    pl = Plan();
+    pl.prm = *p;
+    pl.n = n;
+    pl.G = G;
+    pl.grouped = G > 0;
+    pl.bits = pl.grouped ? 16 : 21;
+    const int lg = ceil_log2_i64(n > 0 ? n : 1);
+    if (p->cell_level >= 0) {
+        pl.Lc = p->cell_level;
+    } else {
+        const int t = lg - 3;
+        pl.Lc = t <= 0 ? 1 : (t + 2) / 3;
+        if (pl.Lc < 1) pl.Lc = 1;
+        if (pl.Lc > pl.bits) pl.Lc = pl.bits;
+    }
+    if (!pl.grouped) {
+        int Ld = (lg + 2) / 3;
+        if (Ld < 1) Ld = 1;
+        if (Ld > 8) Ld = 8;
+        pl.Ld = Ld;
+        pl.table_n = ((int64_t)1 << (3 * Ld)) + 1;
+    }
+    pl.sort_rounds = n <= ((int64_t)1 << 21) ? 4 : 16;
+    pl.sort_tile = (int64_t)256 * pl.sort_rounds;
+    pl.nb_sort = ceil_div(n > 0 ? n : 1, pl.sort_tile);
+    pl.nb_scan_n = ceil_div(n > 0 ? n : 1, kScanTile);
+    pl.nb_scan_t = ceil_div(pl.table_n > 0 ? pl.table_n : 1, kScanTile);
+    const int64_t seg = p->segment;
+    pl.n_items = ceil_div(n > 0 ? n : 1, seg);
+    const int64_t full = (int64_t)256 * p->waves_per_cu;
+    pl.grid = (int)(pl.grouped ? full : (pl.n_items < full ? pl.n_items : full));
+    if (pl.grid < 1) pl.grid = 1;
+
+    const bool f32c = p->precision == SPH_FP32C;
+    const size_t N = (size_t)(n > 0 ? n : 1);
+    size_t off = 0;
+    char *base = static_cast<char *>(ws);
+    auto take = [&](size_t bytes) -> void * {
+        void *r = base ? base + off : nullptr;
+        off = align256(off + bytes);
+        return r;
+    };
+    pl.keysA = (uint64_t *)take(8 * N);
+    pl.keysB = (uint64_t *)take(8 * N);
+    pl.valsA = (int32_t *)take(4 * N);
+    pl.valsB = (int32_t *)take(4 * N);
+    pl.hist = (uint32_t *)take(4 * 256 * (size_t)pl.nb_sort);
+    pl.digit_tot = (uint32_t *)take(4 * 256);
+    if (!f32c) {
+        pl.sx = (double *)take(8 * N);
+        pl.sy = (double *)take(8 * N);
+        pl.sz = (double *)take(8 * N);
+        pl.sm = (double *)take(8 * N);
+    } else {
+        pl.qx = (int32_t *)take(4 * N);
+        pl.qy = (int32_t *)take(4 * N);
+        pl.qz = (int32_t *)take(4 * N);
+        pl.fx = (float *)take(4 * N);
+        pl.fy = (float *)take(4 * N);
+        pl.fz = (float *)take(4 * N);
+        pl.fm = (float *)take(4 * N);
+    }
+    pl.sh0 = (double *)take(8 * N);
+    if (pl.table_n > 0) pl.table = (int32_t *)take(4 * (size_t)pl.table_n);
+    pl.scan_a = (int32_t *)take(4 * N);
+    int64_t nbs = pl.nb_scan_n;
+    if (pl.nb_scan_t > nbs) nbs = pl.nb_scan_t;
+    const int64_t nbg = ceil_div((int64_t)G + 1, kScanTile);
+    if (nbg > nbs) nbs = nbg;
+    pl.bsum = (int32_t *)take(4 * (size_t)(nbs + 1));
+    if (pl.grouped) {
+        pl.frame = (double *)take(8 * 8 * (size_t)G);
+        pl.gitems = (int32_t *)take(4 * ((size_t)G + 1));
+        pl.gorder = (int32_t *)take(4 * (size_t)G);
+    }
+    pl.ctrl = (int32_t *)take(64);
+    pl.stats = (uint64_t *)take(64);
+    pl.lam = (double *)take(8 * N);
+    pl.acc = (double *)take(16 * N);
+    pl.total = off;
+    return SPH_OK;
+}
+
+static int check_params(const sph_params *p, int64_t n, int32_t G, const int64_t *goff) {
+    if (!p) return SPH_E_INVALID;
+    if (p->abi_version != SPH_ABI_VERSION) return SPH_E_INVALID;
+    if (p->precision != SPH_FP64 && p->precision != SPH_FP32C) return SPH_E_INVALID;
+    if (p->io_dtype != SPH_F64 && p->io_dtype != SPH_F32) return SPH_E_INVALID;
+    if (p->mode != SPH_BAND && p->mode != SPH_ROOT) return SPH_E_INVALID;
+    if (p->periodic != 0 && p->periodic != 1) return SPH_E_INVALID;
+    if (n < 0 || n >= ((int64_t)1 << 31) - 1) return SPH_E_INVALID;
+    if (p->periodic) {
+        if (G != 0 || goff) return SPH_E_INVALID;
+        if (!(p->box > 0.0) || !isfinite(p->box)) return SPH_E_INVALID;
+    } else {
+        if (G < 1 || G >= 65536 || !goff) return SPH_E_INVALID;
+    }
+    if (!(p->n_target > 0.0) || !isfinite(p->n_target)) return SPH_E_INVALID;
+    if (!(p->n_tol >= 0.0) || !isfinite(p->n_tol)) return SPH_E_INVALID;
+    if (p->mode == SPH_ROOT && (!(p->root_tol > 0.0) || !isfinite(p->root_tol)))
+        return SPH_E_INVALID;
+    if (p->max_iter < 0 || p->max_iter > 65535) return SPH_E_INVALID;
+    const int bits = p->periodic ? 21 : 16;
+    if (p->cell_level < -1 || p->cell_level > bits || p->cell_level == 0) return SPH_E_INVALID;
+    if (p->tile_cell != 0 && p->tile_cell != -1) return SPH_E_INVALID;
+    if (p->waves_per_cu < 1 || p->waves_per_cu > 32) return SPH_E_INVALID;
+    if (p->segment != 64) return SPH_E_UNSUPPORTED;
+    for (int k = 0; k < 8; ++k)
+        if (p->reserved[k] != 0) return SPH_E_INVALID;
+    return SPH_OK;
+}
+
+static int check_ws(const sph_params *p, int64_t n, int32_t G, void *ws, size_t bytes, Plan *pl) {
+    if (!ws) return SPH_E_INVALID;
+    if (((uintptr_t)ws & 255u) != 0) return SPH_E_INVALID;
+    Plan probe;
+    make_plan(p, n, G, nullptr, &probe);
+    if (bytes < probe.total) return SPH_E_WORKSPACE;
+    return make_plan(p, n, G, ws, pl);
+}
+
+__global__ void k_store_i32(int32_t *p, int32_t v) { *p = v; }
+
+}  // namespace sph
+
+using namespace sph;
+
+extern "C" {
+
+void sph_default_params(sph_params *p) {
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->abi_version = SPH_ABI_VERSION;
+    p->precision = SPH_FP64;
+    p->io_dtype = SPH_F64;
+    p->mode = SPH_BAND;
+    p->periodic = 1;
+    p->max_iter = 64;
+    p->box = 1.0;
+    p->n_target = 64.0;
+    p->n_tol = 2.0;
+    p->root_tol = 1e-12;
+    p->cell_level = -1;
+    p->tile_cell = 0;
+    p->waves_per_cu = 8;
+    p->segment = 64;
+}
+
+int sph_workspace_size(const sph_params *params, int64_t n, int32_t n_groups, size_t *bytes) {
+    if (!bytes || !params) return SPH_E_INVALID;
+    // group offsets are only inspected for presence; the size needs none
+    const int64_t dummy = 0;
+    const int rc = check_params(params, n, n_groups, params->periodic ? nullptr : &dummy);
+    if (rc != SPH_OK) return rc;
+    Plan pl;
+    make_plan(params, n, n_groups, nullptr, &pl);
+    *bytes = pl.total;
+    return SPH_OK;
+}
+
+int sph_sort(const sph_params *params, int64_t n, int32_t n_groups, const int64_t *group_offsets,
+             const void *x, const void *y, const void *z, uint64_t *keys_out, int32_t *perm_out,
+             uint64_t *cell_id_out, int32_t *cell_start_out, int32_t *cell_count_out,
+             int32_t *n_cells_out, void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_params(params, n, n_groups, group_offsets);
+    if (rc != SPH_OK) return rc;
+    if (!x || !y || !z || !keys_out || !perm_out) return SPH_E_INVALID;
+    Plan pl;
+    rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
+    if (rc != SPH_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        if (n_cells_out) {
+            hipLaunchKernelGGL(k_store_i32, dim3(1), dim3(1), 0, st, n_cells_out, 0);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        return SPH_OK;
+    }
+    hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
+    if (e == hipSuccess) e = run_copy_sorted(pl, keys_out, perm_out, st);
+    if (e == hipSuccess && (cell_id_out || cell_start_out || cell_count_out || n_cells_out))
+        e = run_contract_cells(pl, cell_id_out, cell_start_out, cell_count_out, n_cells_out, st);
+    if (e != hipSuccess) return hip_fail(e);
+    return SPH_OK;
+}
+
+int sph_density_solve(const sph_params *params, int64_t n, int32_t n_groups,
+                      const int64_t *group_offsets, const void *x, const void *y, const void *z,
+                      const void *m, const void *h_init, void *rho_out, void *h_out, void *nw_out,
+                      int32_t *nngb_out, int32_t *status_out, uint64_t *stats_out, void *ws,
+                      size_t ws_bytes, void *stream) {
+    int rc = check_params(params, n, n_groups, group_offsets);
+    if (rc != SPH_OK) return rc;
+    if (!x || !y || !z || !m || !rho_out || !h_out) return SPH_E_INVALID;
+    Plan pl;
+    rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
+    if (rc != SPH_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (n == 0) {
+        if (stats_out) {
+            hipError_t e = run_zero_u64(stats_out, 4, st);
+            if (e != hipSuccess) return hip_fail(e);
+        }
+        return SPH_OK;
+    }
+    const bool f32c = params->precision == SPH_FP32C;
+    hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
+    if (e == hipSuccess) e = run_permute(pl, group_offsets, x, y, z, m, h_init, f32c, st);
+    if (e == hipSuccess) {
+        if (!pl.grouped) e = run_dense_table(pl, st);
+        else e = run_group_items(pl, group_offsets, st);
+    }
+    if (e == hipSuccess)
+        e = run_solve(pl, group_offsets, rho_out, h_out, nw_out, nngb_out, status_out, stats_out,
+                      st);
+    if (e != hipSuccess) return hip_fail(e);
+    return SPH_OK;
+}
+
+int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
+                         const int64_t *group_offsets, const void *x, const void *y,
+                         const void *z, const void *m, const void *h, const void *grad_rho,
+                         const void *grad_h, void *grad_x, void *grad_y, void *grad_z,
+                         void *grad_m, void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_params(params, n, n_groups, group_offsets);
+    if (rc != SPH_OK) return rc;
+    if (!x || !y || !z || !m || !h || !grad_rho || !grad_x || !grad_y || !grad_z || !grad_m)
+        return SPH_E_INVALID;
+    Plan pl;
+    rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
+    if (rc != SPH_OK) return rc;
+    (void)grad_h;
+    (void)stream;
+    return SPH_E_UNSUPPORTED;
+}
+
+const char *sph_status_string(int code) {
+    switch (code) {
+        case SPH_OK: return "SPH_OK: success";
+        case SPH_E_INVALID: return "SPH_E_INVALID: invalid argument";
+        case SPH_E_WORKSPACE: return "SPH_E_WORKSPACE: workspace too small";
+        case SPH_E_HIP: return "SPH_E_HIP: a HIP call failed (see sph_last_hip_error)";
+        case SPH_E_UNSUPPORTED: return "SPH_E_UNSUPPORTED: unsupported parameter combination";
+        default: return "unknown status code";
+    }
+}
+
+int sph_last_hip_error(void) { return g_last_hip; }
+
+const char *sph_last_hip_error_string(void) {
+    return hipGetErrorString((hipError_t)g_last_hip);
+}
+
+}  // extern "C"

@@ -1,0 +1,186 @@
+// Internal declarations of libsph (HIP, gfx950).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sph.h"
+
+namespace sph {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kWave = 64;
+
+// Radix sort geometry: one 256-thread block = 4 waves; a wave ranks ROUNDS
+// rounds of 64 consecutive keys, so a block tile holds 4*64*ROUNDS keys.
+constexpr int kSortThreads = 256;
+
+// Scan geometry: 256 threads x 8 items per block.
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// Everything the host computes once per call: sizes, levels and the carved-up
+// workspace.  Pointers are device addresses inside the caller's workspace.
+struct Plan {
+    sph_params prm;
+    int64_t n = 0;
+    int32_t G = 0;            // groups (0: one periodic set)
+    bool grouped = false;
+    int bits = 21;            // bits per axis of the Morton key
+    int Lc = 1;               // cell level of the sort's cell table
+    int Ld = 0;               // level of the dense start table (periodic only)
+    int64_t table_n = 0;      // 8^Ld + 1 entries
+    int sort_rounds = 4;      // radix rounds per wave
+    int64_t sort_tile = 0;    // keys per radix block
+    int64_t nb_sort = 0;      // radix blocks
+    int64_t nb_scan_n = 0;    // scan blocks over n
+    int64_t nb_scan_t = 0;    // scan blocks over table_n
+    int64_t n_items = 0;      // work items of the density kernel (periodic)
+    int grid = 0;             // persistent grid size
+
+    uint64_t *keysA = nullptr, *keysB = nullptr;
+    int32_t *valsA = nullptr, *valsB = nullptr;
+    uint32_t *hist = nullptr, *digit_tot = nullptr;
+    // sorted structure-of-arrays
+    double *sx = nullptr, *sy = nullptr, *sz = nullptr, *sm = nullptr, *sh0 = nullptr;
+    int32_t *qx = nullptr, *qy = nullptr, *qz = nullptr;
+    float *fx = nullptr, *fy = nullptr, *fz = nullptr, *fm = nullptr;
+    int32_t *table = nullptr;
+    int32_t *scan_a = nullptr;   // n-sized int32 scratch (cell flags / scan)
+    int32_t *bsum = nullptr;     // block sums of scans
+    double *frame = nullptr;     // per group: lo xyz, ext xyz, scale, pad (8 doubles)
+    int32_t *gitems = nullptr;   // per group: first work item (G+1)
+    int32_t *gorder = nullptr;   // groups in processing order (G)
+    int32_t *ctrl = nullptr;     // [0] work queue head, [1..] reserved
+    uint64_t *stats = nullptr;   // 4 x uint64 device counters
+    double *lam = nullptr;       // adjoint multipliers (n)
+    double *acc = nullptr;       // adjoint per-particle extras (n x 2)
+    // after sorting
+    uint64_t *skeys = nullptr;
+    int32_t *perm = nullptr;
+    size_t total = 0;
+};
+
+// Fills plan sizes and, when ws != nullptr, the pointers.  Returns SPH_OK or
+// an error code (does not touch the device).
+int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out);
+
+// sort.hip
+hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const void *y,
+                             const void *z, hipStream_t st);
+hipError_t run_permute(Plan &pl, const int64_t *goff, const void *x, const void *y,
+                       const void *z, const void *m, const void *h0, bool fp32c,
+                       hipStream_t st);
+hipError_t run_contract_cells(Plan &pl, uint64_t *cell_id, int32_t *cell_start,
+                              int32_t *cell_count, int32_t *n_cells, hipStream_t st);
+hipError_t run_dense_table(Plan &pl, hipStream_t st);
+hipError_t run_group_items(Plan &pl, const int64_t *goff, hipStream_t st);
+hipError_t run_copy_sorted(Plan &pl, uint64_t *keys_out, int32_t *perm_out, hipStream_t st);
+hipError_t run_zero_u64(uint64_t *p, int64_t cnt, hipStream_t st);
+hipError_t run_zero_i32(int32_t *p, int64_t cnt, hipStream_t st);
+
+// solve.hip
+hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw,
+                     int32_t *nngb, int32_t *status, uint64_t *stats, hipStream_t st);
+
+// backward.hip
+hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void *grad_rho,
+                        const void *grad_h, void *gx, void *gy, void *gz, void *gm,
+                        hipStream_t st);
+
+// ---------------------------------------------------------------- helpers
+
+// Interleave: bit k of v goes to bit 3k (21-bit input).
+__host__ __device__ inline uint64_t spread3_21(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x001f00000000ffffull;
+    v = (v | (v << 16)) & 0x001f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+__host__ __device__ inline uint64_t morton3(uint64_t qx, uint64_t qy, uint64_t qz) {
+    return (spread3_21(qx) << 2) | (spread3_21(qy) << 1) | spread3_21(qz);
+}
+
+// floor(t) clamped to [0, nmax - 1]; NaN -> 0.
+__device__ inline uint32_t quantise(double t, uint32_t nmax) {
+    if (!(t >= 0.0)) return 0u;
+    if (t >= (double)nmax) return nmax - 1u;
+    return (uint32_t)floor(t);
+}
+
+template <typename T>
+__device__ inline double ld(const void *p, int64_t i) {
+    return (double)static_cast<const T *>(p)[i];
+}
+
+template <typename T>
+__device__ inline void st(void *p, int64_t i, double v) {
+    static_cast<T *>(p)[i] = (T)v;
+}
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+__device__ inline uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ inline int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+__device__ inline double readlane_d(double v, int l) {
+    int2 a = __builtin_bit_cast(int2, v);
+    a.x = __builtin_amdgcn_readlane(a.x, l);
+    a.y = __builtin_amdgcn_readlane(a.y, l);
+    return __builtin_bit_cast(double, a);
+}
+
+__device__ inline float readlane_f(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+template <typename T>
+__device__ inline T wave_max(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ inline T wave_min(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        T w = __shfl_xor(v, o, 64);
+        v = w < v ? w : v;
+    }
+    return v;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Inclusive prefix sum across the wave.
+__device__ inline int wave_incl_scan(int v) {
+    const int l = __lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int w = __shfl_up(v, o, 64);
+        if (l >= o) v += w;
+    }
+    return v;
+}
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace sph

@@ -1,0 +1,146 @@
+"""Host-side checks of the C ABI (no GPU needed).
+
+The library must load, export every function the header declares, agree with
+a C compiler on the layout of ``sph_params``, and reject bad arguments on
+the host before anything is enqueued.
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1612_06090_amd as sph
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sph.h")
+
+
+def _lib():
+    if not os.path.exists(sph.LIB_PATH):
+        from paper_1612_06090_amd import build
+        build.build()
+    return sph.load()
+
+
+def test_exports_every_declared_function():
+    text = open(HEADER).read()
+    decl = set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(sph_\w+)\s*\(", text, re.M))
+    assert {"sph_sort", "sph_density_solve", "sph_density_backward", "sph_workspace_size",
+            "sph_status_string", "sph_default_params"} <= decl
+    lib = _lib()
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(sph.EXPORTS) == decl
+    out = subprocess.run(["nm", "-D", "--defined-only", sph.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for name in decl:
+        assert re.search(rf"\bT {name}\b", out), name
+
+
+def test_params_layout_matches_c(tmp_path):
+    src = tmp_path / "probe.c"
+    fields = [f for f, _ in sph.Params._fields_]
+    body = "\n".join(f'printf("{f} %zu\\n", offsetof(sph_params, {f}));' for f in fields)
+    src.write_text(f'#include <stdio.h>\n#include <stddef.h>\n#include "{HEADER}"\n'
+                   f'int main(void){{ printf("size %zu\\n", sizeof(sph_params));\n{body}\n'
+                   f'return 0; }}\n')
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    assert int(got["size"]) == C.sizeof(sph.Params)
+    for f in fields:
+        assert int(got[f]) == getattr(sph.Params, f).offset, f
+
+
+def test_default_params():
+    _lib()
+    p = sph.default_params()
+    assert p.abi_version == sph.ABI_VERSION
+    assert (p.precision, p.io_dtype, p.mode, p.periodic) == (sph.FP64, sph.F64, sph.BAND, 1)
+    assert (p.box, p.n_target, p.n_tol, p.root_tol) == (1.0, 64.0, 2.0, 1e-12)
+    assert (p.max_iter, p.cell_level, p.segment) == (64, -1, 64)
+
+
+def test_workspace_size_monotone_and_valid():
+    _lib()
+    p = sph.default_params()
+    sizes = [sph.workspace_size(p, n) for n in (0, 1, 64, 4096, 1 << 20, 1 << 24)]
+    assert all(b >= a for a, b in zip(sizes, sizes[1:]))
+    assert sizes[-1] > 300 * (1 << 24) // 10
+    q = sph.default_params(precision=sph.FP32C)
+    assert sph.workspace_size(q, 1 << 20) > 0
+    g = sph.default_params(periodic=0, n_target=32.0, n_tol=1.0)
+    assert sph.workspace_size(g, 10000, 300) > 0
+
+
+@pytest.mark.parametrize("field,value", [
+    ("abi_version", 99), ("precision", 7), ("io_dtype", 3), ("mode", 2), ("periodic", 5),
+    ("box", 0.0), ("box", float("nan")), ("n_target", 0.0), ("n_tol", -1.0),
+    ("max_iter", -1), ("max_iter", 70000), ("cell_level", 22), ("cell_level", 0),
+    ("tile_cell", 3), ("waves_per_cu", 0),
+])
+def test_invalid_params_rejected(field, value):
+    _lib()
+    p = sph.default_params()
+    setattr(p, field, value)
+    out = C.c_size_t(0)
+    rc = sph.load().sph_workspace_size(C.byref(p), 100, 0, C.byref(out))
+    assert rc == sph.E_INVALID
+
+
+def test_invalid_calls_rejected_before_any_launch():
+    lib = _lib()
+    p = sph.default_params()
+    fake = C.c_void_p(0x1000)  # never dereferenced: validation fails first
+    # negative n, null inputs, groups on a periodic set, missing workspace
+    assert lib.sph_density_solve(C.byref(p), -1, 0, None, fake, fake, fake, fake, None, fake,
+                                 fake, None, None, None, None, fake, 1 << 30,
+                                 None) == sph.E_INVALID
+    assert lib.sph_density_solve(C.byref(p), 10, 0, None, None, fake, fake, fake, None, fake,
+                                 fake, None, None, None, None, fake, 1 << 30,
+                                 None) == sph.E_INVALID
+    assert lib.sph_density_solve(C.byref(p), 10, 3, fake, fake, fake, fake, fake, None, fake,
+                                 fake, None, None, None, None, fake, 1 << 30,
+                                 None) == sph.E_INVALID
+    assert lib.sph_density_solve(C.byref(p), 10, 0, None, fake, fake, fake, fake, None, fake,
+                                 fake, None, None, None, None, None, 1 << 30,
+                                 None) == sph.E_INVALID
+    # workspace too small
+    ws = C.c_void_p(0x100000)
+    assert lib.sph_density_solve(C.byref(p), 1000, 0, None, fake, fake, fake, fake, None, fake,
+                                 fake, None, None, None, None, ws, 16, None) == sph.E_WORKSPACE
+    # misaligned workspace
+    assert lib.sph_sort(C.byref(p), 1000, 0, None, fake, fake, fake, fake, fake, None, None,
+                        None, None, C.c_void_p(0x100001), 1 << 30, None) == sph.E_INVALID
+    # isolated groups need offsets and at most 65535 groups
+    g = sph.default_params(periodic=0)
+    assert lib.sph_sort(C.byref(g), 1000, 0, None, fake, fake, fake, fake, fake, None, None,
+                        None, None, ws, 1 << 30, None) == sph.E_INVALID
+    assert lib.sph_sort(C.byref(g), 1000, 70000, fake, fake, fake, fake, fake, fake, None, None,
+                        None, None, ws, 1 << 30, None) == sph.E_INVALID
+    # backward: null cotangent
+    assert lib.sph_density_backward(C.byref(p), 10, 0, None, fake, fake, fake, fake, fake, None,
+                                    None, fake, fake, fake, fake, ws, 1 << 30,
+                                    None) == sph.E_INVALID
+
+
+def test_status_strings():
+    _lib()
+    for code in (sph.OK, sph.E_INVALID, sph.E_WORKSPACE, sph.E_HIP, sph.E_UNSUPPORTED):
+        s = sph.status_string(code)
+        assert s.startswith("SPH_")
+    assert "unknown" in sph.status_string(12345)
+
+
+def test_product_does_not_touch_oracle():
+    # the product path never imports the oracle (or any CPU fallback)
+    pkg = os.path.join(ROOT, "paper_1612_06090_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "sph_oracle" not in text, f

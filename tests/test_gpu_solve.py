@@ -1,0 +1,226 @@
+"""GPU parity of the density + smoothing-length solve against the CPU oracle.
+
+FP64: neighbour counts are bit-exact against the oracle evaluated at the
+GPU's h; rho, h and n agree with the oracle's own solve to 1e-12 relative
+(band-edge decisions, where rounding of the sums flips the stopping test, are
+counted and must be rare).  FP32C: at the GPU's h, |drho|/rho <= 1e-5 and
+|dn| <= 1e-4 for every particle against the FP64 oracle; after the full solve
+|dh|/h <= 1e-5 for at least 99.9% of particles.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1612_06090_amd as sph
+import sphgen
+from gpu_util import gpu_solve, rel, say
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _check_fp64_against_oracle(ps, g, subset=None, max_flip_frac=0.0, **okw):
+    """FP64 GPU result g (full set) vs oracle; subset = indices to check."""
+    idx = np.arange(ps.n) if subset is None else np.asarray(subset)
+    o = oracle.solve(ps, subset=None if subset is None else idx, **okw)
+    gh, grho, gnw = g["h"][idx], g["rho"][idx], g["nw"][idx]
+    # 1) self-consistency at the GPU's h: counts exact, sums to rounding
+    e = oracle.eval_at_h(ps, g["h"], search=1)
+    assert np.array_equal(g["nngb"][idx], e["nngb"][idx].astype(np.int32))
+    assert rel(grho, e["rho"][idx]).max() < TOL64
+    assert np.abs(gnw - e["nw"][idx]).max() < TOL64 * ps.n_target
+    # 2) against the oracle's own iteration
+    same = rel(gh, o["h"]) <= TOL64
+    flips = int((~same).sum())
+    say(f"  flips {flips} / {idx.size}")
+    assert flips <= max_flip_frac * idx.size
+    assert rel(grho[same], o["rho"][same]).max(initial=0) < TOL64
+    assert np.array_equal(g["status"][idx][same], o["status"][same])
+    assert np.array_equal(g["nngb"][idx][same], o["nngb"][same])
+    return o
+
+
+def test_fp64_uniform4096():
+    ps = sphgen.config("uniform4096")
+    say(f"[solve fp64] uniform4096 n={ps.n}")
+    g = gpu_solve(ps, stats=True)
+    _check_fp64_against_oracle(ps, g)
+    assert np.all((g["status"] >> 16) == 0)
+    assert np.all(np.abs(g["nw"] - 64.0) <= 2.0)
+    st = g["stats"]
+    assert st[0] >= g["nngb"].sum() and st[1] >= st[0] and st[2] >= ps.n
+
+
+@pytest.mark.parametrize("n,seed", [(4096 * 2 + 37, 41), (100, 42), (63, 43), (65, 44)])
+def test_fp64_uniform_ragged(n, seed):
+    ps = sphgen.uniform(n, seed=seed, n_target=32.0 if n < 200 else 64.0,
+                        n_tol=1.0 if n < 200 else 2.0)
+    say(f"[solve fp64] uniform n={n}")
+    g = gpu_solve(ps)
+    _check_fp64_against_oracle(ps, g, max_flip_frac=0.01)
+
+
+def test_fp64_clustered_small():
+    ps = sphgen.plummer_mixture(1 << 15, 20, seed=45)
+    say(f"[solve fp64] clustered n={ps.n}")
+    g = gpu_solve(ps)
+    _check_fp64_against_oracle(ps, g, max_flip_frac=1e-3)
+
+
+def test_fp64_clustered2p20_sampled():
+    # full size: the GPU solves all 2^20 particles in the launch the benchmark
+    # times; the oracle solves a sample of them one by one
+    ps = sphgen.config("clustered2^20")
+    say(f"[solve fp64] clustered2^20 n={ps.n}")
+    g = gpu_solve(ps)
+    rng = np.random.default_rng(46)
+    sub = rng.choice(ps.n, 3000, replace=False)
+    _check_fp64_against_oracle(ps, g, subset=sub, max_flip_frac=1e-3)
+    assert np.all((g["status"] >> 16) == 0)
+    assert np.all(np.abs(g["nw"] - 64.0) <= 2.0)
+
+
+def test_fp64_groups():
+    ps = sphgen.groups(200, seed=47, lo=32, hi=5000)
+    say(f"[solve fp64] groups n={ps.n} G=200")
+    g = gpu_solve(ps)
+    _check_fp64_against_oracle(ps, g, max_flip_frac=1e-3)
+
+
+def test_fp64_root_mode():
+    ps = sphgen.uniform(3000, seed=48)
+    g = gpu_solve(ps, mode=sph.ROOT, root_tol=1e-12)
+    o = oracle.solve(ps, mode=oracle.ROOT, root_tol=1e-12)
+    assert rel(g["h"], o["h"]).max() < 1e-12
+    assert np.all(np.abs(g["nw"] - 64.0) <= 64.0 * 1e-12 + 1e-12)
+
+
+def test_fp64_io_float32():
+    ps = sphgen.uniform(5000, seed=49)
+    for k in ("x", "y", "z", "m", "h_init"):
+        setattr(ps, k, getattr(ps, k).astype(np.float32).astype(np.float64))
+    g = gpu_solve(ps, io="float32")
+    o = oracle.solve(ps)
+    assert rel(g["h"], o["h"]).max() < 1e-6   # outputs are rounded to float32
+    assert rel(g["rho"], o["rho"]).max() < 1e-6
+
+
+def test_fp64_fixed_h_and_warm_start():
+    ps = sphgen.uniform(5000, seed=50)
+    g0 = gpu_solve(ps, max_iter=0)
+    e = oracle.eval_at_h(ps, ps.h_init, search=1)
+    assert np.array_equal(g0["nngb"], e["nngb"].astype(np.int32))
+    assert rel(g0["rho"], e["rho"]).max() < TOL64
+    assert np.all(g0["status"] == 0) and np.all(g0["h"] == ps.h_init)
+    g = gpu_solve(ps)
+    w = gpu_solve(ps, h_init=g["h"])
+    assert np.all((w["status"] & 0xFFFF) == 0)
+    assert np.array_equal(w["h"], g["h"])
+
+
+def test_fp64_failure_flags():
+    ps = sphgen.uniform(3000, seed=51)
+    g = gpu_solve(ps, max_iter=1)
+    o = oracle.solve(ps, max_iter=1)
+    assert np.array_equal((g["status"] & sph.ST_NOCONV) != 0, (o["status"] & oracle.ST_NOCONV) != 0)
+    # 4 particles cannot reach 64 neighbours before h hits box/2
+    small = sphgen.uniform(4, seed=52)
+    g = gpu_solve(small)
+    assert np.all((g["status"] & sph.ST_HTOOLARGE) != 0)
+    assert np.all(g["h"] == 0.5 * (1.0 - 2.0 ** -20))
+    # an isolated 3-particle group cannot reach 64
+    grp = sphgen.ParticleSet(x=np.array([0.0, 0.1, 0.2]), y=np.zeros(3), z=np.zeros(3),
+                             m=np.ones(3), h_init=np.full(3, 0.05), periodic=False, box=1.0,
+                             n_target=64.0, n_tol=2.0, offsets=np.array([0, 3]))
+    g = gpu_solve(grp)
+    o = oracle.solve(grp, search=0)
+    assert np.all((g["status"] & sph.ST_UNREACHABLE) != 0)
+    assert rel(g["rho"], o["rho"]).max() < TOL64
+
+
+def test_fp64_bad_inputs():
+    ps = sphgen.uniform(2000, seed=53)
+    ps.x = ps.x.copy()
+    ps.y = ps.y.copy()
+    ps.m = ps.m.copy()
+    ps.x[10] = np.nan
+    ps.y[20] = 1.5            # outside the periodic box
+    ps.m[30] = np.inf
+    g = gpu_solve(ps)
+    o = oracle.solve(ps)
+    bad = np.array([10, 20, 30])
+    assert np.all((g["status"][bad] & sph.ST_BADINPUT) != 0)
+    assert np.all(np.isnan(g["rho"][bad]))
+    good = np.setdiff1d(np.arange(ps.n), bad)
+    same = rel(g["h"][good], o["h"][good]) <= TOL64
+    assert same.mean() > 0.999
+    assert rel(g["rho"][good][same], o["rho"][good][same]).max() < TOL64
+
+
+def test_fp64_deterministic():
+    ps = sphgen.plummer_mixture(50000, 8, seed=54)
+    a = gpu_solve(ps)
+    b = gpu_solve(ps)
+    for k in ("rho", "h", "nw", "nngb", "status"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_empty_and_single():
+    import torch
+    z = torch.empty(0, dtype=torch.float64, device="cuda")
+    o = sph.density_solve(z, z, z, z)
+    torch.cuda.synchronize()
+    assert o["rho"].numel() == 0
+    one = sphgen.uniform(1, seed=55)
+    g = gpu_solve(one)
+    assert (g["status"][0] & sph.ST_HTOOLARGE) != 0
+    assert g["nngb"][0] == 1
+
+
+# ------------------------------------------------------------------ FP32C
+
+
+def _fp32c_bounds(ps, g, sub=None):
+    e = oracle.eval_at_h(ps, g["h"], search=1)
+    idx = np.arange(ps.n) if sub is None else sub
+    good = (g["status"][idx] & sph.ST_BADINPUT) == 0
+    drho = rel(g["rho"][idx][good], e["rho"][idx][good])
+    dn = np.abs(g["nw"][idx][good] - e["nw"][idx][good])
+    say(f"  fp32c fixed-h: max |drho|/rho {drho.max():.3e}  max |dn| {dn.max():.3e}")
+    assert drho.max() <= 1e-5
+    assert dn.max() <= 1e-4
+    return e
+
+
+def test_fp32c_uniform4096():
+    ps = sphgen.config("uniform4096")
+    g = gpu_solve(ps, precision=sph.FP32C)
+    _fp32c_bounds(ps, g)
+    o = oracle.solve(ps)
+    dh = rel(g["h"], o["h"])
+    say(f"  fp32c solve: frac |dh|/h <= 1e-5: {(dh <= 1e-5).mean():.5f}")
+    assert (dh <= 1e-5).mean() >= 0.999
+
+
+def test_fp32c_clustered2p20():
+    ps = sphgen.config("clustered2^20")
+    say(f"[solve fp32c] clustered2^20 n={ps.n}")
+    g = gpu_solve(ps, precision=sph.FP32C)
+    assert np.all((g["status"] >> 16) == 0)
+    rng = np.random.default_rng(56)
+    sub = rng.choice(ps.n, 3000, replace=False)
+    _fp32c_bounds(ps, g, sub)
+    o = oracle.solve(ps, subset=sub)
+    dh = rel(g["h"][sub], o["h"])
+    say(f"  fp32c solve: frac |dh|/h <= 1e-5: {(dh <= 1e-5).mean():.5f}")
+    assert (dh <= 1e-5).mean() >= 0.999
+
+
+def test_fp32c_groups():
+    ps = sphgen.groups(300, seed=57, lo=32, hi=4000, n_target=32.0, n_tol=1.0)
+    g = gpu_solve(ps, precision=sph.FP32C)
+    _fp32c_bounds(ps, g)
+    o = oracle.solve(ps)
+    dh = rel(g["h"], o["h"])
+    assert (dh <= 1e-5).mean() >= 0.999
