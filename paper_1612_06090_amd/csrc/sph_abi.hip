@@ -190,10 +190,6 @@ int sph_sort(const sph_params *params, int64_t n, int32_t n_groups, const int64_
              int32_t *n_cells_out, void *ws, size_t ws_bytes, void *stream) {
     int rc = check_params(params, n, n_groups, group_offsets);
     if (rc != SPH_OK) return rc;
-    if (!x || !y || !z || !keys_out || !perm_out) return SPH_E_INVALID;
-    Plan pl;
-    rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
-    if (rc != SPH_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     if (n == 0) {
         if (n_cells_out) {
@@ -203,6 +199,10 @@ int sph_sort(const sph_params *params, int64_t n, int32_t n_groups, const int64_
         }
         return SPH_OK;
     }
+    if (!x || !y || !z || !keys_out || !perm_out) return SPH_E_INVALID;
+    Plan pl;
+    rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
+    if (rc != SPH_OK) return rc;
     hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
     if (e == hipSuccess) e = run_copy_sorted(pl, keys_out, perm_out, st);
     if (e == hipSuccess && (cell_id_out || cell_start_out || cell_count_out || n_cells_out))
@@ -218,10 +218,6 @@ int sph_density_solve(const sph_params *params, int64_t n, int32_t n_groups,
                       size_t ws_bytes, void *stream) {
     int rc = check_params(params, n, n_groups, group_offsets);
     if (rc != SPH_OK) return rc;
-    if (!x || !y || !z || !m || !rho_out || !h_out) return SPH_E_INVALID;
-    Plan pl;
-    rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
-    if (rc != SPH_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     if (n == 0) {
         if (stats_out) {
@@ -230,6 +226,10 @@ int sph_density_solve(const sph_params *params, int64_t n, int32_t n_groups,
         }
         return SPH_OK;
     }
+    if (!x || !y || !z || !m || !rho_out || !h_out) return SPH_E_INVALID;
+    Plan pl;
+    rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
+    if (rc != SPH_OK) return rc;
     const bool f32c = params->precision == SPH_FP32C;
     hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
     if (e == hipSuccess) e = run_permute(pl, group_offsets, x, y, z, m, h_init, f32c, st);
