@@ -195,7 +195,7 @@ struct CandLDS<SPH_FP64> {
 
 template <>
 struct CandLDS<SPH_FP32C> {
-    float x[64], y[64], z[64], m[64];
+    float4 c[64];  // x, y, z relative to the tile origin (grid units), m
 };
 
 struct Sums {
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                     if (pm == 0) continue;
                     const int cnt = pass ? c_en - c_st : 0;
                     const int incl = wave_incl_scan(cnt);
-                    const int total = __shfl(incl, 63, 64);
+                    const int total = __builtin_amdgcn_readlane(incl, 63);
                     const int nr = __popcll(pm);
                     __syncthreads();
                     if (pass) {
@@ -446,14 +446,14 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                             } else {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
                                 const int32_t W = 1 << B;
-                                c.x[l] = (float)(a.qx[j] + sh0 * W - o0) + a.fx[j];
-                                c.y[l] = (float)(a.qy[j] + sh1 * W - o1) + a.fy[j];
-                                c.z[l] = (float)(a.qz[j] + sh2 * W - o2) + a.fz[j];
-                                c.m[l] = a.fm[j];
+                                c.c[l] = make_float4((float)(a.qx[j] + sh0 * W - o0) + a.fx[j],
+                                                     (float)(a.qy[j] + sh1 * W - o1) + a.fy[j],
+                                                     (float)(a.qz[j] + sh2 * W - o2) + a.fz[j],
+                                                     a.fm[j]);
                             }
                         }
                         __syncthreads();
-                        const int mc = total - cbase < 64 ? total - cbase : 64;
+                        const int mc = total - cbase < 64 ? total - cbase : 64;  // wave-uniform
                         if (in_sub) {
                             if (PREC == SPH_FP64) {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
@@ -481,13 +481,14 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                             } else {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
                                 for (int t = 0; t < mc; ++t) {
-                                    const float dx = c.x[t] - pix;
-                                    const float dy = c.y[t] - piy;
-                                    const float dz = c.z[t] - piz;
+                                    const float4 cj = c.c[t];
+                                    const float dx = cj.x - pix;
+                                    const float dy = cj.y - piy;
+                                    const float dz = cj.z - piz;
                                     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
                                     const float q2 = r2 * ih2;
                                     if (q2 < 1.0f) {
-                                        const float q = __builtin_sqrtf(q2);
+                                        const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
                                         const float u = 1.0f - q;
                                         const bool inner = q <= 0.5f;
                                         const float fin = __builtin_fmaf(q2, __builtin_fmaf(6.0f, q, -6.0f), 1.0f);
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                         const float gq = inner ? gin : gout;
                                         kahan(sm.f0, sm.c0, f);
                                         kahan(sm.f1, sm.c1, gq);
-                                        kahan(sm.fr, sm.cr, c.m[t] * f);
+                                        kahan(sm.fr, sm.cr, cj.w * f);
                                         sm.n += 1;
                                     }
                                 }

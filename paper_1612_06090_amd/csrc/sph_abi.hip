@@ -167,7 +167,7 @@ void sph_default_params(sph_params *p) {
     p->n_tol = 2.0;
     p->root_tol = 1e-12;
     p->cell_level = -1;
-    p->tile_cell = 0;
+    p->tile_cell = -1;
     p->waves_per_cu = 8;
     p->segment = 64;
 }
