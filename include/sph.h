@@ -99,8 +99,10 @@ typedef struct {
                                h, as a power of two exponent in {-1, 0} (default -1);
                                results do not depend on it */
     int32_t  waves_per_cu;  /* tuning: persistent grid = 256 CUs x this (default 8) */
-    int32_t  segment;       /* tuning: sorted particles per work item (multiple of 64;
-                               default 64) */
+    int32_t  segment;       /* tuning: particles per wavefront tile, 8/16/32/64 (default
+                               16); each particle is held by 64/segment lanes that split
+                               its candidate stream; results do not depend on it beyond
+                               summation order */
     void    *prof_events[2];/* optional hipEvent_t pair recorded on `stream` immediately
                                before and after the density kernel (NULL: none) */
     int32_t  reserved[8];   /* must be zero */

@@ -212,15 +212,24 @@ __device__ inline void kahan(float &s, float &c, float x) {
     s = t;
 }
 
-template <int PREC, bool GROUPED>
+// P particles per wave tile; each particle is held by S = 64/P lanes, and
+// lane copy kk of a particle tests chunk candidates kk, kk + S, ...; the
+// copies' sums are combined before the (replicated) h update.  Smaller P
+// means a smaller tile region (fewer candidates per particle) and a shorter
+// sequential stream per wave, at the price of more tiles.
+template <int PREC, bool GROUPED, int P>
 __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
+    constexpr int S = 64 / P;
     __shared__ double act_t[3][64];
     __shared__ double act_H[64];
     __shared__ int32_t rg_start[64], rg_excl[64], rg_code[64];
     __shared__ CandLDS<PREC> cd;
 
     const int l = threadIdx.x;
+    const int p = l & (P - 1);   // particle slot in the tile
+    const int kk = l / P;        // copy index of this lane
     const int B = a.bits;
+    constexpr uint64_t kTileMask = P == 64 ? ~0ull : ((1ull << P) - 1ull);
     uint64_t cnt_pairs = 0, cnt_cands = 0, cnt_passes = 0;
 
     for (;;) {
@@ -252,7 +261,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         }
         const double hmax = GROUPED ? INFINITY : 0.5 * a.box * (1.0 - 0x1p-20);
 
-        const int64_t s = b + l;
+        const int64_t s = b + p;
         const bool mine = s < e;
         // this lane's particle
         double xi = 0.0, yi = 0.0, zi = 0.0;  // FP64 absolute position
@@ -282,7 +291,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             }
         }
         const int64_t oi = mine ? (int64_t)a.perm[s] : 0;
-        if (mine && !valid) {
+        if (mine && !valid && kk == 0) {
             write_out(a, oi, NAN, hs.h, NAN, 0, SPH_ST_BADINPUT);
         }
         if (GROUPED && mine && valid) {
@@ -296,16 +305,20 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         bool done = !(mine && valid);
 
         for (;;) {
-            const uint64_t am = __ballot(!done);
+            // active particles (bits 0..P-1: the lanes of copy 0)
+            const uint64_t am = __ballot(!done) & kTileMask;
             if (am == 0) break;
             const double hq = hs.h * sc;  // h in grid units
             const double Hs = hq * (1.0 + 0x1p-20) + 0x1p-20;
-            act_t[0][l] = tx;
-            act_t[1][l] = ty;
-            act_t[2][l] = tz;
-            act_H[l] = done ? -1.0 : Hs;
+            if (kk == 0) {
+                act_t[0][p] = tx;
+                act_t[1][p] = ty;
+                act_t[2][p] = tz;
+                act_H[p] = done ? -1.0 : Hs;
+            }
             const double h2 = hs.h * hs.h;
             const float ih2 = (float)(1.0 / (hq * hq));
+            const float h2f = (float)(hq * hq);
             Sums sm;
             sm.d0 = sm.d1 = sm.dr = 0.0;
             sm.f0 = sm.f1 = sm.fr = sm.c0 = sm.c1 = sm.cr = 0.f;
@@ -317,7 +330,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             int stk_a[7], stk_b[7];
             int sp = 0;
             stk_a[sp] = 0;
-            stk_b[sp] = 64;
+            stk_b[sp] = P;
             ++sp;
             while (sp > 0) {
                 --sp;
@@ -326,7 +339,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                        ~((1ull << la) - 1ull);
                 const uint64_t sub = am & rmask;
                 if (sub == 0) continue;
-                const bool in_sub = ((sub >> l) & 1ull) != 0;
+                const bool in_sub = ((sub >> p) & 1ull) != 0;
                 double mn0 = wave_min(in_sub ? tx : INFINITY);
                 double mn1 = wave_min(in_sub ? ty : INFINITY);
                 double mn2 = wave_min(in_sub ? tz : INFINITY);
@@ -421,10 +434,21 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                         rg_code[slot] = code;
                     }
                     __syncthreads();
-                    if (in_sub) my_cands += (uint64_t)total;
+                    if (in_sub && kk == 0) my_cands += (uint64_t)total;
                     for (int cbase = 0; cbase < total; cbase += 64) {
                         const int gidx = cbase + l;
-                        if (gidx < total) {
+                        if (gidx >= total) {
+                            // padding: a candidate at infinite distance is never in range
+                            if (PREC == SPH_FP64) {
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
+                                c.x[l] = INFINITY; c.y[l] = INFINITY; c.z[l] = INFINITY;
+                                c.m[l] = 0.0;
+                                c.shx[l] = 0.0; c.shy[l] = 0.0; c.shz[l] = 0.0;
+                            } else {
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
+                                c.c[l] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+                            }
+                        } else {
                             int lo = 0, hi = nr - 1;
                             while (lo < hi) {
                                 const int mid = (lo + hi + 1) >> 1;
@@ -454,11 +478,13 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                         }
                         __syncthreads();
                         const int mc = total - cbase < 64 ? total - cbase : 64;  // wave-uniform
+                        const int nu = (mc + S - 1) / S;  // candidates per copy (padded)
                         if (in_sub) {
                             if (PREC == SPH_FP64) {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
                                 const double hinv = 1.0 / hs.h;
-                                for (int t = 0; t < mc; ++t) {
+                                for (int u = 0; u < nu; ++u) {
+                                    const int t = u * S + kk;
                                     const double dx = (c.x[t] - xi) + c.shx[t];
                                     const double dy = (c.y[t] - yi) + c.shy[t];
                                     const double dz = (c.z[t] - zi) + c.shz[t];
@@ -480,29 +506,36 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                 }
                             } else {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
-                                for (int t = 0; t < mc; ++t) {
-                                    const float4 cj = c.c[t];
+                                // cascade summation: each chunk (<= 64 terms) in plain
+                                // binary32, chunk sums Kahan-compensated into the totals
+                                float a0 = 0.f, a1 = 0.f, ar = 0.f;
+                                for (int u = 0; u < nu; ++u) {
+                                    const float4 cj = c.c[u * S + kk];
                                     const float dx = cj.x - pix;
                                     const float dy = cj.y - piy;
                                     const float dz = cj.z - piz;
                                     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                                    const float q2 = r2 * ih2;
-                                    if (q2 < 1.0f) {
+                                    if (r2 < h2f) {
+                                        const float q2 = fminf(r2 * ih2, 1.0f);
                                         const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
                                         const float u = 1.0f - q;
                                         const bool inner = q <= 0.5f;
                                         const float fin = __builtin_fmaf(q2, __builtin_fmaf(6.0f, q, -6.0f), 1.0f);
-                                        const float fout = 2.0f * u * u * u;
+                                        const float u2 = u * u;
+                                        const float fout = (2.0f * u) * u2;
                                         const float f = inner ? fin : fout;
                                         const float gin = q2 * __builtin_fmaf(18.0f, q, -12.0f);
-                                        const float gout = -6.0f * q * u * u;
+                                        const float gout = (-6.0f * q) * u2;
                                         const float gq = inner ? gin : gout;
-                                        kahan(sm.f0, sm.c0, f);
-                                        kahan(sm.f1, sm.c1, gq);
-                                        kahan(sm.fr, sm.cr, cj.w * f);
+                                        a0 += f;
+                                        a1 += gq;
+                                        ar = __builtin_fmaf(cj.w, f, ar);
                                         sm.n += 1;
                                     }
                                 }
+                                kahan(sm.f0, sm.c0, a0);
+                                kahan(sm.f1, sm.c1, a1);
+                                kahan(sm.fr, sm.cr, ar);
                             }
                         }
                         __syncthreads();
@@ -510,24 +543,37 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 }
             }
 
+            double S0, S1, R;
+            if (PREC == SPH_FP64) {
+                S0 = sm.d0; S1 = sm.d1; R = sm.dr;
+            } else {
+                S0 = (double)sm.f0 - (double)sm.c0;
+                S1 = (double)sm.f1 - (double)sm.c1;
+                R = (double)sm.fr - (double)sm.cr;
+            }
+            int32_t npair = sm.n;
+            // combine the S copies of each particle: a butterfly of commutative
+            // adds, so every copy ends with bit-identical sums (and h updates)
+#pragma unroll
+            for (int o = P; o < 64; o <<= 1) {
+                S0 += __shfl_xor(S0, o, 64);
+                S1 += __shfl_xor(S1, o, 64);
+                R += __shfl_xor(R, o, 64);
+                npair += __shfl_xor(npair, o, 64);
+            }
             if (!done) {
-                double S0, S1, R;
-                if (PREC == SPH_FP64) {
-                    S0 = sm.d0; S1 = sm.d1; R = sm.dr;
-                } else {
-                    S0 = (double)sm.f0 - (double)sm.c0;
-                    S1 = (double)sm.f1 - (double)sm.c1;
-                    R = (double)sm.fr - (double)sm.cr;
-                }
                 const double nwv = (32.0 / 3.0) * S0;
                 const double dndh = -(32.0 / 3.0) * S1 / hs.h;
-                cnt_pairs += (uint64_t)sm.n;
-                cnt_cands += my_cands;
-                cnt_passes += 1;
+                if (kk == 0) {
+                    cnt_pairs += (uint64_t)npair;
+                    cnt_cands += my_cands;
+                    cnt_passes += 1;
+                }
                 const double hcur = hs.h;
                 if (h_step(hs, nwv, dndh, a, hmax)) {
                     const double rho = 8.0 * R / (kPi * hcur * hcur * hcur);
-                    write_out(a, oi, rho, hcur, nwv, sm.n, hs.flags | (hs.it & 0xFFFF));
+                    if (kk == 0)
+                        write_out(a, oi, rho, hcur, nwv, npair, hs.flags | (hs.it & 0xFFFF));
                     done = true;
                 }
             }
@@ -585,13 +631,25 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     }
     const dim3 grid((unsigned)pl.grid), block(64);
     const bool f32c = pl.prm.precision == SPH_FP32C;
+    const int P = pl.prm.segment;
+#define SPH_LAUNCH(PR, GR, PP) \
+    hipLaunchKernelGGL((k_solve<PR, GR, PP>), grid, block, 0, st, a)
+#define SPH_LAUNCH_P(PR, GR)                                   \
+    do {                                                      \
+        if (P == 8) SPH_LAUNCH(PR, GR, 8);                    \
+        else if (P == 16) SPH_LAUNCH(PR, GR, 16);             \
+        else if (P == 32) SPH_LAUNCH(PR, GR, 32);             \
+        else SPH_LAUNCH(PR, GR, 64);                          \
+    } while (0)
     if (!pl.grouped) {
-        if (f32c) hipLaunchKernelGGL((k_solve<SPH_FP32C, false>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_solve<SPH_FP64, false>), grid, block, 0, st, a);
+        if (f32c) SPH_LAUNCH_P(SPH_FP32C, false);
+        else SPH_LAUNCH_P(SPH_FP64, false);
     } else {
-        if (f32c) hipLaunchKernelGGL((k_solve<SPH_FP32C, true>), grid, block, 0, st, a);
-        else hipLaunchKernelGGL((k_solve<SPH_FP64, true>), grid, block, 0, st, a);
+        if (f32c) SPH_LAUNCH_P(SPH_FP32C, true);
+        else SPH_LAUNCH_P(SPH_FP64, true);
     }
+#undef SPH_LAUNCH_P
+#undef SPH_LAUNCH
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (pl.prm.prof_events[1]) e = hipEventRecord((hipEvent_t)pl.prm.prof_events[1], st);

@@ -130,7 +130,8 @@ static int check_params(const sph_params *p, int64_t n, int32_t G, const int64_t
     if (p->cell_level < -1 || p->cell_level > bits || p->cell_level == 0) return SPH_E_INVALID;
     if (p->tile_cell != 0 && p->tile_cell != -1) return SPH_E_INVALID;
     if (p->waves_per_cu < 1 || p->waves_per_cu > 32) return SPH_E_INVALID;
-    if (p->segment != 64) return SPH_E_UNSUPPORTED;
+    if (p->segment != 8 && p->segment != 16 && p->segment != 32 && p->segment != 64)
+        return SPH_E_INVALID;
     for (int k = 0; k < 8; ++k)
         if (p->reserved[k] != 0) return SPH_E_INVALID;
     return SPH_OK;
@@ -169,7 +170,7 @@ void sph_default_params(sph_params *p) {
     p->cell_level = -1;
     p->tile_cell = -1;
     p->waves_per_cu = 8;
-    p->segment = 64;
+    p->segment = 16;
 }
 
 int sph_workspace_size(const sph_params *params, int64_t n, int32_t n_groups, size_t *bytes) {

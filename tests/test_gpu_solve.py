@@ -224,3 +224,20 @@ def test_fp32c_groups():
     o = oracle.solve(ps)
     dh = rel(g["h"], o["h"])
     assert (dh <= 1e-5).mean() >= 0.999
+
+
+@pytest.mark.parametrize("segment", [16, 32])
+def test_tile_sizes_fp64(segment):
+    # smaller tiles hold each particle on 64/segment lanes; results must not
+    # depend on the tiling beyond summation order
+    ps = sphgen.plummer_mixture(1 << 15, 20, seed=45)
+    say(f"[solve fp64] clustered n={ps.n} segment={segment}")
+    g = gpu_solve(ps, segment=segment)
+    _check_fp64_against_oracle(ps, g, max_flip_frac=1e-3)
+
+
+@pytest.mark.parametrize("segment", [16, 32])
+def test_tile_sizes_fp32c(segment):
+    ps = sphgen.groups(300, seed=57, lo=32, hi=4000, n_target=32.0, n_tol=1.0)
+    g = gpu_solve(ps, precision=sph.FP32C, segment=segment)
+    _fp32c_bounds(ps, g)
