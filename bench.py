@@ -99,11 +99,15 @@ def cpu_baseline(ps, budget_s=15.0):
     import oracle
     rng = np.random.default_rng(12345)
     cores = oracle.max_threads()
-    t0 = time.perf_counter()
-    probe = rng.choice(ps.n, 2000, replace=False)
-    r = oracle.solve(ps, subset=probe)
-    t_probe = time.perf_counter() - t0
-    k = int(min(ps.n, max(2000, 2000 * budget_s / max(t_probe, 1e-3))))
+    # two probes separate the fixed cost (tree build) from the per-particle cost
+    t = []
+    for k in (2000, 12000):
+        t0 = time.perf_counter()
+        oracle.solve(ps, subset=rng.choice(ps.n, k, replace=False))
+        t.append(time.perf_counter() - t0)
+    per = max((t[1] - t[0]) / 10000.0, 1e-7)
+    fixed = max(t[0] - 2000 * per, 0.0)
+    k = int(min(ps.n, max(2000, (budget_s - fixed) / per)))
     sub = rng.choice(ps.n, k, replace=False)
     t0 = time.perf_counter()
     r = oracle.solve(ps, subset=sub)
@@ -116,6 +120,84 @@ def cpu_baseline(ps, budget_s=15.0):
             "particles_per_s": k / dt}
 
 
+SOLVE_SRC = os.path.join(ROOT, "paper_1612_06090_amd", "csrc", "solve.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "k_solve_clustered2p20_traffic.txt")
+COPY_MIB = 256
+
+
+def solve_source_sha():
+    import hashlib
+    return hashlib.sha256(open(SOLVE_SRC, "rb").read()).hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per k_solve launch from the committed counter summary, or None
+    when the kernel source changed since the counters were taken."""
+    try:
+        d = json.load(open(TRAFFIC_JSON))
+    except (OSError, ValueError):
+        return None
+    if d.get("solve_hip_sha256") != solve_source_sha():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def profile_run(steps):
+    """FP32C solves plus one plain copy of COPY_MIB MiB (the counter calibration)."""
+    import torch
+    import paper_1612_06090_amd as sph
+    import sphgen
+    ps = sphgen.config("clustered2^20")
+    d = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+         for k in ("x", "y", "z", "m", "h_init")}
+    p = sph.default_params(n_target=ps.n_target, n_tol=ps.n_tol, precision=sph.FP32C)
+    for _ in range(steps):
+        sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p)
+    src = torch.ones(COPY_MIB << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[bench] profile run: {steps} solves + one {COPY_MIB} MiB copy", flush=True)
+
+
+def summarize_traffic(fetch_csv, write_csv, cmd):
+    """Per-launch k_solve HBM traffic from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by the same counter on the calibration copy."""
+    import csv
+
+    def per_kernel(path, counter):
+        # the calibration copy is the largest non-solve dispatch of the run
+        solve, other = [], []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0
+            if "k_solve" in r["Kernel_Name"]:
+                solve.append(v)
+            else:
+                other.append(v)
+        return solve, [max(other)]
+
+    fs, fc = per_kernel(fetch_csv, "FETCH_SIZE")
+    ws, wc = per_kernel(write_csv, "WRITE_SIZE")
+    nbytes = float(COPY_MIB << 20)
+    kf = max(fc) / nbytes
+    kw = max(wc) / nbytes
+    fetch = float(np.mean(fs)) / kf
+    write = float(np.mean(ws)) / kw
+    out = {"kernel": "k_solve (FP32C, 16-particle tiles)", "workload": "clustered2^20",
+           "solve_hip_sha256": solve_source_sha(),
+           "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
+           "bytes_per_launch": fetch + write,
+           "copy_calibration": {"bytes": nbytes, "fetch_factor": kf, "write_factor": kw},
+           "raw_kib": {"fetch_solve": fs, "write_solve": ws, "fetch_copy": fc, "write_copy": wc},
+           "command": cmd}
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    json.dump(out, open(TRAFFIC_JSON, "w"), indent=1)
+    print(json.dumps({k: out[k] for k in ("fetch_bytes_per_launch", "write_bytes_per_launch",
+                                          "copy_calibration")}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,7 +205,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
+                    help="write the k_solve traffic summary from two --pmc runs")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic)
+        return
+    if args.profile_run:
+        profile_run(args.steps)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is "
               "single-GPU in this build.", file=sys.stderr)
@@ -153,8 +245,9 @@ def main():
         flop = FLOP_CAND * r["cands"] + FLOP_PAIR[form] * r["pairs"]
         ach = flop / (r["kernel_ms"] * 1e-3)
         peak = PEAK_FP32 if form == "fp32c" else PEAK_FP64
+        tr = measured_traffic() if form == "fp32c" else None
         return {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": None, "kernel": "k_solve",
+                "frac": ach / peak, "traffic": tr, "kernel": "k_solve",
                 "kernel_ms": r["kernel_ms"], "flop_per_launch": flop}
 
     value = f32["pairs"] / (f32["ms_per_step"] * 1e-3)
