@@ -279,7 +279,7 @@ def _make_autograd():
     torch = _torch()
 
     class SPHDensity(torch.autograd.Function):
-        """(rho, h) = SPHDensity.apply(pos, m, params[, group_offsets]).
+        """(rho, h) = SPHDensity.apply(pos, m, params[, group_offsets[, h_init]]).
 
         Backward runs the hand-written adjoint (``sph_density_backward``)
         with each h held on its implicit root, so gradients flow to
@@ -287,10 +287,12 @@ def _make_autograd():
         """
 
         @staticmethod
-        def forward(ctx, pos, m, params, group_offsets=None):
+        def forward(ctx, pos, m, params, group_offsets=None, h_init=None):
+            params = params or default_params()
             x, y, z = (pos[:, a].contiguous() for a in range(3))
             m = m.contiguous()
-            o = density_solve(x, y, z, m, None, params, group_offsets)
+            h0 = None if h_init is None else h_init.detach().contiguous()
+            o = density_solve(x, y, z, m, h0, params, group_offsets)
             ctx.save_for_backward(x, y, z, m, o["h"])
             ctx.params = params
             ctx.goff = group_offsets
@@ -303,7 +305,8 @@ def _make_autograd():
             gh = grad_h.contiguous() if grad_h is not None else None
             g = density_backward(x, y, z, m, h, gr, gh, ctx.params, ctx.goff)
             gpos = torch.stack([g["gx"], g["gy"], g["gz"]], dim=1)
-            return gpos, g["gm"], None, None
+            # h_init only starts the iteration: the converged h does not depend on it
+            return gpos, g["gm"], None, None, None
 
     return SPHDensity
 

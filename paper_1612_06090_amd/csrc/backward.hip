@@ -1,11 +1,663 @@
-// Adjoint of the density solve (filled in below the forward path).
+// Adjoint of the density solve, with each smoothing length held on its
+// implicit root n_i(h_i, x) = n_i(achieved) (the derivative of the converged
+// recompute loop of Sec. IV-A, Listings 2/3, through Eq. 1).
+//
+// For a cotangent (gr, gh) on (rho, h):
+//   lambda_i = -(gr_i drho_i/dh_i + gh_i) / (dn_i/dh_i)          (0 if dn/dh = 0)
+//   alpha_i = gr_i 8/(pi h_i^4), beta_i = lambda_i (32/3)/h_i, gamma_i = gr_i 8/(pi h_i^3)
+//   pair (i, j in N(i)): c_ij = f'(r/h_i) (alpha_i m_j + beta_i)
+//   dL/dx_k = sum_{j: r < h_k} c_kj (x_k - x_j)/r + sum_{i: r < h_i} c_ik (x_k - x_i)/r
+//   dL/dm_k = sum_{i: r < h_i} gamma_i f(r/h_i)          (self term included)
+//
+// Gather form, no atomics: phase 1 computes lambda and the coefficients of
+// every particle; phase 2 gives each particle both its own neighbours
+// (r < h_k) and its reverse neighbours (particles i whose own sphere reaches
+// it, r < h_i, h_i != h_k).  The reverse set is found by a walk over the
+// implicit octree of the Morton-sorted array: a node (key prefix = a
+// contiguous range) is opened only if it comes within max(h_tile, h_max(node))
+// of the tile, with h_max of any range read in O(1) from a range-max table.
+// Every candidate is visited once and tested against both radii.
 #include "sph_internal.h"
 
 namespace sph {
 
-hipError_t run_backward(Plan &, const int64_t *, const void *, const void *, const void *,
-                        void *, void *, void *, void *, hipStream_t) {
-    return hipErrorNotSupported;
+constexpr int kLeafMax = 32;   // a walk node with at most this many particles is a leaf
+constexpr int kWorkCap = 384;  // walk stack capacity (overflowing nodes become leaves)
+constexpr float kSplitExtent = 4.0f;  // split lane ranges wider than this many radii
+
+struct AdjArgs {
+    int64_t n;
+    int32_t G;
+    const int64_t *goff;
+    const uint64_t *skeys;
+    const int32_t *perm;
+    const double *sx, *sy, *sz, *sm, *sh;
+    const int32_t *qx, *qy, *qz;
+    const float *fx, *fy, *fz, *fm;
+    const int32_t *table;
+    int32_t Ld;
+    const double *frame;
+    const int32_t *gitems;
+    int64_t n_items;
+    const float *rmq;
+    int32_t rmq_levels;
+    double box;
+    int32_t bits;
+    double *alpha, *beta, *gamma;
+    const double *grs, *ghs;
+    int32_t phase;
+    int32_t out_f32;
+    void *gx, *gy, *gz, *gm;
+    int32_t *queue;
+};
+
+// max of rmq level 0 over [st, en), en > st
+__device__ inline float range_hmax(const AdjArgs &a, int32_t st, int32_t en) {
+    const int32_t len = en - st;
+    const int k = 31 - __builtin_clz((unsigned)len);
+    const float *t = a.rmq + (int64_t)k * a.n;
+    const float u = t[st], v = t[en - (1 << k)];
+    return u > v ? u : v;
+}
+
+// first slot in [b, e) whose key is >= k
+__device__ inline int32_t lower_bound_key(const uint64_t *keys, int32_t b, int32_t e, uint64_t k) {
+    while (b < e) {
+        const int32_t mid = (b + e) >> 1;
+        if (keys[mid] < k) b = mid + 1; else e = mid;
+    }
+    return b;
+}
+
+template <int PREC>
+struct AdjCand;
+
+template <>
+struct AdjCand<SPH_FP64> {
+    double4 p;     // x, y, z (absolute), m
+    double4 s;     // image shift (absolute), unused
+    double4 h;     // h, 1/h, alpha, beta
+    double g;      // gamma
+};
+
+template <>
+struct AdjCand<SPH_FP32C> {
+    float4 p;      // x, y, z relative to the tile origin (grid units), m
+    float4 h;      // h (grid units), 1/h (grid units), alpha, beta (absolute)
+    float g;       // gamma
+};
+
+template <int PREC>
+struct AdjLDS {
+    int32_t wk_st[kWorkCap], wk_en[kWorkCap], wk_c[kWorkCap][3], wk_L[kWorkCap];
+    int32_t rg_start[64], rg_excl[64], rg_code[64];
+    AdjCand<PREC> cand[64];
+};
+
+// M4 spline f(q) and f'(q) for 0 <= q <= 1 (0 beyond)
+template <typename T>
+__device__ inline void spline_fd(T q, T &f, T &fp) {
+    const T u = T(1) - q;
+    if (q <= T(0.5)) {
+        f = T(1) + q * q * (T(6) * q - T(6));
+        fp = q * (T(18) * q - T(12));
+    } else if (q < T(1)) {
+        f = T(2) * u * u * u;
+        fp = T(-6) * u * u;
+    } else {
+        f = T(0);
+        fp = T(0);
+    }
+}
+
+template <int PREC, bool GROUPED>
+__global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
+    __shared__ AdjLDS<PREC> S;
+    const int l = threadIdx.x;
+    const int B = a.bits;
+
+    for (;;) {
+        int item = 0;
+        if (l == 0) item = atomicAdd(a.queue, 1);
+        item = __builtin_amdgcn_readlane(item, 0);
+        const int64_t n_items = GROUPED ? (int64_t)a.gitems[a.G] : a.n_items;
+        if (item >= n_items) break;
+
+        int64_t b, e;
+        int32_t g = 0;
+        double org0 = 0.0, org1 = 0.0, org2 = 0.0, sc;
+        if (!GROUPED) {
+            b = (int64_t)item * 64;
+            e = b + 64 < a.n ? b + 64 : a.n;
+            sc = 2097152.0 / a.box;
+        } else {
+            int32_t lo = 0, hi = a.G - 1;
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (a.gitems[mid] <= item) lo = mid; else hi = mid - 1;
+            }
+            g = lo;
+            b = a.goff[g] + (int64_t)(item - a.gitems[g]) * 64;
+            e = b + 64 < a.goff[g + 1] ? b + 64 : a.goff[g + 1];
+            const double *f = a.frame + 8 * (int64_t)g;
+            org0 = f[0]; org1 = f[1]; org2 = f[2];
+            sc = f[6];
+        }
+        const int64_t s = b + l;
+        const bool mine = s < e;
+        double xk = 0.0, yk = 0.0, zk = 0.0, mk = 0.0, hk = 1.0;
+        int32_t qxk = 0, qyk = 0, qzk = 0;
+        float fxk = 0.f, fyk = 0.f, fzk = 0.f;
+        bool valid = false;
+        if (mine) {
+            hk = a.sh[s];
+            if constexpr (PREC == SPH_FP64) {
+                xk = a.sx[s]; yk = a.sy[s]; zk = a.sz[s]; mk = a.sm[s];
+                valid = !isnan(xk);
+                const double tx = (xk - org0) * sc, ty = (yk - org1) * sc, tz = (zk - org2) * sc;
+                qxk = valid ? (int32_t)floor(tx) : 0;
+                qyk = valid ? (int32_t)floor(ty) : 0;
+                qzk = valid ? (int32_t)floor(tz) : 0;
+                fxk = (float)(tx - (double)qxk);
+                fyk = (float)(ty - (double)qyk);
+                fzk = (float)(tz - (double)qzk);
+            } else {
+                qxk = a.qx[s]; qyk = a.qy[s]; qzk = a.qz[s];
+                fxk = a.fx[s]; fyk = a.fy[s]; fzk = a.fz[s];
+                mk = (double)a.fm[s];
+                valid = !isnan(fxk);
+            }
+        }
+        const uint64_t vm = __ballot(valid);
+        double ak = 0.0, bk = 0.0;  // own alpha, beta (phase 2)
+        if (a.phase == 2 && valid) { ak = a.alpha[s]; bk = a.beta[s]; }
+        const float akf = (float)ak, bkf = (float)bk;
+
+        // per-lane accumulators: phase 1 -> S1, R, T ; phase 2 -> gx, gy, gz, gm
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+
+        const double hq = hk * sc;  // own h in grid units
+        const float Hk = (float)(hq * (1.0 + 0x1p-16)) + 0x1p-10f;
+        const float hk2f = (float)(hq * hq);
+        const float hkinvf = (float)(1.0 / hq);
+        const double hk2 = hk * hk, hkinv = 1.0 / hk;
+
+        // Lane ranges of the tile, each walked on its own.  A tile whose
+        // bounding box is wide compared with its radius (it straddles distant
+        // parts of the Morton order) is split in halves of its valid lanes:
+        // the walk region stays compact and the binary32 coordinates relative
+        // to the range's origin keep the precision of the local separation.
+        int rs_a[7], rs_b[7];
+        int rsp = 0;
+        if (vm != 0) { rs_a[0] = 0; rs_b[0] = 64; rsp = 1; }
+        while (rsp > 0) {
+            --rsp;
+            const int la = rs_a[rsp], lb = rs_b[rsp];
+            const bool in_sub = valid && l >= la && l < lb;
+            const uint64_t sm = __ballot(in_sub);
+            if (sm == 0) continue;
+            const int first = __ffsll((unsigned long long)sm) - 1;
+            const int32_t t0 = readlane_i(qxk, first), t1 = readlane_i(qyk, first),
+                          t2 = readlane_i(qzk, first);
+            const float pk0 = (float)(qxk - t0) + fxk;
+            const float pk1 = (float)(qyk - t1) + fyk;
+            const float pk2 = (float)(qzk - t2) + fzk;
+            const float mn0 = wave_min(in_sub ? pk0 : INFINITY), mx0 = wave_max(in_sub ? pk0 : -INFINITY);
+            const float mn1 = wave_min(in_sub ? pk1 : INFINITY), mx1 = wave_max(in_sub ? pk1 : -INFINITY);
+            const float mn2 = wave_min(in_sub ? pk2 : INFINITY), mx2 = wave_max(in_sub ? pk2 : -INFINITY);
+            const float Ht = wave_max(in_sub ? Hk : 0.f);
+            const float ext = fmaxf(mx0 - mn0, fmaxf(mx1 - mn1, mx2 - mn2));
+            if (ext > kSplitExtent * Ht && __popcll(sm) > 1) {
+                // lower half of the valid lanes, then the upper half
+                uint64_t t = sm;
+                for (int k = __popcll(sm) / 2; k > 0; --k) t &= t - 1;
+                const int mid = __ffsll((unsigned long long)t) - 1;
+                rs_a[rsp] = mid; rs_b[rsp] = lb; ++rsp;
+                rs_a[rsp] = la; rs_b[rsp] = mid; ++rsp;
+                continue;
+            }
+
+            // ---- walk set-up: root nodes
+            int wsz = 0;   // work stack size (uniform)
+            int nl = 0;    // leaves collected (uniform)
+            const int64_t gbase = GROUPED ? a.goff[g] : 0;
+            const int64_t gend = GROUPED ? a.goff[g + 1] : a.n;
+            // tile region half-width for the roots: own h, and for phase 2 the
+            // largest h of the set (any sphere may reach the tile)
+            float Rroot = Ht;
+            if (a.phase == 2) {
+                const float hall = range_hmax(a, (int32_t)gbase, (int32_t)gend);
+                Rroot = hall > Rroot ? hall : Rroot;
+            }
+            Rroot = Rroot * (1.0f + 0x1p-12f) + 1.0f;
+
+            // streaming of the collected leaves (ranges) through LDS
+            auto stream_leaves = [&](int nleaf) {
+                // prefix sums of leaf sizes (leaf list holds start and count)
+                const int cnt = l < nleaf ? S.rg_excl[l] : 0;  // rg_excl holds counts here
+                const int incl = wave_incl_scan(cnt);
+                const int total = __builtin_amdgcn_readlane(incl, 63);
+                __syncthreads();
+                if (l < nleaf) S.rg_excl[l] = incl - cnt;
+                __syncthreads();
+                for (int cbase = 0; cbase < total; cbase += 64) {
+                    const int gidx = cbase + l;
+                    __syncthreads();
+                    if (gidx < total) {
+                        int lo = 0, hi = nleaf - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (S.rg_excl[mid] <= gidx) lo = mid; else hi = mid - 1;
+                        }
+                        const int64_t j = (int64_t)S.rg_start[lo] + (gidx - S.rg_excl[lo]);
+                        const int cc = S.rg_code[lo];
+                        const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1, sh2 = ((cc >> 4) & 3) - 1;
+                        const double hj = a.sh[j];
+                        const double aj = a.phase == 2 ? a.alpha[j] : 0.0;
+                        const double bj = a.phase == 2 ? a.beta[j] : 0.0;
+                        const double gj = a.phase == 2 ? a.gamma[j] : 0.0;
+                        if constexpr (PREC == SPH_FP64) {
+                            S.cand[l].p = make_double4(a.sx[j], a.sy[j], a.sz[j], a.sm[j]);
+                            S.cand[l].s = make_double4((double)sh0 * a.box, (double)sh1 * a.box,
+                                                       (double)sh2 * a.box, 0.0);
+                            S.cand[l].h = make_double4(hj, 1.0 / hj, aj, bj);
+                            S.cand[l].g = gj;
+                        } else {
+                            const int32_t W = 1 << B;
+                            double scj = sc;
+                            const double hqj = hj * scj;
+                            S.cand[l].p = make_float4((float)(a.qx[j] + sh0 * W - t0) + a.fx[j],
+                                                      (float)(a.qy[j] + sh1 * W - t1) + a.fy[j],
+                                                      (float)(a.qz[j] + sh2 * W - t2) + a.fz[j],
+                                                      a.fm[j]);
+                            S.cand[l].h = make_float4((float)hqj, (float)(1.0 / hqj), (float)aj,
+                                                      (float)bj);
+                            S.cand[l].g = (float)gj;
+                        }
+                    } else {
+                        if constexpr (PREC == SPH_FP64) {
+                            S.cand[l].p = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+                            S.cand[l].s = make_double4(0.0, 0.0, 0.0, 0.0);
+                            S.cand[l].h = make_double4(1.0, 1.0, 0.0, 0.0);
+                            S.cand[l].g = 0.0;
+                        } else {
+                            S.cand[l].p = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+                            S.cand[l].h = make_float4(1.f, 1.f, 0.f, 0.f);
+                            S.cand[l].g = 0.f;
+                        }
+                    }
+                    __syncthreads();
+                    const int mc = total - cbase < 64 ? total - cbase : 64;
+                    if (in_sub) {
+                        if constexpr (PREC == SPH_FP64) {
+                            for (int t = 0; t < mc; ++t) {
+                                const AdjCand<SPH_FP64> c = S.cand[t];
+                                const double dx = (c.p.x - xk) + c.s.x;
+                                const double dy = (c.p.y - yk) + c.s.y;
+                                const double dz = (c.p.z - zk) + c.s.z;
+                                const double r2 = (dx * dx + dy * dy) + dz * dz;
+                                const bool in1 = r2 < hk2;
+                                if (a.phase == 1) {
+                                    if (in1) {
+                                        const double q = sqrt(r2) * hkinv;
+                                        double f, fp;
+                                        spline_fd<double>(q, f, fp);
+                                        acc0 += q * fp;
+                                        acc1 += c.p.w * f;
+                                        acc2 += c.p.w * q * fp;
+                                    }
+                                } else {
+                                    const bool in2 = r2 < c.h.x * c.h.x;
+                                    if (in1 || in2) {
+                                        const double r = sqrt(r2);
+                                        double cc = 0.0;
+                                        if (in1) {
+                                            double f, fp;
+                                            spline_fd<double>(r * hkinv, f, fp);
+                                            cc += fp * (ak * c.p.w + bk);
+                                        }
+                                        if (in2) {
+                                            double f, fp;
+                                            spline_fd<double>(r * c.h.y, f, fp);
+                                            cc += fp * (c.h.z * mk + c.h.w);
+                                            acc3 += c.g * f;
+                                        }
+                                        if (r > 0.0) {
+                                            const double w = cc / r;
+                                            acc0 -= w * dx;
+                                            acc1 -= w * dy;
+                                            acc2 -= w * dz;
+                                        }
+                                    }
+                                }
+                            }
+                        } else {
+                            // chunk partial sums in binary32, folded into binary64
+                            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+                            for (int t = 0; t < mc; ++t) {
+                                const AdjCand<SPH_FP32C> c = S.cand[t];
+                                const float dx = c.p.x - pk0;
+                                const float dy = c.p.y - pk1;
+                                const float dz = c.p.z - pk2;
+                                const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                                const bool in1 = r2 < hk2f;
+                                if (a.phase == 1) {
+                                    if (in1) {
+                                        const float q = fminf(__builtin_amdgcn_sqrtf(r2) * hkinvf, 1.0f);
+                                        float f, fp;
+                                        spline_fd<float>(q, f, fp);
+                                        s0 += q * fp;
+                                        s1 = __builtin_fmaf(c.p.w, f, s1);
+                                        s2 = __builtin_fmaf(c.p.w * q, fp, s2);
+                                    }
+                                } else {
+                                    const bool in2 = r2 < c.h.x * c.h.x;
+                                    if (in1 || in2) {
+                                        const float r = __builtin_amdgcn_sqrtf(r2);
+                                        float cc = 0.f;
+                                        if (in1) {
+                                            float f, fp;
+                                            spline_fd<float>(fminf(r * hkinvf, 1.0f), f, fp);
+                                            cc = fp * __builtin_fmaf(akf, c.p.w, bkf);
+                                        }
+                                        if (in2) {
+                                            float f, fp;
+                                            spline_fd<float>(fminf(r * c.h.y, 1.0f), f, fp);
+                                            cc = __builtin_fmaf(fp, __builtin_fmaf(c.h.z, (float)mk, c.h.w), cc);
+                                            s3 = __builtin_fmaf(c.g, f, s3);
+                                        }
+                                        if (r > 0.f) {
+                                            const float w = cc / r;
+                                            s0 -= w * dx;
+                                            s1 -= w * dy;
+                                            s2 -= w * dz;
+                                        }
+                                    }
+                                }
+                            }
+                            acc0 += (double)s0;
+                            acc1 += (double)s1;
+                            acc2 += (double)s2;
+                            acc3 += (double)s3;
+                        }
+                    }
+                }
+            };
+
+            // node test: does node box (grid units, relative to t) come within
+            // the tile's radius (phase 1) or max(tile radius, node h_max) (phase 2)?
+            auto node_pass = [&](int64_t c0, int64_t c1, int64_t c2, int L, int32_t st, int32_t en) {
+                const int ex = B - L;
+                const int64_t sd = (int64_t)1 << ex;
+                const float side = (float)sd;
+                const float lo0 = (float)(c0 * sd - t0), lo1 = (float)(c1 * sd - t1),
+                            lo2 = (float)(c2 * sd - t2);
+                const float g0 = fmaxf(0.f, fmaxf(lo0 - mx0, mn0 - (lo0 + side)));
+                const float g1 = fmaxf(0.f, fmaxf(lo1 - mx1, mn1 - (lo1 + side)));
+                const float g2 = fmaxf(0.f, fmaxf(lo2 - mx2, mn2 - (lo2 + side)));
+                float R = Ht;
+                if (a.phase == 2) {
+                    const float hm = range_hmax(a, st, en);
+                    R = hm > R ? hm : R;
+                }
+                // slack covers the binary32 rounding of tile coordinates (up to
+                // 2^-3 grid units at 2^21) and of the node corners
+                R = R * (1.0f + 0x1p-12f) + side * 0x1p-12f + 1.0f;
+                return g0 * g0 + g1 * g1 + g2 * g2 <= R * R;
+            };
+
+            // append passing nodes of this round: leaves to the leaf list, the rest
+            // to the work stack (a full stack turns them into leaves)
+            auto place = [&](bool pass, bool leaf, int32_t st, int32_t en, int64_t c0, int64_t c1,
+                             int64_t c2, int L) {
+                uint64_t wm = __ballot(pass && !leaf);
+                const int nw = __popcll(wm);
+                if (wsz + nw > kWorkCap) {
+                    leaf = leaf || pass;
+                    wm = 0;
+                }
+                const uint64_t lm = __ballot(pass && leaf);
+                const int nlf = __popcll(lm);
+                if (nl + nlf > 64) {
+                    stream_leaves(nl);
+                    nl = 0;
+                }
+                __syncthreads();
+                if ((wm >> l) & 1ull) {
+                    const int k = wsz + (int)mbcnt(wm);
+                    S.wk_st[k] = st;
+                    S.wk_en[k] = en;
+                    S.wk_c[k][0] = (int32_t)c0;
+                    S.wk_c[k][1] = (int32_t)c1;
+                    S.wk_c[k][2] = (int32_t)c2;
+                    S.wk_L[k] = L;
+                }
+                if ((lm >> l) & 1ull) {
+                    const int k = nl + (int)mbcnt(lm);
+                    int code = 0;
+                    if (!GROUPED) {
+                        const int s0 = (int)(c0 >> L), s1 = (int)(c1 >> L), s2 = (int)(c2 >> L);
+                        code = (s0 + 1) | ((s1 + 1) << 2) | ((s2 + 1) << 4);
+                    } else {
+                        code = 1 | (1 << 2) | (1 << 4);
+                    }
+                    S.rg_start[k] = st;
+                    S.rg_excl[k] = en - st;  // counts; turned into prefix sums on streaming
+                    S.rg_code[k] = code;
+                }
+                __syncthreads();
+                wsz += __popcll(wm);
+                nl += nlf;
+            };
+
+            // roots: periodic -- every level-1 cell image meeting the region
+            // (tile box +- Rroot); groups -- the group itself (level 0)
+            if (!GROUPED) {
+                const int ex = B - 1;
+                const int64_t lo0 = ((int64_t)t0 + (int64_t)floorf(mn0 - Rroot) - 1) >> ex;
+                const int64_t lo1 = ((int64_t)t1 + (int64_t)floorf(mn1 - Rroot) - 1) >> ex;
+                const int64_t lo2 = ((int64_t)t2 + (int64_t)floorf(mn2 - Rroot) - 1) >> ex;
+                const int64_t hi0 = ((int64_t)t0 + (int64_t)floorf(mx0 + Rroot) + 1) >> ex;
+                const int64_t hi1 = ((int64_t)t1 + (int64_t)floorf(mx1 + Rroot) + 1) >> ex;
+                const int64_t hi2 = ((int64_t)t2 + (int64_t)floorf(mx2 + Rroot) + 1) >> ex;
+                const int64_t nx = hi0 - lo0 + 1, ny = hi1 - lo1 + 1, nz = hi2 - lo2 + 1;
+                const int64_t nroot = nx * ny * nz;  // <= 6^3: region within [-1, 2) boxes
+                for (int64_t rb = 0; rb < nroot; rb += 64) {
+                    const int64_t r = rb + l;
+                    bool pass = false, leaf = false;
+                    int32_t st = 0, en = 0;
+                    int64_t c0 = 0, c1 = 0, c2 = 0;
+                    if (r < nroot) {
+                        c0 = lo0 + r % nx;
+                        c1 = lo1 + (r / nx) % ny;
+                        c2 = lo2 + r / (nx * ny);
+                        const uint64_t cm = morton3((uint64_t)(c0 & 1), (uint64_t)(c1 & 1),
+                                                    (uint64_t)(c2 & 1));
+                        const int sh = 3 * (a.Ld - 1);
+                        st = a.table[cm << sh];
+                        en = a.table[(cm + 1) << sh];
+                        pass = en > st && node_pass(c0, c1, c2, 1, st, en);
+                        leaf = en - st <= kLeafMax;
+                    }
+                    place(pass, leaf, st, en, c0, c1, c2, 1);
+                }
+            } else {
+                bool pass = false, leaf = false;
+                int32_t st = 0, en = 0;
+                if (l == 0) {
+                    st = (int32_t)gbase;
+                    en = (int32_t)gend;
+                    pass = en > st && node_pass(0, 0, 0, 0, st, en);
+                    leaf = en - st <= kLeafMax;
+                }
+                place(pass, leaf, st, en, 0, 0, 0, 0);
+            }
+
+            // expand: pop up to 8 nodes, one lane per child
+            while (wsz > 0) {
+                const int n8 = wsz < 8 ? wsz : 8;
+                const int base = wsz - n8;
+                const int nd = l >> 3, ch = l & 7;
+                bool pass = false, leaf = false;
+                int32_t st = 0, en = 0;
+                int64_t c0 = 0, c1 = 0, c2 = 0;
+                int L = 0;
+                if (nd < n8) {
+                    const int k = base + nd;
+                    const int32_t pst = S.wk_st[k], pen = S.wk_en[k];
+                    const int pL = S.wk_L[k];
+                    const int64_t p0 = S.wk_c[k][0], p1 = S.wk_c[k][1], p2 = S.wk_c[k][2];
+                    L = pL + 1;
+                    c0 = 2 * p0 + ((ch >> 2) & 1);
+                    c1 = 2 * p1 + ((ch >> 1) & 1);
+                    c2 = 2 * p2 + (ch & 1);
+                    // key range of the child: its Morton prefix (wrapped) at level L
+                    const int64_t m = ((int64_t)1 << L) - 1;
+                    const uint64_t cm = morton3((uint64_t)(c0 & m), (uint64_t)(c1 & m),
+                                                (uint64_t)(c2 & m));
+                    const int ks = 3 * (B - L);
+                    const uint64_t gb = GROUPED ? ((uint64_t)(uint32_t)g << 48) : 0ull;
+                    st = lower_bound_key(a.skeys, pst, pen, gb + (cm << ks));
+                    en = ch == 7 ? pen : lower_bound_key(a.skeys, st, pen, gb + ((cm + 1) << ks));
+                    pass = en > st && node_pass(c0, c1, c2, L, st, en);
+                    leaf = en - st <= kLeafMax || L >= B;
+                }
+                __syncthreads();
+                wsz = base;
+                place(pass, leaf, st, en, c0, c1, c2, L);
+            }
+            if (nl > 0) stream_leaves(nl);
+        }
+
+        // ---- per-particle results
+        if (a.phase == 1) {
+            if (mine) {
+                double al = 0.0, be = 0.0, ga = 0.0;
+                if (valid) {
+                    const double gr = a.grs[s], gh = a.ghs[s];
+                    const double h4 = hk * hk * hk * hk;
+                    const double drhodh = -8.0 * (3.0 * acc1 + acc2) / (kPi * h4);
+                    const double dndh = -(32.0 / 3.0) * acc0 / hk;
+                    const double lam = dndh > 0.0 ? -(gr * drhodh + gh) / dndh : 0.0;
+                    al = gr * 8.0 / (kPi * h4);
+                    be = lam * (32.0 / 3.0) / hk;
+                    ga = gr * 8.0 / (kPi * hk * hk * hk);
+                }
+                a.alpha[s] = al;
+                a.beta[s] = be;
+                a.gamma[s] = ga;
+            }
+        } else if (mine) {
+            const int64_t oi = a.perm[s];
+            double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+            // the sums hold c (x_k - x_j)/r: unit vectors, the same in grid units
+            if (valid) { g0 = acc0; g1 = acc1; g2 = acc2; g3 = acc3; }
+            if (a.out_f32) {
+                st<float>(a.gx, oi, g0); st<float>(a.gy, oi, g1);
+                st<float>(a.gz, oi, g2); st<float>(a.gm, oi, g3);
+            } else {
+                st<double>(a.gx, oi, g0); st<double>(a.gy, oi, g1);
+                st<double>(a.gz, oi, g2); st<double>(a.gm, oi, g3);
+            }
+        }
+    }
+}
+
+// sorted-order cotangents
+template <typename T>
+__global__ void k_adj_gather(int64_t n, const int32_t *perm, const void *gr, const void *gh,
+                             double *grs, double *ghs) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+    grs[s] = ld<T>(gr, i);
+    ghs[s] = gh ? ld<T>(gh, i) : 0.0;
+}
+
+// level 0 of the range-max table: h in grid units, rounded up to binary32
+__global__ void k_rmq_base(int64_t n, const double *sh, const uint64_t *skeys, bool grouped,
+                           double box, const double *frame, float *t) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double sc = grouped ? frame[8 * (int64_t)(uint32_t)(skeys[s] >> 48) + 6] : 2097152.0 / box;
+    const double hq = sh[s] * sc;
+    float f = (float)hq;
+    if (!(hq > 0.0) || !isfinite(hq)) f = 0.f;
+    else if ((double)f < hq) f = nextafterf(f, INFINITY);
+    t[s] = f;
+}
+
+__global__ void k_rmq_level(int64_t n, int k, float *t) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const float *p = t + (int64_t)(k - 1) * n;
+    const int64_t o = s + ((int64_t)1 << (k - 1));
+    const float u = p[s], v = p[o < n ? o : n - 1];
+    t[(int64_t)k * n + s] = u > v ? u : v;
+}
+
+hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void *grad_rho,
+                        const void *grad_h, void *gx, void *gy, void *gz, void *gm,
+                        hipStream_t st) {
+    (void)h;
+    const int64_t n = pl.n;
+    const unsigned nbk = (unsigned)ceil_div(n, 256);
+    double *alpha = pl.adj, *beta = pl.adj + n, *gamma = pl.adj + 2 * n;
+    double *grs = pl.adj + 3 * n, *ghs = pl.adj + 4 * n;
+    if (pl.prm.io_dtype == SPH_F32)
+        hipLaunchKernelGGL(k_adj_gather<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm, grad_rho,
+                           grad_h, grs, ghs);
+    else
+        hipLaunchKernelGGL(k_adj_gather<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm, grad_rho,
+                           grad_h, grs, ghs);
+    hipLaunchKernelGGL(k_rmq_base, dim3(nbk), dim3(256), 0, st, n, pl.sh0, pl.skeys, pl.grouped,
+                       pl.prm.box, pl.frame, pl.rmq);
+    for (int k = 1; k < pl.rmq_levels; ++k)
+        hipLaunchKernelGGL(k_rmq_level, dim3(nbk), dim3(256), 0, st, n, k, pl.rmq);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    AdjArgs a;
+    a.n = n;
+    a.G = pl.G;
+    a.goff = goff;
+    a.skeys = pl.skeys;
+    a.perm = pl.perm;
+    a.sx = pl.sx; a.sy = pl.sy; a.sz = pl.sz; a.sm = pl.sm; a.sh = pl.sh0;
+    a.qx = pl.qx; a.qy = pl.qy; a.qz = pl.qz;
+    a.fx = pl.fx; a.fy = pl.fy; a.fz = pl.fz; a.fm = pl.fm;
+    a.table = pl.table;
+    a.Ld = pl.Ld;
+    a.frame = pl.frame;
+    a.gitems = pl.gitems;
+    a.n_items = ceil_div(n, 64);
+    a.rmq = pl.rmq;
+    a.rmq_levels = pl.rmq_levels;
+    a.box = pl.prm.box;
+    a.bits = pl.bits;
+    a.alpha = alpha; a.beta = beta; a.gamma = gamma;
+    a.grs = grs; a.ghs = ghs;
+    a.out_f32 = pl.prm.io_dtype == SPH_F32;
+    a.gx = gx; a.gy = gy; a.gz = gz; a.gm = gm;
+    a.queue = pl.ctrl;
+    const int64_t full = (int64_t)256 * pl.prm.waves_per_cu;
+    const dim3 grid((unsigned)(pl.grouped ? full : (a.n_items < full ? a.n_items : full)));
+    const bool f32c = pl.prm.precision == SPH_FP32C;
+    for (int phase = 1; phase <= 2; ++phase) {
+        a.phase = phase;
+        e = run_zero_i32(pl.ctrl, 4, st);
+        if (e != hipSuccess) return e;
+        if (!pl.grouped) {
+            if (f32c) hipLaunchKernelGGL((k_adjoint<SPH_FP32C, false>), grid, dim3(64), 0, st, a);
+            else hipLaunchKernelGGL((k_adjoint<SPH_FP64, false>), grid, dim3(64), 0, st, a);
+        } else {
+            if (f32c) hipLaunchKernelGGL((k_adjoint<SPH_FP32C, true>), grid, dim3(64), 0, st, a);
+            else hipLaunchKernelGGL((k_adjoint<SPH_FP64, true>), grid, dim3(64), 0, st, a);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace sph

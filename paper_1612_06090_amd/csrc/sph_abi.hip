@@ -101,8 +101,9 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
     }
     pl.ctrl = (int32_t *)take(64);
     pl.stats = (uint64_t *)take(64);
-    pl.lam = (double *)take(8 * N);
-    pl.acc = (double *)take(16 * N);
+    pl.adj = (double *)take(5 * 8 * N);
+    pl.rmq_levels = ceil_log2_i64((int64_t)N) + 1;
+    pl.rmq = (float *)take(4 * N * (size_t)pl.rmq_levels);
     pl.total = off;
     return SPH_OK;
 }
@@ -252,14 +253,27 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
                          void *grad_m, void *ws, size_t ws_bytes, void *stream) {
     int rc = check_params(params, n, n_groups, group_offsets);
     if (rc != SPH_OK) return rc;
+    if (n == 0) return SPH_OK;
     if (!x || !y || !z || !m || !h || !grad_rho || !grad_x || !grad_y || !grad_z || !grad_m)
         return SPH_E_INVALID;
     Plan pl;
     rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
     if (rc != SPH_OK) return rc;
-    (void)grad_h;
-    (void)stream;
-    return SPH_E_UNSUPPORTED;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f32c = params->precision == SPH_FP32C;
+    // the adjoint walks 64-particle tiles
+    pl.prm.segment = 64;
+    hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
+    if (e == hipSuccess) e = run_permute(pl, group_offsets, x, y, z, m, h, f32c, st);
+    if (e == hipSuccess) {
+        if (!pl.grouped) e = run_dense_table(pl, st);
+        else e = run_group_items(pl, group_offsets, st);
+    }
+    if (e == hipSuccess)
+        e = run_backward(pl, group_offsets, h, grad_rho, grad_h, grad_x, grad_y, grad_z, grad_m,
+                         st);
+    if (e != hipSuccess) return hip_fail(e);
+    return SPH_OK;
 }
 
 const char *sph_status_string(int code) {

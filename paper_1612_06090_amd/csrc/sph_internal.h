@@ -54,8 +54,9 @@ struct Plan {
     int32_t *gorder = nullptr;   // groups in processing order (G)
     int32_t *ctrl = nullptr;     // [0] work queue head, [1..] reserved
     uint64_t *stats = nullptr;   // 4 x uint64 device counters
-    double *lam = nullptr;       // adjoint multipliers (n)
-    double *acc = nullptr;       // adjoint per-particle extras (n x 2)
+    double *adj = nullptr;       // adjoint, sorted order: alpha, beta, gamma, grad_rho, grad_h (5 x n)
+    float *rmq = nullptr;        // adjoint: range-max table of h (grid units), rmq_levels x n
+    int rmq_levels = 0;
     // after sorting
     uint64_t *skeys = nullptr;
     int32_t *perm = nullptr;

@@ -61,3 +61,17 @@ def rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def gpu_backward(ps, h, grad_rho, grad_h=None, io="float64", **kw):
+    """sph_density_backward at the given h; returns numpy gx, gy, gz, gm."""
+    import torch
+    p = params_for(ps, io_dtype=sph.F32 if io == "float32" else sph.F64, **kw)
+    d = dev_arrays(ps, io)
+    dt = d["x"].dtype
+    ht = torch.tensor(np.asarray(h), dtype=dt, device="cuda")
+    gr = torch.tensor(np.asarray(grad_rho), dtype=dt, device="cuda")
+    gh = None if grad_h is None else torch.tensor(np.asarray(grad_h), dtype=dt, device="cuda")
+    o = sph.density_backward(d["x"], d["y"], d["z"], d["m"], ht, gr, gh, p, d["goff"])
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in o.items()}
