@@ -94,6 +94,70 @@ def run_form(sph, torch, d, ps, precision, steps, warmup, ev):
                 flagged=int(((status >> 16) != 0).sum()))
 
 
+# adjoint: per in-range pair, 20 FLOP in the coefficient pass (sqrt, q, f, f',
+# three sums) and 40 in the gradient pass (both sides of the pair: f' or f,
+# c_ij, c/r and three products each)
+FLOP_ADJ_PAIR = 60.0
+SORT_BYTES_PER_PARTICLE = 300.0   # keys 36, 8 radix passes 192, histograms 8, permute 64
+
+
+def run_adjoint(sph, torch, d, ps, steps, warmup, ev):
+    """FP32C root-mode solve, then the adjoint under a Gaussian cotangent on rho."""
+    p = sph.default_params(periodic=1, box=ps.box, n_target=ps.n_target, n_tol=ps.n_tol,
+                           precision=sph.FP32C, mode=sph.ROOT, root_tol=1e-6)
+    n = ps.n
+    ws = sph.workspace(p, n, 0, d["x"].device)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fw = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws)
+    torch.cuda.synchronize()
+    fwd_ms = 1e3 * (time.perf_counter() - t0)
+    h = fw["h"]
+    import sphgen
+    gr = torch.tensor(sphgen.cotangent(n, 5), dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        sph.density_backward(d["x"], d["y"], d["z"], d["m"], h, gr, None, p, ws=ws)
+    torch.cuda.synchronize()
+    pairs_ev = [(ev.create(), ev.create()) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        p.prof_events[0] = pairs_ev[k][0]
+        p.prof_events[1] = pairs_ev[k][1]
+        sph.density_backward(d["x"], d["y"], d["z"], d["m"], h, gr, None, p, ws=ws)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    kern = float(np.mean([ev.elapsed_ms(a, b) for a, b in pairs_ev]))
+    for a, b in pairs_ev:
+        ev.hip.hipEventDestroy(a)
+        ev.hip.hipEventDestroy(b)
+    pairs = int(fw["nngb"].to(torch.int64).sum().item())
+    flop = FLOP_ADJ_PAIR * pairs
+    ach = flop / (kern * 1e-3)
+    flagged = int(((fw["status"] >> 16) != 0).sum().item())
+    return {"workload": "clustered2^20, FP32C root-mode solve (root_tol 1e-6), then the adjoint "
+                        "with grad_rho ~ N(0,1) (seed 5)",
+            "forward_ms": fwd_ms, "ms_per_call": 1e3 * wall, "kernel_ms": kern,
+            "pairs": pairs, "forward_flagged": flagged,
+            "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32 / 1e12,
+                         "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
+                         "kernel": "k_adjoint (both passes)", "flop_per_launch": flop}}
+
+
+def run_sort(sph, torch, d, ps, steps):
+    """Keys, radix sort, permutation and the cell table alone (sph_sort)."""
+    p = sph.default_params(periodic=1, box=ps.box)
+    sph.sort(d["x"], d["y"], d["z"], p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sph.sort(d["x"], d["y"], d["z"], p)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    gbs = SORT_BYTES_PER_PARTICLE * ps.n / (ms * 1e-3) / 1e9
+    return {"ms_per_call": ms, "bytes_per_particle": SORT_BYTES_PER_PARTICLE,
+            "achieved_GBps": gbs, "peak_GBps": 8000.0, "frac": gbs / 8000.0}
+
+
 def cpu_baseline(ps, budget_s=15.0):
     """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
     import oracle
@@ -205,6 +269,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
@@ -240,6 +305,13 @@ def main():
     if not args.no_fp64:
         f64 = run_form(sph, torch, d, ps, sph.FP64, max(3, args.steps // 2), 1, ev)
         print(f"[bench] fp64 {f64}", file=sys.stderr, flush=True)
+
+    srt = run_sort(sph, torch, d, ps, max(3, args.steps))
+    print(f"[bench] sort {srt}", file=sys.stderr, flush=True)
+    adj = None
+    if not args.no_adjoint:
+        adj = run_adjoint(sph, torch, d, ps, max(3, args.steps // 2), 1, ev)
+        print(f"[bench] adjoint {adj}", file=sys.stderr, flush=True)
 
     def roof(r, form):
         flop = FLOP_CAND * r["cands"] + FLOP_PAIR[form] * r["pairs"]
@@ -284,6 +356,9 @@ def main():
             "roofline": roof(f64, "fp64"),
         }
         line["fp32c_speedup_over_fp64"] = f64["ms_per_step"] / f32["ms_per_step"]
+    line["sort"] = srt
+    if adj is not None:
+        line["adjoint"] = adj
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(ps)
     print(json.dumps(line), flush=True)

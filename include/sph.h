@@ -104,7 +104,9 @@ typedef struct {
                                its candidate stream; results do not depend on it beyond
                                summation order */
     void    *prof_events[2];/* optional hipEvent_t pair recorded on `stream` immediately
-                               before and after the density kernel (NULL: none) */
+                               before and after the density kernel (sph_density_solve)
+                               or the two adjoint kernels (sph_density_backward);
+                               NULL: none */
     int32_t  reserved[8];   /* must be zero */
 } sph_params;
 

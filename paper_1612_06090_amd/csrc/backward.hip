@@ -14,16 +14,26 @@
 // (r < h_k) and its reverse neighbours (particles i whose own sphere reaches
 // it, r < h_i, h_i != h_k).  The reverse set is found by a walk over the
 // implicit octree of the Morton-sorted array: a node (key prefix = a
-// contiguous range) is opened only if it comes within max(h_tile, h_max(node))
-// of the tile, with h_max of any range read in O(1) from a range-max table.
-// Every candidate is visited once and tested against both radii.
+// contiguous range) is opened only if it comes within max(h_k, h_max(node))
+// of some particle k of the tile, with h_max of any range read in O(1) from a
+// range-max table.  Every candidate is visited once and tested against both
+// radii.
+//
+// A wave holds a tile of 16 consecutive sorted particles, each on 4 lanes
+// that split every 64-candidate chunk between them (partial sums are folded
+// across the 4 copies at the end).  The next chunk's candidates are loaded
+// while the current one is evaluated.
 #include "sph_internal.h"
 
 namespace sph {
 
-constexpr int kLeafMax = 32;   // a walk node with at most this many particles is a leaf
-constexpr int kWorkCap = 384;  // walk stack capacity (overflowing nodes become leaves)
-constexpr float kSplitExtent = 4.0f;  // split lane ranges wider than this many radii
+constexpr int kLeafMax = 16;   // a walk node with at most this many particles is a leaf
+constexpr int kWorkCap = 256;  // walk stack capacity (overflowing nodes become leaves)
+constexpr float kSplitExtent = 4.0f;  // split particle ranges wider than this many radii
+constexpr int kAdjP = kAdjTile;       // particles per wave tile
+constexpr int kAdjS = 64 / kAdjP;     // lanes per particle
+constexpr int kAdjWavesPerCU = 16;    // persistent waves per compute unit
+static_assert(kAdjP * kAdjS == 64, "tile shape");
 
 struct AdjArgs {
     int64_t n;
@@ -91,29 +101,30 @@ template <int PREC>
 struct AdjLDS {
     int32_t wk_st[kWorkCap], wk_en[kWorkCap], wk_c[kWorkCap][3], wk_L[kWorkCap];
     int32_t rg_start[64], rg_excl[64], rg_code[64];
+    float sp[4][kAdjP];   // the tile's spheres: x, y, z (grid units, range origin), radius
     AdjCand<PREC> cand[64];
 };
 
-// M4 spline f(q) and f'(q) for 0 <= q <= 1 (0 beyond)
+// M4 spline f(q) and f'(q) for 0 <= q <= 1, without branches (callers clamp q
+// to 1, where both vanish, or discard the result out of range)
 template <typename T>
 __device__ inline void spline_fd(T q, T &f, T &fp) {
     const T u = T(1) - q;
-    if (q <= T(0.5)) {
-        f = T(1) + q * q * (T(6) * q - T(6));
-        fp = q * (T(18) * q - T(12));
-    } else if (q < T(1)) {
-        f = T(2) * u * u * u;
-        fp = T(-6) * u * u;
-    } else {
-        f = T(0);
-        fp = T(0);
-    }
+    const T u2 = u * u;
+    const bool inner = q <= T(0.5);
+    const T fin = T(1) + q * q * (T(6) * q - T(6));
+    const T gin = q * (T(18) * q - T(12));
+    f = inner ? fin : T(2) * u2 * u;
+    fp = inner ? gin : T(-6) * u2;
 }
 
 template <int PREC, bool GROUPED>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
     __shared__ AdjLDS<PREC> S;
     const int l = threadIdx.x;
+    const int p = l & (kAdjP - 1);  // particle slot of this lane
+    const int kk = l / kAdjP;       // copy: this lane's share of each chunk
+    constexpr uint64_t kTileMask = (1ull << kAdjP) - 1ull;
     const int B = a.bits;
 
     for (;;) {
@@ -127,8 +138,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
         int32_t g = 0;
         double org0 = 0.0, org1 = 0.0, org2 = 0.0, sc;
         if (!GROUPED) {
-            b = (int64_t)item * 64;
-            e = b + 64 < a.n ? b + 64 : a.n;
+            b = (int64_t)item * kAdjP;
+            e = b + kAdjP < a.n ? b + kAdjP : a.n;
             sc = 2097152.0 / a.box;
         } else {
             int32_t lo = 0, hi = a.G - 1;
@@ -137,13 +148,13 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 if (a.gitems[mid] <= item) lo = mid; else hi = mid - 1;
             }
             g = lo;
-            b = a.goff[g] + (int64_t)(item - a.gitems[g]) * 64;
-            e = b + 64 < a.goff[g + 1] ? b + 64 : a.goff[g + 1];
+            b = a.goff[g] + (int64_t)(item - a.gitems[g]) * kAdjP;
+            e = b + kAdjP < a.goff[g + 1] ? b + kAdjP : a.goff[g + 1];
             const double *f = a.frame + 8 * (int64_t)g;
             org0 = f[0]; org1 = f[1]; org2 = f[2];
             sc = f[6];
         }
-        const int64_t s = b + l;
+        const int64_t s = b + p;
         const bool mine = s < e;
         double xk = 0.0, yk = 0.0, zk = 0.0, mk = 0.0, hk = 1.0;
         int32_t qxk = 0, qyk = 0, qzk = 0;
@@ -168,12 +179,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 valid = !isnan(fxk);
             }
         }
-        const uint64_t vm = __ballot(valid);
+        const uint64_t vm = __ballot(valid) & kTileMask;
         double ak = 0.0, bk = 0.0;  // own alpha, beta (phase 2)
         if (a.phase == 2 && valid) { ak = a.alpha[s]; bk = a.beta[s]; }
-        const float akf = (float)ak, bkf = (float)bk;
+        const float akf = (float)ak, bkf = (float)bk, mkf = (float)mk;
 
-        // per-lane accumulators: phase 1 -> S1, R, T ; phase 2 -> gx, gy, gz, gm
+        // per-lane partial sums: phase 1 -> S1, R, T ; phase 2 -> gx, gy, gz, gm
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
 
         const double hq = hk * sc;  // own h in grid units
@@ -181,20 +192,25 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
         const float hk2f = (float)(hq * hq);
         const float hkinvf = (float)(1.0 / hq);
         const double hk2 = hk * hk, hkinv = 1.0 / hk;
+        const int64_t gbase = GROUPED ? a.goff[g] : 0;
+        const int64_t gend = GROUPED ? a.goff[g + 1] : a.n;
+        float hall = 0.f;  // largest h of the set (phase 2: any sphere may reach)
+        if (a.phase == 2 && vm != 0) hall = range_hmax(a, (int32_t)gbase, (int32_t)gend);
 
-        // Lane ranges of the tile, each walked on its own.  A tile whose
+        // Particle ranges of the tile, each walked on its own.  A range whose
         // bounding box is wide compared with its radius (it straddles distant
-        // parts of the Morton order) is split in halves of its valid lanes:
-        // the walk region stays compact and the binary32 coordinates relative
-        // to the range's origin keep the precision of the local separation.
-        int rs_a[7], rs_b[7];
+        // parts of the Morton order) is split in halves of its valid
+        // particles: the walk region stays compact and the binary32
+        // coordinates relative to the range's origin keep the precision of the
+        // local separation.
+        int rs_a[5], rs_b[5];
         int rsp = 0;
-        if (vm != 0) { rs_a[0] = 0; rs_b[0] = 64; rsp = 1; }
+        if (vm != 0) { rs_a[0] = 0; rs_b[0] = kAdjP; rsp = 1; }
         while (rsp > 0) {
             --rsp;
             const int la = rs_a[rsp], lb = rs_b[rsp];
-            const bool in_sub = valid && l >= la && l < lb;
-            const uint64_t sm = __ballot(in_sub);
+            const bool in_sub = valid && p >= la && p < lb;
+            const uint64_t sm = __ballot(in_sub) & kTileMask;
             if (sm == 0) continue;
             const int first = __ffsll((unsigned long long)sm) - 1;
             const int32_t t0 = readlane_i(qxk, first), t1 = readlane_i(qyk, first),
@@ -208,7 +224,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
             const float Ht = wave_max(in_sub ? Hk : 0.f);
             const float ext = fmaxf(mx0 - mn0, fmaxf(mx1 - mn1, mx2 - mn2));
             if (ext > kSplitExtent * Ht && __popcll(sm) > 1) {
-                // lower half of the valid lanes, then the upper half
+                // lower half of the valid particles, then the upper half
                 uint64_t t = sm;
                 for (int k = __popcll(sm) / 2; k > 0; --k) t &= t - 1;
                 const int mid = __ffsll((unsigned long long)t) - 1;
@@ -216,194 +232,191 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 rs_a[rsp] = la; rs_b[rsp] = mid; ++rsp;
                 continue;
             }
+            __syncthreads();
+            if (kk == 0) {
+                S.sp[0][p] = pk0;
+                S.sp[1][p] = pk1;
+                S.sp[2][p] = pk2;
+                S.sp[3][p] = Hk;
+            }
+            __syncthreads();
 
-            // ---- walk set-up: root nodes
             int wsz = 0;   // work stack size (uniform)
             int nl = 0;    // leaves collected (uniform)
-            const int64_t gbase = GROUPED ? a.goff[g] : 0;
-            const int64_t gend = GROUPED ? a.goff[g + 1] : a.n;
-            // tile region half-width for the roots: own h, and for phase 2 the
-            // largest h of the set (any sphere may reach the tile)
-            float Rroot = Ht;
-            if (a.phase == 2) {
-                const float hall = range_hmax(a, (int32_t)gbase, (int32_t)gend);
-                Rroot = hall > Rroot ? hall : Rroot;
-            }
+            float Rroot = a.phase == 2 && hall > Ht ? hall : Ht;
             Rroot = Rroot * (1.0f + 0x1p-12f) + 1.0f;
 
-            // streaming of the collected leaves (ranges) through LDS
+            // one candidate of the leaf list (flat index gidx) into registers
+            auto load_cand = [&](int gidx, int total, int nleaf, AdjCand<PREC> &c) {
+                if (gidx < total) {
+                    int lo = 0, hi = nleaf - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (S.rg_excl[mid] <= gidx) lo = mid; else hi = mid - 1;
+                    }
+                    const int64_t j = (int64_t)S.rg_start[lo] + (gidx - S.rg_excl[lo]);
+                    const int cc = S.rg_code[lo];
+                    const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1, sh2 = ((cc >> 4) & 3) - 1;
+                    const double hj = a.sh[j];
+                    const double aj = a.phase == 2 ? a.alpha[j] : 0.0;
+                    const double bj = a.phase == 2 ? a.beta[j] : 0.0;
+                    const double gj = a.phase == 2 ? a.gamma[j] : 0.0;
+                    if constexpr (PREC == SPH_FP64) {
+                        c.p = make_double4(a.sx[j], a.sy[j], a.sz[j], a.sm[j]);
+                        c.s = make_double4((double)sh0 * a.box, (double)sh1 * a.box,
+                                           (double)sh2 * a.box, 0.0);
+                        c.h = make_double4(hj, 1.0 / hj, aj, bj);
+                        c.g = gj;
+                    } else {
+                        const int32_t W = 1 << B;
+                        const double hqj = hj * sc;
+                        c.p = make_float4((float)(a.qx[j] + sh0 * W - t0) + a.fx[j],
+                                          (float)(a.qy[j] + sh1 * W - t1) + a.fy[j],
+                                          (float)(a.qz[j] + sh2 * W - t2) + a.fz[j], a.fm[j]);
+                        c.h = make_float4((float)hqj, (float)(1.0 / hqj), (float)aj, (float)bj);
+                        c.g = (float)gj;
+                    }
+                } else {
+                    if constexpr (PREC == SPH_FP64) {
+                        c.p = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
+                        c.s = make_double4(0.0, 0.0, 0.0, 0.0);
+                        c.h = make_double4(1.0, 1.0, 0.0, 0.0);
+                        c.g = 0.0;
+                    } else {
+                        c.p = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+                        c.h = make_float4(1.f, 1.f, 0.f, 0.f);
+                        c.g = 0.f;
+                    }
+                }
+            };
+
+            // the pair terms of one LDS chunk for this lane's share of it
+            auto eval_chunk = [&](int mc) {
+                const int nu = (mc + kAdjS - 1) / kAdjS;
+                if constexpr (PREC == SPH_FP64) {
+                    for (int u = 0; u < nu; ++u) {
+                        const AdjCand<SPH_FP64> c = S.cand[u * kAdjS + kk];
+                        const double dx = (c.p.x - xk) + c.s.x;
+                        const double dy = (c.p.y - yk) + c.s.y;
+                        const double dz = (c.p.z - zk) + c.s.z;
+                        const double r2 = (dx * dx + dy * dy) + dz * dz;
+                        const bool in1 = r2 < hk2;
+                        if (a.phase == 1) {
+                            if (in1) {
+                                const double q = sqrt(r2) * hkinv;
+                                double f, fp;
+                                spline_fd<double>(q, f, fp);
+                                acc0 += q * fp;
+                                acc1 += c.p.w * f;
+                                acc2 += c.p.w * q * fp;
+                            }
+                        } else {
+                            const bool in2 = r2 < c.h.x * c.h.x;
+                            if (in1 || in2) {
+                                const double r = sqrt(r2);
+                                double f1, fp1, f2, fp2;
+                                spline_fd<double>(fmin(r * hkinv, 1.0), f1, fp1);
+                                spline_fd<double>(fmin(r * c.h.y, 1.0), f2, fp2);
+                                const double c1 = in1 ? fp1 * (ak * c.p.w + bk) : 0.0;
+                                const double c2 = in2 ? fp2 * (c.h.z * mk + c.h.w) : 0.0;
+                                acc3 += in2 ? c.g * f2 : 0.0;
+                                const double w = r > 0.0 ? (c1 + c2) / r : 0.0;
+                                acc0 -= w * dx;
+                                acc1 -= w * dy;
+                                acc2 -= w * dz;
+                            }
+                        }
+                    }
+                } else {
+                    // chunk partial sums in binary32, folded into binary64
+                    float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+                    for (int u = 0; u < nu; ++u) {
+                        const AdjCand<SPH_FP32C> c = S.cand[u * kAdjS + kk];
+                        const float dx = c.p.x - pk0;
+                        const float dy = c.p.y - pk1;
+                        const float dz = c.p.z - pk2;
+                        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                        const bool in1 = r2 < hk2f;
+                        if (a.phase == 1) {
+                            if (in1) {
+                                const float q = fminf(__builtin_amdgcn_sqrtf(r2) * hkinvf, 1.0f);
+                                float f, fp;
+                                spline_fd<float>(q, f, fp);
+                                const float qfp = q * fp;
+                                s0 += qfp;
+                                s1 = __builtin_fmaf(c.p.w, f, s1);
+                                s2 = __builtin_fmaf(c.p.w, qfp, s2);
+                            }
+                        } else {
+                            const bool in2 = r2 < c.h.x * c.h.x;
+                            if (in1 || in2) {
+                                const float r = __builtin_amdgcn_sqrtf(r2);
+                                const float rinv = r > 0.f ? __builtin_amdgcn_rcpf(r) : 0.f;
+                                float f1, fp1, f2, fp2;
+                                spline_fd<float>(fminf(r * hkinvf, 1.0f), f1, fp1);
+                                spline_fd<float>(fminf(r * c.h.y, 1.0f), f2, fp2);
+                                const float c1 = in1 ? fp1 * __builtin_fmaf(akf, c.p.w, bkf) : 0.f;
+                                const float c2 = in2 ? fp2 * __builtin_fmaf(c.h.z, mkf, c.h.w) : 0.f;
+                                s3 = __builtin_fmaf(in2 ? c.g : 0.f, f2, s3);
+                                const float w = (c1 + c2) * rinv;
+                                s0 = __builtin_fmaf(-w, dx, s0);
+                                s1 = __builtin_fmaf(-w, dy, s1);
+                                s2 = __builtin_fmaf(-w, dz, s2);
+                            }
+                        }
+                    }
+                    acc0 += (double)s0;
+                    acc1 += (double)s1;
+                    acc2 += (double)s2;
+                    acc3 += (double)s3;
+                }
+            };
+
+            // stream the collected leaves (ranges) through LDS, one chunk of 64
+            // candidates ahead in registers
             auto stream_leaves = [&](int nleaf) {
-                // prefix sums of leaf sizes (leaf list holds start and count)
                 const int cnt = l < nleaf ? S.rg_excl[l] : 0;  // rg_excl holds counts here
                 const int incl = wave_incl_scan(cnt);
                 const int total = __builtin_amdgcn_readlane(incl, 63);
                 __syncthreads();
                 if (l < nleaf) S.rg_excl[l] = incl - cnt;
                 __syncthreads();
+                AdjCand<PREC> nxt;
+                load_cand(l, total, nleaf, nxt);
                 for (int cbase = 0; cbase < total; cbase += 64) {
-                    const int gidx = cbase + l;
                     __syncthreads();
-                    if (gidx < total) {
-                        int lo = 0, hi = nleaf - 1;
-                        while (lo < hi) {
-                            const int mid = (lo + hi + 1) >> 1;
-                            if (S.rg_excl[mid] <= gidx) lo = mid; else hi = mid - 1;
-                        }
-                        const int64_t j = (int64_t)S.rg_start[lo] + (gidx - S.rg_excl[lo]);
-                        const int cc = S.rg_code[lo];
-                        const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1, sh2 = ((cc >> 4) & 3) - 1;
-                        const double hj = a.sh[j];
-                        const double aj = a.phase == 2 ? a.alpha[j] : 0.0;
-                        const double bj = a.phase == 2 ? a.beta[j] : 0.0;
-                        const double gj = a.phase == 2 ? a.gamma[j] : 0.0;
-                        if constexpr (PREC == SPH_FP64) {
-                            S.cand[l].p = make_double4(a.sx[j], a.sy[j], a.sz[j], a.sm[j]);
-                            S.cand[l].s = make_double4((double)sh0 * a.box, (double)sh1 * a.box,
-                                                       (double)sh2 * a.box, 0.0);
-                            S.cand[l].h = make_double4(hj, 1.0 / hj, aj, bj);
-                            S.cand[l].g = gj;
-                        } else {
-                            const int32_t W = 1 << B;
-                            double scj = sc;
-                            const double hqj = hj * scj;
-                            S.cand[l].p = make_float4((float)(a.qx[j] + sh0 * W - t0) + a.fx[j],
-                                                      (float)(a.qy[j] + sh1 * W - t1) + a.fy[j],
-                                                      (float)(a.qz[j] + sh2 * W - t2) + a.fz[j],
-                                                      a.fm[j]);
-                            S.cand[l].h = make_float4((float)hqj, (float)(1.0 / hqj), (float)aj,
-                                                      (float)bj);
-                            S.cand[l].g = (float)gj;
-                        }
-                    } else {
-                        if constexpr (PREC == SPH_FP64) {
-                            S.cand[l].p = make_double4(INFINITY, INFINITY, INFINITY, 0.0);
-                            S.cand[l].s = make_double4(0.0, 0.0, 0.0, 0.0);
-                            S.cand[l].h = make_double4(1.0, 1.0, 0.0, 0.0);
-                            S.cand[l].g = 0.0;
-                        } else {
-                            S.cand[l].p = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
-                            S.cand[l].h = make_float4(1.f, 1.f, 0.f, 0.f);
-                            S.cand[l].g = 0.f;
-                        }
-                    }
+                    S.cand[l] = nxt;
                     __syncthreads();
+                    if (cbase + 64 < total) load_cand(cbase + 64 + l, total, nleaf, nxt);
                     const int mc = total - cbase < 64 ? total - cbase : 64;
-                    if (in_sub) {
-                        if constexpr (PREC == SPH_FP64) {
-                            for (int t = 0; t < mc; ++t) {
-                                const AdjCand<SPH_FP64> c = S.cand[t];
-                                const double dx = (c.p.x - xk) + c.s.x;
-                                const double dy = (c.p.y - yk) + c.s.y;
-                                const double dz = (c.p.z - zk) + c.s.z;
-                                const double r2 = (dx * dx + dy * dy) + dz * dz;
-                                const bool in1 = r2 < hk2;
-                                if (a.phase == 1) {
-                                    if (in1) {
-                                        const double q = sqrt(r2) * hkinv;
-                                        double f, fp;
-                                        spline_fd<double>(q, f, fp);
-                                        acc0 += q * fp;
-                                        acc1 += c.p.w * f;
-                                        acc2 += c.p.w * q * fp;
-                                    }
-                                } else {
-                                    const bool in2 = r2 < c.h.x * c.h.x;
-                                    if (in1 || in2) {
-                                        const double r = sqrt(r2);
-                                        double cc = 0.0;
-                                        if (in1) {
-                                            double f, fp;
-                                            spline_fd<double>(r * hkinv, f, fp);
-                                            cc += fp * (ak * c.p.w + bk);
-                                        }
-                                        if (in2) {
-                                            double f, fp;
-                                            spline_fd<double>(r * c.h.y, f, fp);
-                                            cc += fp * (c.h.z * mk + c.h.w);
-                                            acc3 += c.g * f;
-                                        }
-                                        if (r > 0.0) {
-                                            const double w = cc / r;
-                                            acc0 -= w * dx;
-                                            acc1 -= w * dy;
-                                            acc2 -= w * dz;
-                                        }
-                                    }
-                                }
-                            }
-                        } else {
-                            // chunk partial sums in binary32, folded into binary64
-                            float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-                            for (int t = 0; t < mc; ++t) {
-                                const AdjCand<SPH_FP32C> c = S.cand[t];
-                                const float dx = c.p.x - pk0;
-                                const float dy = c.p.y - pk1;
-                                const float dz = c.p.z - pk2;
-                                const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                                const bool in1 = r2 < hk2f;
-                                if (a.phase == 1) {
-                                    if (in1) {
-                                        const float q = fminf(__builtin_amdgcn_sqrtf(r2) * hkinvf, 1.0f);
-                                        float f, fp;
-                                        spline_fd<float>(q, f, fp);
-                                        s0 += q * fp;
-                                        s1 = __builtin_fmaf(c.p.w, f, s1);
-                                        s2 = __builtin_fmaf(c.p.w * q, fp, s2);
-                                    }
-                                } else {
-                                    const bool in2 = r2 < c.h.x * c.h.x;
-                                    if (in1 || in2) {
-                                        const float r = __builtin_amdgcn_sqrtf(r2);
-                                        float cc = 0.f;
-                                        if (in1) {
-                                            float f, fp;
-                                            spline_fd<float>(fminf(r * hkinvf, 1.0f), f, fp);
-                                            cc = fp * __builtin_fmaf(akf, c.p.w, bkf);
-                                        }
-                                        if (in2) {
-                                            float f, fp;
-                                            spline_fd<float>(fminf(r * c.h.y, 1.0f), f, fp);
-                                            cc = __builtin_fmaf(fp, __builtin_fmaf(c.h.z, (float)mk, c.h.w), cc);
-                                            s3 = __builtin_fmaf(c.g, f, s3);
-                                        }
-                                        if (r > 0.f) {
-                                            const float w = cc / r;
-                                            s0 -= w * dx;
-                                            s1 -= w * dy;
-                                            s2 -= w * dz;
-                                        }
-                                    }
-                                }
-                            }
-                            acc0 += (double)s0;
-                            acc1 += (double)s1;
-                            acc2 += (double)s2;
-                            acc3 += (double)s3;
-                        }
-                    }
+                    if (in_sub) eval_chunk(mc);
                 }
             };
 
-            // node test: does node box (grid units, relative to t) come within
-            // the tile's radius (phase 1) or max(tile radius, node h_max) (phase 2)?
+            // node test: does the node box (grid units, relative to the range
+            // origin) come within the radius of some sphere of the range -- its
+            // own h (phase 1), or max(h, the node's largest h) (phase 2)?
             auto node_pass = [&](int64_t c0, int64_t c1, int64_t c2, int L, int32_t st, int32_t en) {
                 const int ex = B - L;
                 const int64_t sd = (int64_t)1 << ex;
                 const float side = (float)sd;
                 const float lo0 = (float)(c0 * sd - t0), lo1 = (float)(c1 * sd - t1),
                             lo2 = (float)(c2 * sd - t2);
-                const float g0 = fmaxf(0.f, fmaxf(lo0 - mx0, mn0 - (lo0 + side)));
-                const float g1 = fmaxf(0.f, fmaxf(lo1 - mx1, mn1 - (lo1 + side)));
-                const float g2 = fmaxf(0.f, fmaxf(lo2 - mx2, mn2 - (lo2 + side)));
-                float R = Ht;
-                if (a.phase == 2) {
-                    const float hm = range_hmax(a, st, en);
-                    R = hm > R ? hm : R;
-                }
+                const float hm = a.phase == 2 ? range_hmax(a, st, en) : 0.f;
                 // slack covers the binary32 rounding of tile coordinates (up to
                 // 2^-3 grid units at 2^21) and of the node corners
-                R = R * (1.0f + 0x1p-12f) + side * 0x1p-12f + 1.0f;
-                return g0 * g0 + g1 * g1 + g2 * g2 <= R * R;
+                const float slack = side * 0x1p-12f + 1.0f;
+                bool pass = false;
+                for (uint64_t it = sm; it; it &= it - 1) {
+                    const int i = __ffsll((unsigned long long)it) - 1;
+                    const float x = S.sp[0][i], y = S.sp[1][i], z = S.sp[2][i];
+                    const float H = fmaxf(S.sp[3][i], hm) * (1.0f + 0x1p-12f) + slack;
+                    const float g0 = fmaxf(0.f, fmaxf(lo0 - x, x - (lo0 + side)));
+                    const float g1 = fmaxf(0.f, fmaxf(lo1 - y, y - (lo1 + side)));
+                    const float g2 = fmaxf(0.f, fmaxf(lo2 - z, z - (lo2 + side)));
+                    pass = pass || (g0 * g0 + g1 * g1 + g2 * g2 <= H * H);
+                }
+                return pass;
             };
 
             // append passing nodes of this round: leaves to the leaf list, the rest
@@ -450,10 +463,67 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 nl += nlf;
             };
 
-            // roots: periodic -- every level-1 cell image meeting the region
-            // (tile box +- Rroot); groups -- the group itself (level 0)
+            // expand the work stack: pop up to 8 nodes, one lane per child
+            auto expand_all = [&]() {
+                while (wsz > 0) {
+                    const int n8 = wsz < 8 ? wsz : 8;
+                    const int base = wsz - n8;
+                    const int nd = l >> 3, ch = l & 7;
+                    bool pass = false, leaf = false;
+                    int32_t st = 0, en = 0, pen = 0;
+                    int64_t c0 = 0, c1 = 0, c2 = 0;
+                    int L = 0;
+                    if (nd < n8) {
+                        const int k = base + nd;
+                        const int32_t pst = S.wk_st[k];
+                        pen = S.wk_en[k];
+                        const int pL = S.wk_L[k];
+                        const int64_t p0 = S.wk_c[k][0], p1 = S.wk_c[k][1], p2 = S.wk_c[k][2];
+                        L = pL + 1;
+                        c0 = 2 * p0 + ((ch >> 2) & 1);
+                        c1 = 2 * p1 + ((ch >> 1) & 1);
+                        c2 = 2 * p2 + (ch & 1);
+                        // key range of the child: its Morton prefix (wrapped) at level L
+                        const int64_t m = ((int64_t)1 << L) - 1;
+                        const uint64_t cm = morton3((uint64_t)(c0 & m), (uint64_t)(c1 & m),
+                                                    (uint64_t)(c2 & m));
+                        if (!GROUPED && L <= a.Ld) {
+                            const int sh = 3 * (a.Ld - L);
+                            st = a.table[cm << sh];
+                            en = a.table[(cm + 1) << sh];
+                        } else {
+                            const int ks = 3 * (B - L);
+                            const uint64_t gb = GROUPED ? ((uint64_t)(uint32_t)g << 48) : 0ull;
+                            st = lower_bound_key(a.skeys, pst, pen, gb + (cm << ks));
+                        }
+                    }
+                    if (GROUPED || a.Ld < B) {
+                        // searched children end where the next sibling starts
+                        const int32_t nst = __shfl_down(st, 1, 64);
+                        if (nd < n8 && (GROUPED || L > a.Ld)) en = ch == 7 ? pen : nst;
+                    }
+                    if (nd < n8) {
+                        pass = en > st && node_pass(c0, c1, c2, L, st, en);
+                        leaf = en - st <= kLeafMax || L >= B;
+                    }
+                    __syncthreads();
+                    wsz = base;
+                    place(pass, leaf, st, en, c0, c1, c2, L);
+                }
+            };
+
+            // roots: periodic -- the cell images at level Lr meeting the region
+            // (range box +- Rroot), Lr the finest level (at most that of the
+            // dense table) whose cells cover the region's width in 6; groups --
+            // the group itself (level 0).  Each batch of 64 roots is walked in turn.
             if (!GROUPED) {
-                const int ex = B - 1;
+                const float wdt = fmaxf(mx0 - mn0, fmaxf(mx1 - mn1, mx2 - mn2)) + 2.0f * Rroot;
+                int ex = 0;
+                while (ex < B - 1 && 6.0f * (float)(1 << ex) < wdt) ++ex;
+                int Lr = B - ex;
+                if (Lr > a.Ld) Lr = a.Ld;
+                if (Lr < 1) Lr = 1;
+                ex = B - Lr;
                 const int64_t lo0 = ((int64_t)t0 + (int64_t)floorf(mn0 - Rroot) - 1) >> ex;
                 const int64_t lo1 = ((int64_t)t1 + (int64_t)floorf(mn1 - Rroot) - 1) >> ex;
                 const int64_t lo2 = ((int64_t)t2 + (int64_t)floorf(mn2 - Rroot) - 1) >> ex;
@@ -461,7 +531,9 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 const int64_t hi1 = ((int64_t)t1 + (int64_t)floorf(mx1 + Rroot) + 1) >> ex;
                 const int64_t hi2 = ((int64_t)t2 + (int64_t)floorf(mx2 + Rroot) + 1) >> ex;
                 const int64_t nx = hi0 - lo0 + 1, ny = hi1 - lo1 + 1, nz = hi2 - lo2 + 1;
-                const int64_t nroot = nx * ny * nz;  // <= 6^3: region within [-1, 2) boxes
+                const int64_t nroot = nx * ny * nz;  // at most 9^3 (6^3 at level 1)
+                const int64_t msk = ((int64_t)1 << Lr) - 1;
+                const int sh = 3 * (a.Ld - Lr);
                 for (int64_t rb = 0; rb < nroot; rb += 64) {
                     const int64_t r = rb + l;
                     bool pass = false, leaf = false;
@@ -471,15 +543,15 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                         c0 = lo0 + r % nx;
                         c1 = lo1 + (r / nx) % ny;
                         c2 = lo2 + r / (nx * ny);
-                        const uint64_t cm = morton3((uint64_t)(c0 & 1), (uint64_t)(c1 & 1),
-                                                    (uint64_t)(c2 & 1));
-                        const int sh = 3 * (a.Ld - 1);
+                        const uint64_t cm = morton3((uint64_t)(c0 & msk), (uint64_t)(c1 & msk),
+                                                    (uint64_t)(c2 & msk));
                         st = a.table[cm << sh];
                         en = a.table[(cm + 1) << sh];
-                        pass = en > st && node_pass(c0, c1, c2, 1, st, en);
-                        leaf = en - st <= kLeafMax;
+                        pass = en > st && node_pass(c0, c1, c2, Lr, st, en);
+                        leaf = en - st <= kLeafMax || Lr >= B;
                     }
-                    place(pass, leaf, st, en, c0, c1, c2, 1);
+                    place(pass, leaf, st, en, c0, c1, c2, Lr);
+                    expand_all();
                 }
             } else {
                 bool pass = false, leaf = false;
@@ -491,47 +563,22 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                     leaf = en - st <= kLeafMax;
                 }
                 place(pass, leaf, st, en, 0, 0, 0, 0);
-            }
-
-            // expand: pop up to 8 nodes, one lane per child
-            while (wsz > 0) {
-                const int n8 = wsz < 8 ? wsz : 8;
-                const int base = wsz - n8;
-                const int nd = l >> 3, ch = l & 7;
-                bool pass = false, leaf = false;
-                int32_t st = 0, en = 0;
-                int64_t c0 = 0, c1 = 0, c2 = 0;
-                int L = 0;
-                if (nd < n8) {
-                    const int k = base + nd;
-                    const int32_t pst = S.wk_st[k], pen = S.wk_en[k];
-                    const int pL = S.wk_L[k];
-                    const int64_t p0 = S.wk_c[k][0], p1 = S.wk_c[k][1], p2 = S.wk_c[k][2];
-                    L = pL + 1;
-                    c0 = 2 * p0 + ((ch >> 2) & 1);
-                    c1 = 2 * p1 + ((ch >> 1) & 1);
-                    c2 = 2 * p2 + (ch & 1);
-                    // key range of the child: its Morton prefix (wrapped) at level L
-                    const int64_t m = ((int64_t)1 << L) - 1;
-                    const uint64_t cm = morton3((uint64_t)(c0 & m), (uint64_t)(c1 & m),
-                                                (uint64_t)(c2 & m));
-                    const int ks = 3 * (B - L);
-                    const uint64_t gb = GROUPED ? ((uint64_t)(uint32_t)g << 48) : 0ull;
-                    st = lower_bound_key(a.skeys, pst, pen, gb + (cm << ks));
-                    en = ch == 7 ? pen : lower_bound_key(a.skeys, st, pen, gb + ((cm + 1) << ks));
-                    pass = en > st && node_pass(c0, c1, c2, L, st, en);
-                    leaf = en - st <= kLeafMax || L >= B;
-                }
-                __syncthreads();
-                wsz = base;
-                place(pass, leaf, st, en, c0, c1, c2, L);
+                expand_all();
             }
             if (nl > 0) stream_leaves(nl);
         }
 
-        // ---- per-particle results
+        // fold the copies' partial sums (lanes p, p + 16, p + 32, p + 48)
+        for (int o = kAdjP; o < 64; o <<= 1) {
+            acc0 += __shfl_xor(acc0, o, 64);
+            acc1 += __shfl_xor(acc1, o, 64);
+            acc2 += __shfl_xor(acc2, o, 64);
+            acc3 += __shfl_xor(acc3, o, 64);
+        }
+
+        // ---- per-particle results (copy 0 writes)
         if (a.phase == 1) {
-            if (mine) {
+            if (mine && kk == 0) {
                 double al = 0.0, be = 0.0, ga = 0.0;
                 if (valid) {
                     const double gr = a.grs[s], gh = a.ghs[s];
@@ -547,7 +594,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 a.beta[s] = be;
                 a.gamma[s] = ga;
             }
-        } else if (mine) {
+        } else if (mine && kk == 0) {
             const int64_t oi = a.perm[s];
             double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
             // the sums hold c (x_k - x_j)/r: unit vectors, the same in grid units
@@ -630,7 +677,7 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
     a.Ld = pl.Ld;
     a.frame = pl.frame;
     a.gitems = pl.gitems;
-    a.n_items = ceil_div(n, 64);
+    a.n_items = ceil_div(n, kAdjP);
     a.rmq = pl.rmq;
     a.rmq_levels = pl.rmq_levels;
     a.box = pl.prm.box;
@@ -640,9 +687,13 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
     a.out_f32 = pl.prm.io_dtype == SPH_F32;
     a.gx = gx; a.gy = gy; a.gz = gz; a.gm = gm;
     a.queue = pl.ctrl;
-    const int64_t full = (int64_t)256 * pl.prm.waves_per_cu;
+    const int64_t full = (int64_t)256 * kAdjWavesPerCU;
     const dim3 grid((unsigned)(pl.grouped ? full : (a.n_items < full ? a.n_items : full)));
     const bool f32c = pl.prm.precision == SPH_FP32C;
+    if (pl.prm.prof_events[0]) {
+        e = hipEventRecord((hipEvent_t)pl.prm.prof_events[0], st);
+        if (e != hipSuccess) return e;
+    }
     for (int phase = 1; phase <= 2; ++phase) {
         a.phase = phase;
         e = run_zero_i32(pl.ctrl, 4, st);
@@ -657,7 +708,8 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    if (pl.prm.prof_events[1]) e = hipEventRecord((hipEvent_t)pl.prm.prof_events[1], st);
+    return e;
 }
 
 }  // namespace sph

@@ -261,8 +261,8 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
     if (rc != SPH_OK) return rc;
     hipStream_t st = (hipStream_t)stream;
     const bool f32c = params->precision == SPH_FP32C;
-    // the adjoint walks 64-particle tiles
-    pl.prm.segment = 64;
+    // group work items of the adjoint are its tiles
+    pl.prm.segment = kAdjTile;
     hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
     if (e == hipSuccess) e = run_permute(pl, group_offsets, x, y, z, m, h, f32c, st);
     if (e == hipSuccess) {

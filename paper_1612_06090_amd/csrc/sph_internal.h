@@ -15,6 +15,9 @@ constexpr int kWave = 64;
 // rounds of 64 consecutive keys, so a block tile holds 4*64*ROUNDS keys.
 constexpr int kSortThreads = 256;
 
+// Particles per wave tile of the adjoint kernels.
+constexpr int kAdjTile = 16;
+
 // Scan geometry: 256 threads x 8 items per block.
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;

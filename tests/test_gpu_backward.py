@@ -5,8 +5,11 @@ cotangents on rho and, separately, on h.  FP64: every component within
 1e-11 of the largest oracle component (the sums differ only in order).
 FP32C: every component within 2e-5 of the largest, relative L2 <= 1e-5.
 Invariants that need no oracle: translation invariance (position gradients of
-each isolated set sum to zero) and degree-1 homogeneity in the masses
-(sum_k m_k dL/dm_k = sum_i grad_rho_i rho_i, h not depending on masses).
+each isolated set sum to zero), degree-1 homogeneity in the masses
+(sum_k m_k dL/dm_k = sum_i grad_rho_i rho_i, h not depending on masses),
+scaling of an isolated group (x -> s x takes h -> s h at fixed n and
+rho -> s^-3 rho, so sum_k x_k . dL/dx_k = -3 sum gr rho + sum gh h), and the
+symmetry of a cubic lattice (every position gradient vanishes).
 """
 import numpy as np
 import pytest
@@ -109,6 +112,44 @@ def test_backward_invariants(name, precision):
     rhs = float(np.dot(gr, s["rho"]))
     say(f"  homogeneity: {lhs:.15e} vs {rhs:.15e}")
     assert abs(lhs - rhs) <= tol * np.dot(np.abs(gr), s["rho"])
+
+
+@pytest.mark.parametrize("precision", [sph.FP64, sph.FP32C])
+def test_backward_group_scaling(precision):
+    ps, s, gr, gh = _setup("groups200", precision)
+    g = gpu_backward(ps, s["h"], gr, gh, precision=precision)
+    tol = 1e-11 if precision == sph.FP64 else 1e-5
+    worst = 0.0
+    for a, b in zip(ps.offsets[:-1], ps.offsets[1:]):
+        if b == a:
+            continue
+        xg = ps.x[a:b] * g["gx"][a:b] + ps.y[a:b] * g["gy"][a:b] + ps.z[a:b] * g["gz"][a:b]
+        lhs = xg.sum()
+        rhs = -3.0 * np.dot(gr[a:b], s["rho"][a:b]) + np.dot(gh[a:b], s["h"][a:b])
+        scale = (np.abs(xg).sum() + 3.0 * np.dot(np.abs(gr[a:b]), s["rho"][a:b])
+                 + np.dot(np.abs(gh[a:b]), s["h"][a:b]))
+        worst = max(worst, abs(lhs - rhs) / scale)
+    say(f"  scaling identity: worst relative residual {worst:.2e}")
+    assert worst <= tol
+
+
+@pytest.mark.parametrize("precision", [sph.FP64, sph.FP32C])
+def test_backward_lattice_symmetry(precision):
+    # 16^3 lattice, h = 2.72 spacings for every particle: each site sees the
+    # same symmetric neighbourhood, so d(sum rho)/dx = 0 and dL/dm = sum_j W
+    ps = sphgen.lattice(16, h=0.17)
+    h = np.full(ps.n, 0.17)
+    ones = np.ones(ps.n)
+    g = gpu_backward(ps, h, ones, ones, precision=precision)
+    r = gpu_backward(ps, h, sphgen.cotangent(ps.n, 81), None, precision=precision)
+    scale = np.abs(r["gx"]).max()
+    tol = 1e-12 if precision == sph.FP64 else 1e-5
+    for k in ("gx", "gy", "gz"):
+        say(f"  lattice {k}: max {np.abs(g[k]).max() / scale:.2e} of the random-cotangent scale")
+        assert np.abs(g[k]).max() <= tol * scale
+    e = oracle.eval_at_h(ps, h, search=1)
+    sumw = e["rho"] / ps.m
+    assert np.abs(g["gm"] - sumw).max() <= (1e-13 if precision == sph.FP64 else 1e-6) * sumw.max()
 
 
 def test_backward_deterministic():
