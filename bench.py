@@ -158,6 +158,57 @@ def run_sort(sph, torch, d, ps, steps):
             "achieved_GBps": gbs, "peak_GBps": 8000.0, "frac": gbs / 8000.0}
 
 
+def run_batched(sph, torch, steps, warmup):
+    """groups10k (10,000 isolated Plummer groups, sizes ~ n^-2 on [32, 131072],
+    N_t = 32 +- 1), FP32C, autotuned launch parameters, sort + solve replayed
+    from a captured HIP graph."""
+    import sphgen
+    ps = sphgen.config("groups10k")
+    n, G = ps.n, len(ps.offsets) - 1
+    d = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+         for k in ("x", "y", "z", "m", "h_init")}
+    goff = torch.tensor(ps.offsets, dtype=torch.int64, device="cuda")
+    p0 = sph.default_params(periodic=0, n_target=ps.n_target, n_tol=ps.n_tol,
+                            precision=sph.FP32C)
+    t0 = time.perf_counter()
+    p, tuned_ms = sph.autotune(d["x"], d["y"], d["z"], d["m"], d["h_init"], p0, goff)
+    tune_s = time.perf_counter() - t0
+    ws = sph.workspace(p, n, G, d["x"].device)
+    st = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, goff, stats=True,
+                           ws=ws)
+    torch.cuda.synchronize()
+    pairs = int(st["stats"][0].item())
+    cands = int(st["stats"][1].item())
+    final_pairs = int(st["nngb"].to(torch.int64).sum().item())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        for _ in range(max(1, warmup)):
+            sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, goff, ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, goff, ws=ws)
+    graph.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"workload": f"groups10k: {G} isolated Plummer groups (sizes ~ n^-2 on [32, 131072], "
+                        f"scale radii log-uniform 0.005-0.05), {n} particles, N_t = 32 +- 1, "
+                        "FP32C, autotuned, sort + solve replayed from one HIP graph",
+            "n": n, "groups": G, "ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
+            "particles_per_s": n / (ms * 1e-3), "pairs_per_step": pairs,
+            "candidates_per_step": cands, "final_pairs_per_s": final_pairs / (ms * 1e-3),
+            "tuned": {"segment": p.segment, "waves_per_cu": p.waves_per_cu,
+                      "tile_cell": p.tile_cell, "ms": tuned_ms, "tuning_s": tune_s}}
+
+
 def cpu_baseline(ps, budget_s=15.0):
     """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
     import oracle
@@ -270,6 +321,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
@@ -312,6 +364,11 @@ def main():
     if not args.no_adjoint:
         adj = run_adjoint(sph, torch, d, ps, max(3, args.steps // 2), 1, ev)
         print(f"[bench] adjoint {adj}", file=sys.stderr, flush=True)
+
+    bat = None
+    if not args.no_batched:
+        bat = run_batched(sph, torch, max(3, args.steps), args.warmup)
+        print(f"[bench] batched {bat}", file=sys.stderr, flush=True)
 
     def roof(r, form):
         flop = FLOP_CAND * r["cands"] + FLOP_PAIR[form] * r["pairs"]
@@ -357,6 +414,8 @@ def main():
         }
         line["fp32c_speedup_over_fp64"] = f64["ms_per_step"] / f32["ms_per_step"]
     line["sort"] = srt
+    if bat is not None:
+        line["batched"] = bat
     if adj is not None:
         line["adjoint"] = adj
     if not args.no_cpu_baseline:

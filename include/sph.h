@@ -146,9 +146,10 @@ int sph_sort(const sph_params *params, int64_t n, int32_t n_groups,
 
 /* Density and smoothing-length solve (Eq. 1 with the recompute loop of
  * Sec. IV-A).  Per particle, starting from h = h_init (NULL: every particle
- * starts at 2 (V/n)^(1/3), V = box^3 periodic or the group's bounding-box
- * volume), repeat: evaluate at h the sums over neighbours j (r_ij^2 < h^2,
- * minimum image when periodic, same group when isolated)
+ * starts at 2 (V/n)^(1/3), V = box^3 periodic, or the group's bounding-box
+ * volume with every extent taken at least 2^-16 of the largest extent),
+ * repeat: evaluate at h the sums over neighbours j (r_ij^2 < h^2, minimum
+ * image when periodic, same group when isolated)
  *     S0 = sum f(q), S1 = sum q f'(q), R = sum m_j f(q),   q = r_ij / h,
  * giving rho = 8R/(pi h^3), n = (32/3) S0, dn/dh = -(32/3) S1/h; stop per
  * `mode`; else set lo = h if n < N_t, else hi = h, and take the Newton step
@@ -190,6 +191,30 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
                          const void *h, const void *grad_rho, const void *grad_h,
                          void *grad_x, void *grad_y, void *grad_z, void *grad_m,
                          void *ws, size_t ws_bytes, void *stream);
+
+/* Launch-parameter autotuner of sph_density_solve (the batched persistent form
+ * whose per-item work is uneven and unknown in advance: the dynamic scheduling
+ * of Sec. IV-A).  Times sph_density_solve on the given input for every
+ * combination of segment {8, 16, 32, 64}, waves_per_cu {4, 8, 16} and
+ * tile_cell {-1, 0} (one warm-up call, then the median of three, timed with
+ * HIP events on `stream`), and writes *params with the fastest combination to
+ * *best_out (and its time in ms to *best_ms_out, if not NULL).  rho_out and
+ * h_out (device, capacity n, io_dtype) are scratch outputs and are
+ * overwritten; ws is a workspace as for sph_density_solve.
+ * Results are cached in the process (mutex-guarded), keyed by the device
+ * architecture, every parameter other than the three tuned ones, whether
+ * h_init is given, floor(log2 n) and floor(log2(n_groups + 1)); a cached key
+ * returns at once without touching the device.  If the environment variable
+ * SPH_TUNE_CACHE names a file, entries are read from it on first use and new
+ * ones appended.  The call synchronizes with `stream` (it must not be
+ * captured into a graph).  Returns SPH_OK, or the first failing code of the
+ * solves (SPH_E_INVALID / SPH_E_WORKSPACE / SPH_E_HIP). */
+int sph_autotune(const sph_params *params, int64_t n, int32_t n_groups,
+                 const int64_t *group_offsets,
+                 const void *x, const void *y, const void *z, const void *m,
+                 const void *h_init, void *rho_out, void *h_out,
+                 void *ws, size_t ws_bytes, void *stream,
+                 sph_params *best_out, float *best_ms_out);
 
 /* Static text for a return code. */
 const char *sph_status_string(int code);

@@ -17,7 +17,7 @@ import os
 
 __all__ = [
     "LIB_PATH", "Params", "SPHError", "load", "default_params", "workspace_size", "sort",
-    "density_solve", "density_backward", "density", "SPHDensity", "status_string",
+    "density_solve", "density_backward", "autotune", "density", "SPHDensity", "status_string",
     "FP64", "FP32C", "F64", "F32", "BAND", "ROOT",
     "ST_NOCONV", "ST_HTOOLARGE", "ST_BADINPUT", "ST_UNREACHABLE",
 ]
@@ -36,7 +36,7 @@ ST_UNREACHABLE = 1 << 19
 
 EXPORTS = [
     "sph_default_params", "sph_workspace_size", "sph_sort", "sph_density_solve",
-    "sph_density_backward", "sph_status_string", "sph_last_hip_error",
+    "sph_density_backward", "sph_autotune", "sph_status_string", "sph_last_hip_error",
     "sph_last_hip_error_string",
 ]
 
@@ -99,6 +99,9 @@ def load():
     L.sph_density_solve.restype = C.c_int
     L.sph_density_backward.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P]
     L.sph_density_backward.restype = C.c_int
+    L.sph_autotune.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, SZ, P, PP,
+                               C.POINTER(C.c_float)]
+    L.sph_autotune.restype = C.c_int
     L.sph_status_string.argtypes = [C.c_int]
     L.sph_status_string.restype = C.c_char_p
     L.sph_last_hip_error.argtypes = []
@@ -262,6 +265,28 @@ def density_backward(x, y, z, m, h, grad_rho, grad_h=None, params: Params | None
     if rc != OK:
         raise SPHError(rc, "sph_density_backward")
     return dict(gx=gx, gy=gy, gz=gz, gm=gm)
+
+
+def autotune(x, y, z, m, h_init=None, params: Params | None = None, group_offsets=None, ws=None):
+    """``sph_autotune``: returns (tuned Params, its time per solve in ms)."""
+    torch = _torch()
+    params = params or default_params()
+    dev = _check_dev(x, y, z, m, h_init, group_offsets)
+    n = x.shape[0]
+    G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    if ws is None:
+        ws = workspace(params, n, G, dev)
+    dt = _io(params)
+    rho = torch.empty(max(n, 1), dtype=dt, device=dev)
+    h = torch.empty(max(n, 1), dtype=dt, device=dev)
+    best = Params()
+    ms = C.c_float(0.0)
+    rc = load().sph_autotune(C.byref(params), n, G, _ptr(group_offsets), _ptr(x), _ptr(y),
+                             _ptr(z), _ptr(m), _ptr(h_init), _ptr(rho), _ptr(h), _ptr(ws),
+                             ws.numel(), _stream(dev), C.byref(best), C.byref(ms))
+    if rc != OK:
+        raise SPHError(rc, "sph_autotune")
+    return best, float(ms.value)
 
 
 def density(pos, m, h_init=None, group_offsets=None, **params):

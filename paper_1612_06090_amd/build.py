@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsph.so")
-SOURCES = ["sph_abi.hip", "sort.hip", "solve.hip", "backward.hip"]
+SOURCES = ["sph_abi.hip", "sort.hip", "solve.hip", "backward.hip", "tune.hip"]
 
 # -ffp-contract=off: the FP64 pair distance must be evaluated exactly as
 # written (no fused multiply-add); the FP32 path asks for its FMAs explicitly.

@@ -48,6 +48,7 @@ struct AdjArgs {
     int32_t Ld;
     const double *frame;
     const int32_t *gitems;
+    const int32_t *gorder;
     int64_t n_items;
     const float *rmq;
     int32_t rmq_levels;
@@ -147,8 +148,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 const int32_t mid = (lo + hi + 1) >> 1;
                 if (a.gitems[mid] <= item) lo = mid; else hi = mid - 1;
             }
-            g = lo;
-            b = a.goff[g] + (int64_t)(item - a.gitems[g]) * kAdjP;
+            g = a.gorder[lo];  // position lo of the largest-first order
+            b = a.goff[g] + (int64_t)(item - a.gitems[lo]) * kAdjP;
             e = b + kAdjP < a.goff[g + 1] ? b + kAdjP : a.goff[g + 1];
             const double *f = a.frame + 8 * (int64_t)g;
             org0 = f[0]; org1 = f[1]; org2 = f[2];
@@ -677,6 +678,7 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
     a.Ld = pl.Ld;
     a.frame = pl.frame;
     a.gitems = pl.gitems;
+    a.gorder = pl.gorder;
     a.n_items = ceil_div(n, kAdjP);
     a.rmq = pl.rmq;
     a.rmq_levels = pl.rmq_levels;

@@ -51,6 +51,7 @@ struct SolveArgs {
     int32_t Ld;
     const double *frame;
     const int32_t *gitems;
+    const int32_t *gorder;
     int64_t n_items;
     int32_t seg;
     double box;
@@ -252,8 +253,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 const int32_t mid = (lo + hi + 1) >> 1;
                 if (a.gitems[mid] <= item) lo = mid; else hi = mid - 1;
             }
-            g = lo;
-            b = a.goff[g] + (int64_t)(item - a.gitems[g]) * a.seg;
+            g = a.gorder[lo];  // position lo of the largest-first order
+            b = a.goff[g] + (int64_t)(item - a.gitems[lo]) * a.seg;
             e = b + a.seg < a.goff[g + 1] ? b + a.seg : a.goff[g + 1];
             const double *f = a.frame + 8 * (int64_t)g;
             org0 = f[0]; org1 = f[1]; org2 = f[2];
@@ -604,6 +605,7 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     a.Ld = pl.Ld;
     a.frame = pl.frame;
     a.gitems = pl.gitems;
+    a.gorder = pl.gorder;
     a.n_items = pl.n_items;
     a.seg = pl.prm.segment;
     a.box = pl.prm.box;

@@ -241,31 +241,34 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_down(int64_t n, const ui
     }
 }
 
+// LSD radix sort of (key, value) pairs over `passes` 8-bit digits; the result
+// ends in the A buffers after an even number of passes.
 template <int ROUNDS>
-static hipError_t radix_sort_impl(Plan &pl, int passes, hipStream_t st) {
-    const int64_t n = pl.n;
-    const int64_t nb = pl.nb_sort;
-    uint64_t *ka = pl.keysA, *kb = pl.keysB;
-    int32_t *va = pl.valsA, *vb = pl.valsB;
+static hipError_t radix_passes(int64_t n, int64_t nb, int passes, uint64_t *ka, uint64_t *kb,
+                               int32_t *va, int32_t *vb, uint32_t *hist, uint32_t *digit_tot,
+                               hipStream_t st, uint64_t **kout, int32_t **vout) {
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_radix_up<ROUNDS>, dim3((unsigned)nb), dim3(kSortThreads), 0, st, n,
-                           ka, shift, pl.hist, nb);
-        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kSortThreads), 0, st, pl.hist, nb,
-                           pl.digit_tot);
+                           ka, shift, hist, nb);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kSortThreads), 0, st, hist, nb,
+                           digit_tot);
         hipLaunchKernelGGL(k_radix_down<ROUNDS>, dim3((unsigned)nb), dim3(kSortThreads), 0, st,
-                           n, ka, va, kb, vb, shift, pl.hist, pl.digit_tot, nb);
+                           n, ka, va, kb, vb, shift, hist, digit_tot, nb);
         uint64_t *tk = ka; ka = kb; kb = tk;
         int32_t *tv = va; va = vb; vb = tv;
     }
-    pl.skeys = ka;
-    pl.perm = va;
+    *kout = ka;
+    *vout = va;
     return hipGetLastError();
 }
 
 static hipError_t radix_sort(Plan &pl, int passes, hipStream_t st) {
-    if (pl.sort_rounds == 16) return radix_sort_impl<16>(pl, passes, st);
-    return radix_sort_impl<4>(pl, passes, st);
+    if (pl.sort_rounds == 16)
+        return radix_passes<16>(pl.n, pl.nb_sort, passes, pl.keysA, pl.keysB, pl.valsA, pl.valsB,
+                                pl.hist, pl.digit_tot, st, &pl.skeys, &pl.perm);
+    return radix_passes<4>(pl.n, pl.nb_sort, passes, pl.keysA, pl.keysB, pl.valsA, pl.valsB,
+                           pl.hist, pl.digit_tot, st, &pl.skeys, &pl.perm);
 }
 
 hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const void *y,
@@ -300,14 +303,17 @@ hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const
 
 // ------------------------------------------------------- sorted SoA gather
 
-// Default initial smoothing length 2 (V / n)^(1/3).
+// Default initial smoothing length 2 (V / n)^(1/3): V = box^3, or the group's
+// bounding-box volume with every extent at least 2^-16 of the largest.
 __device__ inline double default_h(bool grouped, double box, int64_t n, const double *frame,
                                    const int64_t *goff, uint64_t key) {
     if (!grouped) return 2.0 * cbrt(box * box * box / (double)n);
     const uint32_t g = (uint32_t)(key >> 48);
-    const double E = frame[8 * (int64_t)g + 7];
+    const double *f = frame + 8 * (int64_t)g;
+    const double emin = f[7] * 0x1p-16;
+    const double V = fmax(f[3], emin) * fmax(f[4], emin) * fmax(f[5], emin);
     const double ng = (double)(goff[g + 1] - goff[g]);
-    return 2.0 * cbrt(E * E * E / ng);
+    return 2.0 * cbrt(V / ng);
 }
 
 __device__ inline bool valid_input(bool periodic, double box, double x, double y, double z,
@@ -609,21 +615,44 @@ hipError_t run_dense_table(Plan &pl, hipStream_t st) {
     return scan<1, true, true>(pl.table, pl.table, tn, pl.bsum, st);
 }
 
-// Work items of the batched form: group g owns items [gitems[g], gitems[g+1]),
-// one per `segment` particles; gitems[G] = total.
-__global__ void k_group_ntiles(int32_t G, const int64_t *goff, int32_t seg, int32_t *cnt) {
+// Largest group first: sort key (2^31 - 1 - size) << 16 | g, so that the
+// ascending sort lists groups by decreasing size, ties by group id.
+__global__ void k_group_lpt_keys(int32_t G, const int64_t *goff, uint64_t *keys, int32_t *vals) {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g > G) return;
-    if (g == G) { cnt[g] = 0; return; }
+    if (g >= G) return;
     const int64_t ng = goff[g + 1] - goff[g];
-    cnt[g] = (int32_t)((ng + seg - 1) / seg);
+    keys[g] = ((uint64_t)(0x7FFFFFFFll - ng) << 16) | (uint64_t)g;
+    vals[g] = (int32_t)g;
+}
+
+// Work items of the batched form: the group at position k of the
+// largest-first order (gorder[k]) owns items [gitems[k], gitems[k+1]), one per
+// `segment` particles; gitems[G] = total.
+__global__ void k_group_ntiles(int32_t G, const int64_t *goff, const int32_t *gorder,
+                               int32_t seg, int32_t *cnt) {
+    const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (k > G) return;
+    if (k == G) { cnt[k] = 0; return; }
+    const int32_t g = gorder[k];
+    const int64_t ng = goff[g + 1] - goff[g];
+    cnt[k] = (int32_t)((ng + seg - 1) / seg);
 }
 
 hipError_t run_group_items(Plan &pl, const int64_t *goff, hipStream_t st) {
-    const int64_t cnt = (int64_t)pl.G + 1;
+    const int64_t G = pl.G;
+    hipLaunchKernelGGL(k_group_lpt_keys, dim3((unsigned)ceil_div(G, 256)), dim3(256), 0, st,
+                       pl.G, goff, pl.gkeysA, pl.gvalsA);
+    uint64_t *ko = nullptr;
+    int32_t *vo = nullptr;
+    // sizes < 2^31 and ids < 2^16: 47 key bits, 6 digit passes
+    hipError_t e = radix_passes<4>(G, pl.nb_gsort, 6, pl.gkeysA, pl.gkeysB, pl.gvalsA,
+                                   pl.gvalsB, pl.ghist, pl.digit_tot, st, &ko, &vo);
+    if (e != hipSuccess) return e;
+    pl.gorder = vo;
+    const int64_t cnt = G + 1;
     hipLaunchKernelGGL(k_group_ntiles, dim3((unsigned)ceil_div(cnt, 256)), dim3(256), 0, st,
-                       pl.G, goff, pl.prm.segment, pl.gitems);
-    hipError_t e = hipGetLastError();
+                       pl.G, goff, pl.gorder, pl.prm.segment, pl.gitems);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     return scan<0, false, false>(pl.gitems, pl.gitems, cnt, pl.bsum, st);
 }

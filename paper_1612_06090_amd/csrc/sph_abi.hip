@@ -97,7 +97,12 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
     if (pl.grouped) {
         pl.frame = (double *)take(8 * 8 * (size_t)G);
         pl.gitems = (int32_t *)take(4 * ((size_t)G + 1));
-        pl.gorder = (int32_t *)take(4 * (size_t)G);
+        pl.nb_gsort = ceil_div((int64_t)G, (int64_t)256 * 4);
+        pl.gkeysA = (uint64_t *)take(8 * (size_t)G);
+        pl.gkeysB = (uint64_t *)take(8 * (size_t)G);
+        pl.gvalsA = (int32_t *)take(4 * (size_t)G);
+        pl.gvalsB = (int32_t *)take(4 * (size_t)G);
+        pl.ghist = (uint32_t *)take(4 * 256 * (size_t)pl.nb_gsort);
     }
     pl.ctrl = (int32_t *)take(64);
     pl.stats = (uint64_t *)take(64);

@@ -54,7 +54,11 @@ struct Plan {
     int32_t *bsum = nullptr;     // block sums of scans
     double *frame = nullptr;     // per group: lo xyz, ext xyz, scale, pad (8 doubles)
     int32_t *gitems = nullptr;   // per group: first work item (G+1)
-    int32_t *gorder = nullptr;   // groups in processing order (G)
+    int32_t *gorder = nullptr;   // groups in processing order, largest first (G)
+    uint64_t *gkeysA = nullptr, *gkeysB = nullptr;  // group-order sort (G each)
+    int32_t *gvalsA = nullptr, *gvalsB = nullptr;
+    uint32_t *ghist = nullptr;
+    int64_t nb_gsort = 0;        // radix blocks of the group-order sort
     int32_t *ctrl = nullptr;     // [0] work queue head, [1..] reserved
     uint64_t *stats = nullptr;   // 4 x uint64 device counters
     double *adj = nullptr;       // adjoint, sorted order: alpha, beta, gamma, grad_rho, grad_h (5 x n)

@@ -1,0 +1,175 @@
+// Launch-parameter autotuner of the density solve: times every candidate
+// (tile size, persistent waves per CU, tile cell level) on the caller's own
+// input and keeps the fastest.  Results are cached per process (and, when the
+// environment names a file, across processes), keyed by device, the
+// parameters that change the work, and the size class of the input.
+#include "sph_internal.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace sph {
+namespace {
+
+struct TuneEntry {
+    int32_t segment, waves_per_cu, tile_cell;
+    float ms;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, TuneEntry> g_tune;
+bool g_tune_file_loaded = false;
+
+const int kSegments[] = {8, 16, 32, 64};
+const int kWaves[] = {4, 8, 16};
+const int kTileCell[] = {-1, 0};
+
+int floor_log2(int64_t v) {
+    int k = 0;
+    while (v > 1) { v >>= 1; ++k; }
+    return k;
+}
+
+std::string tune_key(const sph_params *p, int64_t n, int32_t G, bool has_h0) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    hipDeviceProp_t prop;
+    char name[64] = "unknown";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        snprintf(name, sizeof(name), "%s", prop.gcnArchName);
+        for (char *c = name; *c; ++c)
+            if (*c == ' ' || *c == ':') *c = '_';
+    }
+    char buf[320];
+    snprintf(buf, sizeof(buf), "%s/p%d/io%d/m%d/per%d/nt%.17g/tol%.17g/rt%.17g/it%d/cl%d/h0%d/n%d/g%d",
+             name, p->precision, p->io_dtype, p->mode, p->periodic, p->n_target, p->n_tol,
+             p->root_tol, p->max_iter, p->cell_level, has_h0 ? 1 : 0, floor_log2(n),
+             floor_log2((int64_t)G + 1));
+    return std::string(buf);
+}
+
+// Lines "key segment waves_per_cu tile_cell ms"; unreadable lines are skipped.
+void load_file_locked() {
+    if (g_tune_file_loaded) return;
+    g_tune_file_loaded = true;
+    const char *path = getenv("SPH_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[320];
+    TuneEntry t;
+    while (fscanf(f, "%319s %d %d %d %f", key, &t.segment, &t.waves_per_cu, &t.tile_cell,
+                  &t.ms) == 5)
+        g_tune[key] = t;
+    fclose(f);
+}
+
+void append_file_locked(const std::string &key, const TuneEntry &t) {
+    const char *path = getenv("SPH_TUNE_CACHE");
+    if (!path || !*path) return;
+    FILE *f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d %d %.6g\n", key.c_str(), t.segment, t.waves_per_cu, t.tile_cell, t.ms);
+    fclose(f);
+}
+
+}  // namespace
+}  // namespace sph
+
+using namespace sph;
+
+extern "C" int sph_autotune(const sph_params *params, int64_t n, int32_t n_groups,
+                            const int64_t *group_offsets, const void *x, const void *y,
+                            const void *z, const void *m, const void *h_init, void *rho_out,
+                            void *h_out, void *ws, size_t ws_bytes, void *stream,
+                            sph_params *best_out, float *best_ms_out) {
+    if (!params || !best_out) return SPH_E_INVALID;
+    size_t need = 0;
+    int rc = sph_workspace_size(params, n, n_groups, &need);
+    if (rc != SPH_OK) return rc;
+    if (n > 0 && (!x || !y || !z || !m || !rho_out || !h_out || !ws)) return SPH_E_INVALID;
+    if (n > 0 && ws_bytes < need) return SPH_E_WORKSPACE;
+    sph_params base = *params;
+    base.prof_events[0] = base.prof_events[1] = nullptr;
+    *best_out = base;
+    if (best_ms_out) *best_ms_out = 0.f;
+    if (n == 0) return SPH_OK;
+
+    const std::string key = tune_key(&base, n, n_groups, h_init != nullptr);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_file_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            best_out->segment = it->second.segment;
+            best_out->waves_per_cu = it->second.waves_per_cu;
+            best_out->tile_cell = it->second.tile_cell;
+            if (best_ms_out) *best_ms_out = it->second.ms;
+            return SPH_OK;
+        }
+    }
+
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return SPH_E_HIP;
+    }
+    TuneEntry best{base.segment, base.waves_per_cu, base.tile_cell, INFINITY};
+    rc = SPH_OK;
+    for (int seg : kSegments) {
+        for (int wv : kWaves) {
+            for (int tc : kTileCell) {
+                sph_params p = base;
+                p.segment = seg;
+                p.waves_per_cu = wv;
+                p.tile_cell = tc;
+                std::vector<float> t;
+                for (int r = 0; r < 4 && rc == SPH_OK; ++r) {
+                    if (hipEventRecord(e0, st) != hipSuccess) { rc = SPH_E_HIP; break; }
+                    rc = sph_density_solve(&p, n, n_groups, group_offsets, x, y, z, m, h_init,
+                                           rho_out, h_out, nullptr, nullptr, nullptr, nullptr,
+                                           ws, ws_bytes, stream);
+                    if (rc != SPH_OK) break;
+                    float ms = 0.f;
+                    if (hipEventRecord(e1, st) != hipSuccess ||
+                        hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        rc = SPH_E_HIP;
+                        break;
+                    }
+                    if (r > 0) t.push_back(ms);  // the first call warms up
+                }
+                if (rc != SPH_OK) break;
+                std::sort(t.begin(), t.end());
+                const float med = t[t.size() / 2];
+                if (med < best.ms) best = TuneEntry{seg, wv, tc, med};
+            }
+            if (rc != SPH_OK) break;
+        }
+        if (rc != SPH_OK) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SPH_OK) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (g_tune.find(key) == g_tune.end()) {
+            g_tune[key] = best;
+            append_file_locked(key, best);
+        }
+    }
+    best_out->segment = best.segment;
+    best_out->waves_per_cu = best.waves_per_cu;
+    best_out->tile_cell = best.tile_cell;
+    if (best_ms_out) *best_ms_out = best.ms;
+    return SPH_OK;
+}

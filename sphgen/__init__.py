@@ -29,6 +29,7 @@ __all__ = [
     "plummer_radii",
     "plummer_mixture",
     "group_sizes",
+    "group_volume",
     "groups",
     "cotangent",
     "config",
@@ -217,6 +218,16 @@ def group_sizes(n_groups: int, seed: int, lo: int = 32, hi: int = 131072,
     return np.clip(s, lo, hi)
 
 
+def group_volume(p: np.ndarray) -> float:
+    """Bounding-box volume of an (k, 3) point set: the product of the extents,
+    each at least 2^-16 of the largest (the largest taken as 1 when all are 0)."""
+    ext = p.max(axis=0) - p.min(axis=0)
+    e = float(ext.max())
+    if not e > 0.0:
+        e = 1.0
+    return float(np.prod(np.maximum(ext, e * 2.0 ** -16)))
+
+
 def groups(n_groups: int, seed: int, lo: int = 32, hi: int = 131072,
            slope: float = -2.0, a_range=(0.005, 0.05), n_target: float = 32.0,
            n_tol: float = 1.0, sizes: np.ndarray | None = None) -> ParticleSet:
@@ -245,9 +256,9 @@ def groups(n_groups: int, seed: int, lo: int = 32, hi: int = 131072,
         p = c + plummer_radii(rng, k, a)[:, None] * _isotropic(rng, k)
         sl = slice(int(offsets[g]), int(offsets[g + 1]))
         x[sl], y[sl], z[sl] = p[:, 0], p[:, 1], p[:, 2]
-        ext = p.max(axis=0) - p.min(axis=0)
-        vol = float(np.prod(np.maximum(ext, 1e-300)))
-        h0[sl] = default_h_init(k, vol)
+        if k == 0:
+            continue
+        h0[sl] = default_h_init(k, group_volume(p))
     return ParticleSet(
         x=x, y=y, z=z, m=np.full(n, 1.0 / n), h_init=h0, periodic=False,
         box=1.0, n_target=float(n_target), n_tol=float(n_tol), offsets=offsets,

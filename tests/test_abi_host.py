@@ -144,3 +144,22 @@ def test_product_does_not_touch_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "sph_oracle" not in text, f
+
+
+def test_autotune_host_checks():
+    lib = _lib()
+    p = sph.default_params()
+    best = sph.Params()
+    ms = C.c_float(-1.0)
+    # null result pointer, invalid parameters: rejected before any device call
+    assert lib.sph_autotune(C.byref(p), 10, 0, None, None, None, None, None, None, None, None,
+                            None, 0, None, None, None) == sph.E_INVALID
+    bad = sph.default_params(segment=12)
+    assert lib.sph_autotune(C.byref(bad), 10, 0, None, None, None, None, None, None, None, None,
+                            None, 0, None, C.byref(best), None) == sph.E_INVALID
+    # an empty input needs no device: the parameters come back unchanged
+    assert lib.sph_autotune(C.byref(p), 0, 0, None, None, None, None, None, None, None, None,
+                            None, 0, None, C.byref(best), C.byref(ms)) == sph.OK
+    assert (best.segment, best.waves_per_cu, best.tile_cell) == (p.segment, p.waves_per_cu,
+                                                                  p.tile_cell)
+    assert ms.value == 0.0

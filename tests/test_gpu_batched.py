@@ -1,0 +1,130 @@
+"""The batched form: many isolated groups of uneven size in one persistent
+launch, work items in largest-group-first order, launch parameters from the
+autotuner, and the whole sort + solve captured in a HIP graph.
+
+Parity as for the single set: FP64 neighbour counts bit-exact and rho, h to
+1e-12 relative; FP32C within 1e-5 (rho) and 1e-4 (n) at the GPU's h.  Graph
+replays must reproduce the eager call bit for bit (the solve is
+deterministic), also after the inputs change in place between replays.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1612_06090_amd as sph
+import sphgen
+from gpu_util import dev_arrays, gpu_solve, params_for, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _fp32c_at_h(ps, g, sub=None):
+    e = oracle.eval_at_h(ps, g["h"], search=1)
+    idx = np.arange(ps.n) if sub is None else sub
+    drho = rel(g["rho"][idx], e["rho"][idx]).max()
+    dn = np.abs(g["nw"][idx] - e["nw"][idx]).max()
+    say(f"  fp32c at h: max |drho|/rho {drho:.2e}  max |dn| {dn:.2e}")
+    assert drho <= 1e-5 and dn <= 1e-4
+
+
+def test_groups_order_with_empty_groups_fp64():
+    # sizes straddle one tile, several tiles and the empty case; the largest
+    # group is not first in caller order
+    sizes = np.array([0, 33, 5000, 0, 1, 700, 16, 17, 2, 0, 1200, 64, 65, 0])
+    ps = sphgen.groups(len(sizes), seed=60, sizes=sizes, n_target=32.0, n_tol=1.0)
+    for seg in (8, 16, 64):
+        g = gpu_solve(ps, segment=seg)
+        o = oracle.solve(ps)
+        e = oracle.eval_at_h(ps, g["h"], search=1)
+        assert np.array_equal(g["nngb"], e["nngb"].astype(np.int32))
+        same = rel(g["h"], o["h"]) <= 1e-12
+        assert same.mean() >= 0.999
+        assert rel(g["rho"][same], o["rho"][same]).max() < 1e-12
+
+
+def test_groups10k_scaled_fp32c():
+    ps = sphgen.config("groups10k", scale=0.05)
+    say(f"[batched] groups10k x0.05 n={ps.n} G={len(ps.offsets) - 1}")
+    g = gpu_solve(ps, precision=sph.FP32C)
+    _fp32c_at_h(ps, g)
+    o = oracle.solve(ps)
+    dh = rel(g["h"], o["h"])
+    say(f"  frac |dh|/h <= 1e-5: {(dh <= 1e-5).mean():.5f}")
+    assert (dh <= 1e-5).mean() >= 0.999
+
+
+def test_groups10k_full_sampled():
+    ps = sphgen.config("groups10k")
+    say(f"[batched] groups10k n={ps.n} G={len(ps.offsets) - 1}")
+    g = gpu_solve(ps, precision=sph.FP32C)
+    assert np.all((g["status"] & (sph.ST_NOCONV | sph.ST_BADINPUT)) == 0)
+    rng = np.random.default_rng(61)
+    sub = rng.choice(ps.n, 3000, replace=False)
+    o = oracle.solve(ps, subset=sub)
+    dh = rel(g["h"][sub], o["h"])
+    say(f"  sampled frac |dh|/h <= 1e-5: {(dh <= 1e-5).mean():.5f}")
+    assert (dh <= 1e-5).mean() >= 0.999
+    _fp32c_at_h(ps, g, sub)
+
+
+def test_autotune_and_cache():
+    import time
+    import torch
+    ps = sphgen.config("groups10k", scale=0.05)
+    p = params_for(ps, precision=sph.FP32C)
+    d = dev_arrays(ps)
+    best, ms = sph.autotune(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, d["goff"])
+    say(f"  tuned: segment {best.segment} waves/CU {best.waves_per_cu} "
+        f"tile_cell {best.tile_cell}: {ms:.3f} ms")
+    assert best.segment in (8, 16, 32, 64) and best.waves_per_cu in (4, 8, 16)
+    assert best.tile_cell in (-1, 0) and ms > 0.0
+    assert (best.precision, best.n_target, best.periodic) == (p.precision, p.n_target, 0)
+    t0 = time.perf_counter()
+    again, ms2 = sph.autotune(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, d["goff"])
+    assert time.perf_counter() - t0 < 0.05   # served from the cache
+    assert (again.segment, again.waves_per_cu, again.tile_cell, ms2) == \
+        (best.segment, best.waves_per_cu, best.tile_cell, ms)
+    o = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], best, d["goff"])
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy().astype(np.float64) for k, v in o.items()}
+    _fp32c_at_h(ps, g)
+
+
+def test_graph_replay_matches_eager():
+    import torch
+    ps = sphgen.config("groups10k", scale=0.05)
+    p = params_for(ps, precision=sph.FP32C)
+    d = dev_arrays(ps)
+    n, G = ps.n, len(ps.offsets) - 1
+    ws = sph.workspace(p, n, G, d["x"].device)
+
+    def eager():
+        o = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, d["goff"], ws=ws)
+        torch.cuda.synchronize()
+        return {k: v.clone() for k, v in o.items()}
+
+    ref = eager()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, d["goff"], ws=ws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, d["goff"],
+                                ws=ws)
+    for r in range(3):
+        eager()                      # the program's own work between replays
+        graph.replay()
+        torch.cuda.synchronize()
+        for k in ("rho", "h", "nw", "nngb", "status"):
+            assert torch.equal(out[k], ref[k]), (r, k)
+    # inputs changed in place: the replay reads the new values
+    d["x"].mul_(0.5)
+    ref2 = eager()
+    graph.replay()
+    torch.cuda.synchronize()
+    for k in ("rho", "h", "nw", "nngb", "status"):
+        assert torch.equal(out[k], ref2[k]), k
+    assert not torch.equal(ref2["rho"], ref["rho"])
