@@ -209,6 +209,36 @@ def run_batched(sph, torch, steps, warmup):
                       "tile_cell": p.tile_cell, "ms": tuned_ms, "tuning_s": tune_s}}
 
 
+def run_large(sph, torch, steps):
+    """clustered2^24: 2^24 particles, 2000 Plummer spheres (central contrast
+    <= 1e5), N_t = 64 +- 1, FP32C, full sort in every call."""
+    import sphgen
+    ps = sphgen.config("clustered2^24")
+    n = ps.n
+    d = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+         for k in ("x", "y", "z", "m", "h_init")}
+    p = sph.default_params(periodic=1, box=ps.box, n_target=ps.n_target, n_tol=ps.n_tol,
+                           precision=sph.FP32C)
+    ws = sph.workspace(p, n, 0, d["x"].device)
+    o = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, stats=True, ws=ws)
+    torch.cuda.synchronize()
+    pairs = int(o["stats"][0].item())
+    flagged = int(((o["status"] >> 16) != 0).sum().item())
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    srt = run_sort(sph, torch, d, ps, steps)
+    return {"workload": "clustered2^24: 2^24 particles, 2000 Plummer spheres (contrast <= 1e5) "
+                        "+ 30% background, N_t = 64 +- 1, FP32C, full sort every call",
+            "n": n, "ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
+            "particles_per_s": n / (ms * 1e-3), "pairs_per_step": pairs, "flagged": flagged,
+            "sort": srt}
+
+
 def cpu_baseline(ps, budget_s=15.0):
     """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
     import oracle
@@ -322,6 +352,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
@@ -370,6 +401,11 @@ def main():
         bat = run_batched(sph, torch, max(3, args.steps), args.warmup)
         print(f"[bench] batched {bat}", file=sys.stderr, flush=True)
 
+    big = None
+    if not args.no_large:
+        big = run_large(sph, torch, 3)
+        print(f"[bench] large {big}", file=sys.stderr, flush=True)
+
     def roof(r, form):
         flop = FLOP_CAND * r["cands"] + FLOP_PAIR[form] * r["pairs"]
         ach = flop / (r["kernel_ms"] * 1e-3)
@@ -416,6 +452,8 @@ def main():
     line["sort"] = srt
     if bat is not None:
         line["batched"] = bat
+    if big is not None:
+        line["large"] = big
     if adj is not None:
         line["adjoint"] = adj
     if not args.no_cpu_baseline:

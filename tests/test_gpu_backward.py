@@ -152,6 +152,68 @@ def test_backward_lattice_symmetry(precision):
     assert np.abs(g["gm"] - sumw).max() <= (1e-13 if precision == sph.FP64 else 1e-6) * sumw.max()
 
 
+def test_backward_clustered2p20_central_differences():
+    # full-size set, FP64 root-mode solves: the directional derivative of
+    # L = sum gr rho along 8 random unit directions over all (x, m), and 16
+    # single-coordinate probes, against the adjoint (FP64 and FP32C)
+    import torch
+    ps = sphgen.config("clustered2^20")
+    n = ps.n
+    prm = sph.default_params(mode=sph.ROOT, root_tol=1e-14, n_target=ps.n_target,
+                             n_tol=ps.n_tol, max_iter=200)
+    base = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+            for k in ("x", "y", "z", "m")}
+    h0 = torch.tensor(ps.h_init, dtype=torch.float64, device="cuda")
+    gr_np = sphgen.cotangent(n, 5)
+    gr = torch.tensor(gr_np, device="cuda")
+
+    def L(dx=None, dm=None, eps=0.0):
+        x = {k: v.clone() for k, v in base.items()}
+        if dx is not None:
+            for a, k in enumerate("xyz"):
+                x[k] = torch.remainder(x[k] + eps * dx[:, a], 1.0)
+        if dm is not None:
+            x["m"] = x["m"] + eps * dm
+        o = sph.density_solve(x["x"], x["y"], x["z"], x["m"], h0, prm)
+        return float((gr * o["rho"]).sum()), o
+
+    L0, o0 = L()
+    assert int(((o0["status"] >> 16) != 0).sum()) == 0
+    h = o0["h"].cpu().numpy()
+    g64 = gpu_backward(ps, h, gr_np)
+    g32 = gpu_backward(ps, h, gr_np, precision=sph.FP32C)
+    eps = 1e-6
+    rng = np.random.default_rng(82)
+    worst = {"fp64": 0.0, "fp32c": 0.0}
+    for t in range(8):
+        v = rng.standard_normal(4 * n)
+        v /= np.linalg.norm(v)
+        dx = torch.tensor(v[:3 * n].reshape(n, 3), device="cuda")
+        dm = torch.tensor(v[3 * n:], device="cuda")
+        fd = (L(dx, dm, eps)[0] - L(dx, dm, -eps)[0]) / (2 * eps)
+        for tag, g in (("fp64", g64), ("fp32c", g32)):
+            an = float(np.dot(v[:3 * n], np.stack([g["gx"], g["gy"], g["gz"]], 1).ravel())
+                       + np.dot(v[3 * n:], g["gm"]))
+            worst[tag] = max(worst[tag], abs(fd - an) / abs(fd))
+        say(f"  direction {t}: fd {fd:.10e}")
+    say(f"  worst relative error: {worst}")
+    assert worst["fp64"] <= 1e-5 and worst["fp32c"] <= 1e-4
+    # single coordinates of particles in the densest regions (largest rho)
+    top = np.argsort(-o0["rho"].cpu().numpy())[:8]
+    probes = list(top) + list(rng.choice(n, 8, replace=False))
+    scale = np.abs(g64["gx"]).max()
+    for k in probes:
+        for a, key in enumerate(("gx", "gy", "gz")):
+            if a != k % 3:
+                continue
+            dx = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+            dx[k, a] = 1.0
+            step = 1e-6 * h[k]
+            fd = (L(dx, None, step)[0] - L(dx, None, -step)[0]) / (2 * step)
+            err = abs(fd - g64[key][k])
+            assert err <= 1e-5 * max(abs(fd), 1e-3 * scale), (k, a, fd, g64[key][k])
+
+
 def test_backward_deterministic():
     ps, s, gr, gh = _setup("clustered32k")
     for prec in (sph.FP64, sph.FP32C):

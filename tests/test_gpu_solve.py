@@ -241,3 +241,20 @@ def test_tile_sizes_fp32c(segment):
     ps = sphgen.groups(300, seed=57, lo=32, hi=4000, n_target=32.0, n_tol=1.0)
     g = gpu_solve(ps, precision=sph.FP32C, segment=segment)
     _fp32c_bounds(ps, g)
+
+
+def test_fp32c_clustered2p24_sampled():
+    # 2^24 particles, 2000 spheres, contrast <= 1e5, N_t = 64 +- 1: the GPU
+    # solves every particle (full sort in the call), the oracle a sample
+    ps = sphgen.config("clustered2^24")
+    say(f"[solve fp32c] clustered2^24 n={ps.n}")
+    g = gpu_solve(ps, precision=sph.FP32C)
+    assert np.all((g["status"] & (sph.ST_NOCONV | sph.ST_BADINPUT | sph.ST_HTOOLARGE)) == 0)
+    assert np.all(np.abs(g["nw"] - 64.0) <= 1.0)
+    rng = np.random.default_rng(62)
+    sub = rng.choice(ps.n, 2000, replace=False)
+    o = oracle.solve(ps, subset=sub)
+    dh = rel(g["h"][sub], o["h"])
+    say(f"  sampled frac |dh|/h <= 1e-5: {(dh <= 1e-5).mean():.5f}")
+    assert (dh <= 1e-5).mean() >= 0.999
+    _fp32c_bounds(ps, g, sub)
