@@ -98,7 +98,7 @@ typedef struct {
     int32_t  tile_cell;     /* tuning: neighbour-cell side in units of the tile's largest
                                h, as a power of two exponent in {-1, 0} (default -1);
                                results do not depend on it */
-    int32_t  waves_per_cu;  /* tuning: persistent grid = 256 CUs x this (default 8) */
+    int32_t  waves_per_cu;  /* tuning: persistent grid = 256 CUs x this (default 16) */
     int32_t  segment;       /* tuning: particles per wavefront tile, 8/16/32/64 (default
                                16); each particle is held by 64/segment lanes that split
                                its candidate stream; results do not depend on it beyond
@@ -195,7 +195,7 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
 /* Launch-parameter autotuner of sph_density_solve (the batched persistent form
  * whose per-item work is uneven and unknown in advance: the dynamic scheduling
  * of Sec. IV-A).  Times sph_density_solve on the given input for every
- * combination of segment {8, 16, 32, 64}, waves_per_cu {4, 8, 16} and
+ * combination of segment {8, 16, 32, 64}, waves_per_cu {8, 16, 32} and
  * tile_cell {-1, 0} (one warm-up call, then the median of three, timed with
  * HIP events on `stream`), and writes *params with the fastest combination to
  * *best_out (and its time in ms to *best_ms_out, if not NULL).  rho_out and

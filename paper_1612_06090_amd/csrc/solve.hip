@@ -65,6 +65,21 @@ struct SolveArgs {
     uint64_t *stats;
 };
 
+// Values every lane of the wave already holds (results of a full-wave
+// reduction or broadcast), moved to scalar registers.
+__device__ inline double uniform_d(double v) {
+    int2 b = __builtin_bit_cast(int2, v);
+    b.x = __builtin_amdgcn_readfirstlane(b.x);
+    b.y = __builtin_amdgcn_readfirstlane(b.y);
+    return __builtin_bit_cast(double, b);
+}
+
+__device__ inline int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ inline uint64_t uniform_u64(uint64_t v) {
+    return __builtin_bit_cast(uint64_t, uniform_d(__builtin_bit_cast(double, v)));
+}
+
 struct HState {
     double h, lo, hi;
     int it, flags;
@@ -231,12 +246,12 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     const int kk = l / P;        // copy index of this lane
     const int B = a.bits;
     constexpr uint64_t kTileMask = P == 64 ? ~0ull : ((1ull << P) - 1ull);
-    uint64_t cnt_pairs = 0, cnt_cands = 0, cnt_passes = 0;
+    uint64_t cnt_pairs = 0, cnt_cands = 0, cnt_passes = 0;  // wave totals
 
     for (;;) {
         int item = 0;
         if (l == 0) item = atomicAdd(a.queue, 1);
-        item = __shfl(item, 0, 64);
+        item = uniform_i(__shfl(item, 0, 64));
         const int64_t n_items = GROUPED ? (int64_t)a.gitems[a.G] : a.n_items;
         if (item >= n_items) break;
 
@@ -257,8 +272,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             b = a.goff[g] + (int64_t)(item - a.gitems[lo]) * a.seg;
             e = b + a.seg < a.goff[g + 1] ? b + a.seg : a.goff[g + 1];
             const double *f = a.frame + 8 * (int64_t)g;
-            org0 = f[0]; org1 = f[1]; org2 = f[2];
-            sc = f[6];
+            org0 = uniform_d(f[0]); org1 = uniform_d(f[1]); org2 = uniform_d(f[2]);
+            sc = uniform_d(f[6]);
         }
         const double hmax = GROUPED ? INFINITY : 0.5 * a.box * (1.0 - 0x1p-20);
 
@@ -268,7 +283,6 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         double xi = 0.0, yi = 0.0, zi = 0.0;  // FP64 absolute position
         int32_t qxi = 0, qyi = 0, qzi = 0;    // FP32C grid coordinates
         float fxi = 0.f, fyi = 0.f, fzi = 0.f;
-        double tx = 0.0, ty = 0.0, tz = 0.0;  // grid-unit position (culling)
         HState hs;
         hs.h = mine ? a.sh0[s] : 1.0;
         hs.lo = 0.0;
@@ -281,19 +295,24 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             if (PREC == SPH_FP64) {
                 xi = a.sx[s]; yi = a.sy[s]; zi = a.sz[s];
                 valid = !isnan(xi);
-                tx = (xi - org0) * sc; ty = (yi - org1) * sc; tz = (zi - org2) * sc;
             } else {
                 qxi = a.qx[s]; qyi = a.qy[s]; qzi = a.qz[s];
                 fxi = a.fx[s]; fyi = a.fy[s]; fzi = a.fz[s];
                 valid = !isnan(fxi);
+            }
+        }
+        // grid-unit position (culling), recomputed where needed
+        auto grid_pos = [&](double &tx, double &ty, double &tz) {
+            if (PREC == SPH_FP64) {
+                tx = (xi - org0) * sc; ty = (yi - org1) * sc; tz = (zi - org2) * sc;
+            } else {
                 tx = (double)qxi + (double)fxi;
                 ty = (double)qyi + (double)fyi;
                 tz = (double)qzi + (double)fzi;
             }
-        }
-        const int64_t oi = mine ? (int64_t)a.perm[s] : 0;
+        };
         if (mine && !valid && kk == 0) {
-            write_out(a, oi, NAN, hs.h, NAN, 0, SPH_ST_BADINPUT);
+            write_out(a, a.perm[s], NAN, hs.h, NAN, 0, SPH_ST_BADINPUT);
         }
         if (GROUPED && mine && valid) {
             const double ng = (double)(a.goff[g + 1] - a.goff[g]);
@@ -312,6 +331,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             const double hq = hs.h * sc;  // h in grid units
             const double Hs = hq * (1.0 + 0x1p-20) + 0x1p-20;
             if (kk == 0) {
+                double tx, ty, tz;
+                grid_pos(tx, ty, tz);
                 act_t[0][p] = tx;
                 act_t[1][p] = ty;
                 act_t[2][p] = tz;
@@ -324,57 +345,58 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             sm.d0 = sm.d1 = sm.dr = 0.0;
             sm.f0 = sm.f1 = sm.fr = sm.c0 = sm.c1 = sm.cr = 0.f;
             sm.n = 0;
-            uint64_t my_cands = 0;
+            uint64_t pass_cands = 0;  // wave total: candidates streamed x particles
             __syncthreads();
 
-            // sub-tiles: lane ranges [la, lb) of the active set
-            int stk_a[7], stk_b[7];
-            int sp = 0;
-            stk_a[sp] = 0;
-            stk_b[sp] = P;
-            ++sp;
-            while (sp > 0) {
-                --sp;
-                const int la = stk_a[sp], lb = stk_b[sp];
+            // sub-tiles: lane ranges [la, lb) of the active set, split in halves
+            // depth first.  The pending ranges always tile [la, P) in order, so
+            // the stack is the bit set of their first lanes.
+            uint64_t starts = 1;
+            while (starts) {
+                const int la = __builtin_ctzll(starts);
+                starts &= starts - 1;
+                const int lb = starts ? __builtin_ctzll(starts) : P;
                 const uint64_t rmask = (lb == 64 ? ~0ull : ((1ull << lb) - 1ull)) &
                                        ~((1ull << la) - 1ull);
                 const uint64_t sub = am & rmask;
                 if (sub == 0) continue;
                 const bool in_sub = ((sub >> p) & 1ull) != 0;
-                double mn0 = wave_min(in_sub ? tx : INFINITY);
-                double mn1 = wave_min(in_sub ? ty : INFINITY);
-                double mn2 = wave_min(in_sub ? tz : INFINITY);
-                double mx0 = wave_max(in_sub ? tx : -INFINITY);
-                double mx1 = wave_max(in_sub ? ty : -INFINITY);
-                double mx2 = wave_max(in_sub ? tz : -INFINITY);
-                const double Hm = wave_max(in_sub ? Hs : 0.0);
+                double tx, ty, tz;
+                grid_pos(tx, ty, tz);
+                const double mn0 = uniform_d(wave_min(in_sub ? tx : INFINITY));
+                const double mn1 = uniform_d(wave_min(in_sub ? ty : INFINITY));
+                const double mn2 = uniform_d(wave_min(in_sub ? tz : INFINITY));
+                const double mx0 = uniform_d(wave_max(in_sub ? tx : -INFINITY));
+                const double mx1 = uniform_d(wave_max(in_sub ? ty : -INFINITY));
+                const double mx2 = uniform_d(wave_max(in_sub ? tz : -INFINITY));
+                const double Hm = uniform_d(wave_max(in_sub ? Hs : 0.0));
                 int ex = ceil_log2_pos(ldexp(Hm, a.cell_exp));
                 int L = B - ex;
                 const int Lmin = GROUPED ? 0 : 1;
                 if (L < Lmin) { L = Lmin; ex = B - L; }
                 const double side = ldexp(1.0, ex);
                 const double inv = ldexp(1.0, -ex);
-                int64_t clo0 = (int64_t)floor((mn0 - Hm) * inv), chi0 = (int64_t)floor((mx0 + Hm) * inv);
-                int64_t clo1 = (int64_t)floor((mn1 - Hm) * inv), chi1 = (int64_t)floor((mx1 + Hm) * inv);
-                int64_t clo2 = (int64_t)floor((mn2 - Hm) * inv), chi2 = (int64_t)floor((mx2 + Hm) * inv);
-                const int64_t ncell = (int64_t)1 << L;
+                // cell coordinates stay within [-2^22, 2^23): 32 bits suffice
+                int32_t clo0 = (int32_t)floor((mn0 - Hm) * inv), chi0 = (int32_t)floor((mx0 + Hm) * inv);
+                int32_t clo1 = (int32_t)floor((mn1 - Hm) * inv), chi1 = (int32_t)floor((mx1 + Hm) * inv);
+                int32_t clo2 = (int32_t)floor((mn2 - Hm) * inv), chi2 = (int32_t)floor((mx2 + Hm) * inv);
+                const int32_t ncell = (int32_t)1 << L;
                 if (GROUPED) {
                     clo0 = clo0 < 0 ? 0 : clo0; clo1 = clo1 < 0 ? 0 : clo1; clo2 = clo2 < 0 ? 0 : clo2;
                     chi0 = chi0 >= ncell ? ncell - 1 : chi0;
                     chi1 = chi1 >= ncell ? ncell - 1 : chi1;
                     chi2 = chi2 >= ncell ? ncell - 1 : chi2;
                 }
-                const int64_t nx = chi0 - clo0 + 1, ny = chi1 - clo1 + 1, nz = chi2 - clo2 + 1;
+                const int32_t nx = chi0 - clo0 + 1, ny = chi1 - clo1 + 1, nz = chi2 - clo2 + 1;
                 if (nx <= 0 || ny <= 0 || nz <= 0) continue;
-                const int64_t K = nx * ny * nz;
+                const int64_t K = (int64_t)nx * ny * nz;
                 if (K > kMaxRegionCells && __popcll(sub) > 1) {
                     // split the active lanes of this range into two halves
                     int cnt = __popcll(sub) / 2;
                     uint64_t t = sub;
                     for (int k = 0; k < cnt; ++k) t &= t - 1;  // drop the lowest cnt lanes
                     const int mid = __ffsll((unsigned long long)t) - 1;
-                    stk_a[sp] = mid; stk_b[sp] = lb; ++sp;
-                    stk_a[sp] = la; stk_b[sp] = mid; ++sp;
+                    starts |= (1ull << la) | (1ull << mid);
                     continue;
                 }
                 // FP32C tile origin: grid coordinates of the first active lane
@@ -390,9 +412,10 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                     bool pass = false;
                     int32_t c_st = 0, c_en = 0, code = 0;
                     if (k < K) {
-                        const int64_t c0 = clo0 + k % nx;
-                        const int64_t c1 = clo1 + (k / nx) % ny;
-                        const int64_t c2 = clo2 + k / (nx * ny);
+                        const int32_t kq = (int32_t)k;
+                        const int32_t c0 = clo0 + kq % nx;
+                        const int32_t c1 = clo1 + (kq / nx) % ny;
+                        const int32_t c2 = clo2 + kq / (nx * ny);
                         const double lo0 = (double)c0 * side - 0x1p-20, hi0 = (double)(c0 + 1) * side + 0x1p-20;
                         const double lo1 = (double)c1 * side - 0x1p-20, hi1 = (double)(c1 + 1) * side + 0x1p-20;
                         const double lo2 = (double)c2 * side - 0x1p-20, hi2 = (double)(c2 + 1) * side + 0x1p-20;
@@ -435,7 +458,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                         rg_code[slot] = code;
                     }
                     __syncthreads();
-                    if (in_sub && kk == 0) my_cands += (uint64_t)total;
+                    pass_cands += (uint64_t)total * (uint64_t)__popcll(sub);
                     for (int cbase = 0; cbase < total; cbase += 64) {
                         const int gidx = cbase + l;
                         if (gidx >= total) {
@@ -562,31 +585,29 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 R += __shfl_xor(R, o, 64);
                 npair += __shfl_xor(npair, o, 64);
             }
+            if (a.stats) {
+                cnt_pairs += uniform_u64(wave_sum<uint64_t>(!done && kk == 0 ? (uint64_t)npair : 0));
+                cnt_cands += pass_cands;
+                cnt_passes += (uint64_t)__popcll(am);
+            }
             if (!done) {
                 const double nwv = (32.0 / 3.0) * S0;
                 const double dndh = -(32.0 / 3.0) * S1 / hs.h;
-                if (kk == 0) {
-                    cnt_pairs += (uint64_t)npair;
-                    cnt_cands += my_cands;
-                    cnt_passes += 1;
-                }
                 const double hcur = hs.h;
                 if (h_step(hs, nwv, dndh, a, hmax)) {
                     const double rho = 8.0 * R / (kPi * hcur * hcur * hcur);
                     if (kk == 0)
-                        write_out(a, oi, rho, hcur, nwv, npair, hs.flags | (hs.it & 0xFFFF));
+                        write_out(a, a.perm[b + p], rho, hcur, nwv, npair,
+                                  hs.flags | (hs.it & 0xFFFF));
                     done = true;
                 }
             }
         }
     }
-    if (a.stats) {
-        const uint64_t p = wave_sum(cnt_pairs), c = wave_sum(cnt_cands), q = wave_sum(cnt_passes);
-        if (l == 0) {
-            atomicAdd((unsigned long long *)&a.stats[0], (unsigned long long)p);
-            atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)c);
-            atomicAdd((unsigned long long *)&a.stats[2], (unsigned long long)q);
-        }
+    if (a.stats && l == 0) {
+        atomicAdd((unsigned long long *)&a.stats[0], (unsigned long long)cnt_pairs);
+        atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)cnt_cands);
+        atomicAdd((unsigned long long *)&a.stats[2], (unsigned long long)cnt_passes);
     }
 }
 

@@ -175,7 +175,7 @@ void sph_default_params(sph_params *p) {
     p->root_tol = 1e-12;
     p->cell_level = -1;
     p->tile_cell = -1;
-    p->waves_per_cu = 8;
+    p->waves_per_cu = 16;
     p->segment = 16;
 }
 

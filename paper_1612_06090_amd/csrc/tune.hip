@@ -29,7 +29,7 @@ std::map<std::string, TuneEntry> g_tune;
 bool g_tune_file_loaded = false;
 
 const int kSegments[] = {8, 16, 32, 64};
-const int kWaves[] = {4, 8, 16};
+const int kWaves[] = {8, 16, 32};
 const int kTileCell[] = {-1, 0};
 
 int floor_log2(int64_t v) {

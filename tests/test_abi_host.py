@@ -62,6 +62,7 @@ def test_default_params():
     assert (p.precision, p.io_dtype, p.mode, p.periodic) == (sph.FP64, sph.F64, sph.BAND, 1)
     assert (p.box, p.n_target, p.n_tol, p.root_tol) == (1.0, 64.0, 2.0, 1e-12)
     assert (p.max_iter, p.cell_level, p.segment, p.tile_cell) == (64, -1, 16, -1)
+    assert p.waves_per_cu == 16
 
 
 def test_workspace_size_monotone_and_valid():

@@ -76,7 +76,7 @@ def test_autotune_and_cache():
     best, ms = sph.autotune(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, d["goff"])
     say(f"  tuned: segment {best.segment} waves/CU {best.waves_per_cu} "
         f"tile_cell {best.tile_cell}: {ms:.3f} ms")
-    assert best.segment in (8, 16, 32, 64) and best.waves_per_cu in (4, 8, 16)
+    assert best.segment in (8, 16, 32, 64) and best.waves_per_cu in (8, 16, 32)
     assert best.tile_cell in (-1, 0) and ms > 0.0
     assert (best.precision, best.n_target, best.periodic) == (p.precision, p.n_target, 0)
     t0 = time.perf_counter()
