@@ -96,7 +96,7 @@ typedef struct {
     int32_t  cell_level;    /* level of the cell table returned by sph_sort;
                                -1 = max(1, ceil((ceil(log2 n) - 3) / 3)) */
     int32_t  tile_cell;     /* tuning: neighbour-cell side in units of the tile's largest
-                               h, as a power of two exponent in {-1, 0} (default -1);
+                               h, as a power of two exponent in {-2, -1, 0} (default -1);
                                results do not depend on it */
     int32_t  waves_per_cu;  /* tuning: persistent grid = 256 CUs x this (default 16) */
     int32_t  segment;       /* tuning: particles per wavefront tile, 8/16/32/64 (default

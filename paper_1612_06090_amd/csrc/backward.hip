@@ -250,11 +250,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
             // one candidate of the leaf list (flat index gidx) into registers
             auto load_cand = [&](int gidx, int total, int nleaf, AdjCand<PREC> &c) {
                 if (gidx < total) {
-                    int lo = 0, hi = nleaf - 1;
-                    while (lo < hi) {
-                        const int mid = (lo + hi + 1) >> 1;
-                        if (S.rg_excl[mid] <= gidx) lo = mid; else hi = mid - 1;
-                    }
+                    const int lo = range_of(S.rg_excl, nleaf, gidx);
                     const int64_t j = (int64_t)S.rg_start[lo] + (gidx - S.rg_excl[lo]);
                     const int cc = S.rg_code[lo];
                     const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1, sh2 = ((cc >> 4) & 3) - 1;

@@ -345,6 +345,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             sm.d0 = sm.d1 = sm.dr = 0.0;
             sm.f0 = sm.f1 = sm.fr = sm.c0 = sm.c1 = sm.cr = 0.f;
             sm.n = 0;
+            float pa0 = 0.f, pa1 = 0.f, par = 0.f;  // FP32C plain partial sums
+            int pchunks = 0;                        // chunks since the last fold
             uint64_t pass_cands = 0;  // wave total: candidates streamed x particles
             __syncthreads();
 
@@ -473,11 +475,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                 c.c[l] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
                             }
                         } else {
-                            int lo = 0, hi = nr - 1;
-                            while (lo < hi) {
-                                const int mid = (lo + hi + 1) >> 1;
-                                if (rg_excl[mid] <= gidx) lo = mid; else hi = mid - 1;
-                            }
+                            const int lo = range_of(rg_excl, nr, gidx);
                             const int64_t j = (int64_t)rg_start[lo] + (gidx - rg_excl[lo]);
                             const int cc = rg_code[lo];
                             const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1,
@@ -502,11 +500,14 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                         }
                         __syncthreads();
                         const int mc = total - cbase < 64 ? total - cbase : 64;  // wave-uniform
-                        const int nu = (mc + S - 1) / S;  // candidates per copy (padded)
+                        // candidates per copy, rounded up to the unroll of 4: the slots
+                        // past mc hold padding, and 4 * ceil(mc / 4S) * S <= 64
+                        const int nu = (((mc + S - 1) / S) + 3) & ~3;
                         if (in_sub) {
                             if (PREC == SPH_FP64) {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
                                 const double hinv = 1.0 / hs.h;
+#pragma unroll 4
                                 for (int u = 0; u < nu; ++u) {
                                     const int t = u * S + kk;
                                     const double dx = (c.x[t] - xi) + c.shx[t];
@@ -530,9 +531,9 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                 }
                             } else {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
-                                // cascade summation: each chunk (<= 64 terms) in plain
-                                // binary32, chunk sums Kahan-compensated into the totals
-                                float a0 = 0.f, a1 = 0.f, ar = 0.f;
+                                // cascade summation: up to 64 terms per lane in plain
+                                // binary32 (S chunks), then Kahan-compensated into the totals
+#pragma unroll 4
                                 for (int u = 0; u < nu; ++u) {
                                     const float4 cj = c.c[u * S + kk];
                                     const float dx = cj.x - pix;
@@ -551,22 +552,31 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                         const float gin = q2 * __builtin_fmaf(18.0f, q, -12.0f);
                                         const float gout = (-6.0f * q) * u2;
                                         const float gq = inner ? gin : gout;
-                                        a0 += f;
-                                        a1 += gq;
-                                        ar = __builtin_fmaf(cj.w, f, ar);
+                                        pa0 += f;
+                                        pa1 += gq;
+                                        par = __builtin_fmaf(cj.w, f, par);
                                         sm.n += 1;
                                     }
                                 }
-                                kahan(sm.f0, sm.c0, a0);
-                                kahan(sm.f1, sm.c1, a1);
-                                kahan(sm.fr, sm.cr, ar);
                             }
+                        }
+                        if (PREC == SPH_FP32C && ++pchunks == S) {
+                            kahan(sm.f0, sm.c0, pa0);
+                            kahan(sm.f1, sm.c1, pa1);
+                            kahan(sm.fr, sm.cr, par);
+                            pa0 = pa1 = par = 0.f;
+                            pchunks = 0;
                         }
                         __syncthreads();
                     }
                 }
             }
 
+            if (PREC == SPH_FP32C) {
+                kahan(sm.f0, sm.c0, pa0);
+                kahan(sm.f1, sm.c1, pa1);
+                kahan(sm.fr, sm.cr, par);
+            }
             double S0, S1, R;
             if (PREC == SPH_FP64) {
                 S0 = sm.d0; S1 = sm.d1; R = sm.dr;

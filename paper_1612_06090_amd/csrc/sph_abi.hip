@@ -134,7 +134,7 @@ static int check_params(const sph_params *p, int64_t n, int32_t G, const int64_t
     if (p->max_iter < 0 || p->max_iter > 65535) return SPH_E_INVALID;
     const int bits = p->periodic ? 21 : 16;
     if (p->cell_level < -1 || p->cell_level > bits || p->cell_level == 0) return SPH_E_INVALID;
-    if (p->tile_cell != 0 && p->tile_cell != -1) return SPH_E_INVALID;
+    if (p->tile_cell < -2 || p->tile_cell > 0) return SPH_E_INVALID;
     if (p->waves_per_cu < 1 || p->waves_per_cu > 32) return SPH_E_INVALID;
     if (p->segment != 8 && p->segment != 16 && p->segment != 32 && p->segment != 64)
         return SPH_E_INVALID;

@@ -189,6 +189,23 @@ __device__ inline int wave_incl_scan(int v) {
     return v;
 }
 
+// Index of the last entry of excl[0..nr) that is <= g, for ascending excl
+// with excl[0] <= g and a wave-uniform nr in [1, 64]: a branch-free binary
+// descent over power-of-two steps (the steps not below nr are skipped by the
+// whole wave).
+__device__ inline int range_of(const int32_t *excl, int nr, int g) {
+    int r = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+        if (step < nr) {
+            const int t = r + step;
+            const int ts = t < nr ? t : nr - 1;
+            r = (t < nr && excl[ts] <= g) ? t : r;
+        }
+    }
+    return r;
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace sph

@@ -81,7 +81,7 @@ def test_workspace_size_monotone_and_valid():
     ("abi_version", 99), ("precision", 7), ("io_dtype", 3), ("mode", 2), ("periodic", 5),
     ("box", 0.0), ("box", float("nan")), ("n_target", 0.0), ("n_tol", -1.0),
     ("max_iter", -1), ("max_iter", 70000), ("cell_level", 22), ("cell_level", 0),
-    ("tile_cell", 3), ("waves_per_cu", 0), ("segment", 12), ("segment", 128),
+    ("tile_cell", 3), ("tile_cell", -3), ("waves_per_cu", 0), ("segment", 12), ("segment", 128),
 ])
 def test_invalid_params_rejected(field, value):
     _lib()
