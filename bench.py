@@ -335,12 +335,38 @@ def summarize_traffic(fetch_csv, write_csv, cmd):
            "fetch_bytes_per_launch": fetch, "write_bytes_per_launch": write,
            "bytes_per_launch": fetch + write,
            "copy_calibration": {"bytes": nbytes, "fetch_factor": kf, "write_factor": kw},
-           "raw_kib": {"fetch_solve": fs, "write_solve": ws, "fetch_copy": fc, "write_copy": wc},
+           "raw_bytes_per_dispatch": {"fetch_solve": fs, "write_solve": ws, "fetch_copy": fc,
+                                      "write_copy": wc},
            "command": cmd}
     os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
     json.dump(out, open(TRAFFIC_JSON, "w"), indent=1)
     print(json.dumps({k: out[k] for k in ("fetch_bytes_per_launch", "write_bytes_per_launch",
                                           "copy_calibration")}))
+
+
+TRACE_MD = os.path.join(ROOT, "profiles", "k_solve_clustered2p20_kernel_trace.md")
+
+
+def summarize_trace(stats_csv, cmd):
+    """Kernel-time table from rocprofv3 --kernel-trace --stats (kernel_stats.csv)."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["# k_solve on clustered2^20 — rocprofv3 kernel trace", "",
+           "Command (GPU box, repo root):", "", "    " + cmd, "",
+           "Workload: the 2^20-particle clustered set (200 Plummer spheres + 30% background), "
+           "N_t = 64 +- 2; one call = keys + radix sort + permute + dense cell table + "
+           "density/h solve. `k_solve<1, ...>` is the FP32C solve, `k_solve<0, ...>` the FP64 "
+           "one, both with 16-particle tiles.", "",
+           f"Solve source sha256: `{solve_source_sha()}`", "",
+           "| Kernel | Calls | Avg (us) | Share |", "|---|---|---|---|"]
+    for r in rows[:14]:
+        name = r["Name"].split("(")[0]
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+                   f"{float(r['Percentage']):.2f}% |")
+    os.makedirs(os.path.dirname(TRACE_MD), exist_ok=True)
+    open(TRACE_MD, "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
 
 
 def main():
@@ -355,9 +381,14 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "CMD"),
+                    help="write the kernel-trace summary from rocprofv3 --stats output")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
                     help="write the k_solve traffic summary from two --pmc runs")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
         return
