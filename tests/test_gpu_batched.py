@@ -128,3 +128,36 @@ def test_graph_replay_matches_eager():
     for k in ("rho", "h", "nw", "nngb", "status"):
         assert torch.equal(out[k], ref2[k]), k
     assert not torch.equal(ref2["rho"], ref["rho"])
+
+
+def test_autotune_file_cache(tmp_path):
+    # a second process reads the first one's result from SPH_TUNE_CACHE and
+    # returns it without timing anything
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys, time, json; sys.path.insert(0, %r)\n"
+        "import torch, sphgen, paper_1612_06090_amd as sph\n"
+        "ps = sphgen.config('groups10k', scale=0.02)\n"
+        "d = {k: torch.tensor(getattr(ps, k), device='cuda') for k in ('x','y','z','m','h_init')}\n"
+        "goff = torch.tensor(ps.offsets, device='cuda')\n"
+        "p = sph.default_params(periodic=0, n_target=32.0, n_tol=1.0, precision=sph.FP32C)\n"
+        "t = time.perf_counter()\n"
+        "b, ms = sph.autotune(d['x'], d['y'], d['z'], d['m'], d['h_init'], p, goff)\n"
+        "print(json.dumps([b.segment, b.waves_per_cu, b.tile_cell, ms, time.perf_counter() - t]))\n"
+    ) % root
+    env = dict(os.environ, SPH_TUNE_CACHE=str(tmp_path / "tune.txt"))
+    runs = []
+    for _ in range(2):
+        out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True,
+                             text=True, timeout=240)
+        assert out.returncode == 0, out.stderr[-2000:]
+        runs.append(json.loads(out.stdout.strip().splitlines()[-1]))
+    say(f"  first {runs[0]}, second {runs[1]}")
+    assert runs[0][:3] == runs[1][:3]
+    assert abs(runs[0][3] - runs[1][3]) <= 1e-5 * runs[0][3]   # the file keeps 6 digits
+    assert runs[1][4] < 0.05
+    assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1
