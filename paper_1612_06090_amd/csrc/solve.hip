@@ -401,10 +401,11 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                     starts |= (1ull << la) | (1ull << mid);
                     continue;
                 }
-                // FP32C tile origin: grid coordinates of the first active lane
-                const int first = __ffsll((unsigned long long)sub) - 1;
-                const int32_t o0 = readlane_i(qxi, first), o1 = readlane_i(qyi, first),
-                              o2 = readlane_i(qzi, first);
+                // FP32C origin: the grid point at the centre of the sub-tile's box, so
+                // that the binary32 coordinates of the region are as small as they can be
+                const int32_t o0 = (int32_t)floor(0.5 * (mn0 + mx0));
+                const int32_t o1 = (int32_t)floor(0.5 * (mn1 + mx1));
+                const int32_t o2 = (int32_t)floor(0.5 * (mn2 + mx2));
                 const float pix = (float)(qxi - o0) + fxi;
                 const float piy = (float)(qyi - o1) + fyi;
                 const float piz = (float)(qzi - o2) + fzi;
@@ -515,17 +516,18 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                     const double dz = (c.z[t] - zi) + c.shz[t];
                                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                                     if (r2 < h2) {
+                                        // the spline in the form of the FP32C path (factors
+                                        // 2 and 6 applied to the totals)
                                         const double q = sqrt(r2) * hinv;
-                                        const double q2 = q * q;
                                         const double u = 1.0 - q;
-                                        const bool inner = q <= 0.5;
-                                        const double f = inner ? 1.0 - 6.0 * q2 + 6.0 * q2 * q
-                                                               : 2.0 * u * u * u;
-                                        const double gq = inner ? q2 * (18.0 * q - 12.0)
-                                                                : -6.0 * q * u * u;
-                                        sm.d0 += f;
-                                        sm.d1 += gq;
-                                        sm.dr += c.m[t] * f;
+                                        const double v = fmax(0.5 - q, 0.0);
+                                        const double u2 = u * u;
+                                        const double v2 = v * v;
+                                        const double fh = u2 * u - 4.0 * v * v2;
+                                        const double gs = q * (4.0 * v2 - u2);
+                                        sm.d0 += fh;
+                                        sm.d1 += gs;
+                                        sm.dr += c.m[t] * fh;
                                         sm.n += 1;
                                     }
                                 }
@@ -541,20 +543,20 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                     const float dz = cj.z - piz;
                                     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
                                     if (r2 < h2f) {
-                                        const float q2 = fminf(r2 * ih2, 1.0f);
-                                        const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
+                                        // f(q) = 2 (u^3 - 4 v^3) and q f'(q) = 6 q (4 v^2 - u^2)
+                                        // with u = 1 - q, v = max(1/2 - q, 0): one form for
+                                        // both spline pieces; the factors 2 and 6 are applied
+                                        // to the totals
+                                        const float q = __builtin_amdgcn_sqrtf(r2 * ih2);  // 1 ulp
                                         const float u = 1.0f - q;
-                                        const bool inner = q <= 0.5f;
-                                        const float fin = __builtin_fmaf(q2, __builtin_fmaf(6.0f, q, -6.0f), 1.0f);
+                                        const float v = fminf(fmaxf(0.5f - q, 0.0f), 1.0f);
                                         const float u2 = u * u;
-                                        const float fout = (2.0f * u) * u2;
-                                        const float f = inner ? fin : fout;
-                                        const float gin = q2 * __builtin_fmaf(18.0f, q, -12.0f);
-                                        const float gout = (-6.0f * q) * u2;
-                                        const float gq = inner ? gin : gout;
-                                        pa0 += f;
-                                        pa1 += gq;
-                                        par = __builtin_fmaf(cj.w, f, par);
+                                        const float v2 = v * v;
+                                        const float fh = __builtin_fmaf(-4.0f * v, v2, u2 * u);
+                                        const float gs = q * __builtin_fmaf(4.0f, v2, -u2);
+                                        pa0 += fh;
+                                        pa1 += gs;
+                                        par = __builtin_fmaf(cj.w, fh, par);
                                         sm.n += 1;
                                     }
                                 }
@@ -579,11 +581,11 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             }
             double S0, S1, R;
             if (PREC == SPH_FP64) {
-                S0 = sm.d0; S1 = sm.d1; R = sm.dr;
+                S0 = 2.0 * sm.d0; S1 = 6.0 * sm.d1; R = 2.0 * sm.dr;
             } else {
-                S0 = (double)sm.f0 - (double)sm.c0;
-                S1 = (double)sm.f1 - (double)sm.c1;
-                R = (double)sm.fr - (double)sm.cr;
+                S0 = 2.0 * ((double)sm.f0 - (double)sm.c0);
+                S1 = 6.0 * ((double)sm.f1 - (double)sm.c1);
+                R = 2.0 * ((double)sm.fr - (double)sm.cr);
             }
             int32_t npair = sm.n;
             // combine the S copies of each particle: a butterfly of commutative
