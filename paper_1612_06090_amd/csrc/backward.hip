@@ -152,8 +152,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
             b = a.goff[g] + (int64_t)(item - a.gitems[lo]) * kAdjP;
             e = b + kAdjP < a.goff[g + 1] ? b + kAdjP : a.goff[g + 1];
             const double *f = a.frame + 8 * (int64_t)g;
-            org0 = f[0]; org1 = f[1]; org2 = f[2];
-            sc = f[6];
+            org0 = uniform_dbl(f[0]); org1 = uniform_dbl(f[1]); org2 = uniform_dbl(f[2]);
+            sc = uniform_dbl(f[6]);
         }
         const int64_t s = b + p;
         const bool mine = s < e;
@@ -196,7 +196,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
         const int64_t gbase = GROUPED ? a.goff[g] : 0;
         const int64_t gend = GROUPED ? a.goff[g + 1] : a.n;
         float hall = 0.f;  // largest h of the set (phase 2: any sphere may reach)
-        if (a.phase == 2 && vm != 0) hall = range_hmax(a, (int32_t)gbase, (int32_t)gend);
+        if (a.phase == 2 && vm != 0)
+            hall = uniform_f(range_hmax(a, (int32_t)gbase, (int32_t)gend));
 
         // Particle ranges of the tile, each walked on its own.  A range whose
         // bounding box is wide compared with its radius (it straddles distant
@@ -219,10 +220,13 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
             const float pk0 = (float)(qxk - t0) + fxk;
             const float pk1 = (float)(qyk - t1) + fyk;
             const float pk2 = (float)(qzk - t2) + fzk;
-            const float mn0 = wave_min(in_sub ? pk0 : INFINITY), mx0 = wave_max(in_sub ? pk0 : -INFINITY);
-            const float mn1 = wave_min(in_sub ? pk1 : INFINITY), mx1 = wave_max(in_sub ? pk1 : -INFINITY);
-            const float mn2 = wave_min(in_sub ? pk2 : INFINITY), mx2 = wave_max(in_sub ? pk2 : -INFINITY);
-            const float Ht = wave_max(in_sub ? Hk : 0.f);
+            const float mn0 = uniform_f(wave_min(in_sub ? pk0 : INFINITY));
+            const float mx0 = uniform_f(wave_max(in_sub ? pk0 : -INFINITY));
+            const float mn1 = uniform_f(wave_min(in_sub ? pk1 : INFINITY));
+            const float mx1 = uniform_f(wave_max(in_sub ? pk1 : -INFINITY));
+            const float mn2 = uniform_f(wave_min(in_sub ? pk2 : INFINITY));
+            const float mx2 = uniform_f(wave_max(in_sub ? pk2 : -INFINITY));
+            const float Ht = uniform_f(wave_max(in_sub ? Hk : 0.f));
             const float ext = fmaxf(mx0 - mn0, fmaxf(mx1 - mn1, mx2 - mn2));
             if (ext > kSplitExtent * Ht && __popcll(sm) > 1) {
                 // lower half of the valid particles, then the upper half

@@ -140,6 +140,19 @@ __device__ inline uint32_t mbcnt(uint64_t m) {
 
 __device__ inline int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 
+// Values every lane of the wave already holds (results of a full-wave
+// reduction or broadcast), moved to scalar registers.
+__device__ inline float uniform_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+
+__device__ inline double uniform_dbl(double v) {
+    int2 b = __builtin_bit_cast(int2, v);
+    b.x = __builtin_amdgcn_readfirstlane(b.x);
+    b.y = __builtin_amdgcn_readfirstlane(b.y);
+    return __builtin_bit_cast(double, b);
+}
+
 __device__ inline double readlane_d(double v, int l) {
     int2 a = __builtin_bit_cast(int2, v);
     a.x = __builtin_amdgcn_readlane(a.x, l);
