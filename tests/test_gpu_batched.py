@@ -161,3 +161,32 @@ def test_autotune_file_cache(tmp_path):
     assert abs(runs[0][3] - runs[1][3]) <= 1e-5 * runs[0][3]   # the file keeps 6 digits
     assert runs[1][4] < 0.05
     assert len((tmp_path / "tune.txt").read_text().splitlines()) == 1
+
+
+def test_maximum_group_count():
+    # 65535 groups (the limit), sizes 0..4 and a few large ones: sort, solve
+    # and adjoint against the oracle
+    rng = np.random.default_rng(63)
+    sizes = rng.integers(0, 5, 65535)
+    sizes[rng.choice(65535, 5, replace=False)] = 3000
+    ps = sphgen.groups(65535, seed=64, sizes=sizes, n_target=8.0, n_tol=1.0)
+    say(f"[batched] G=65535 n={ps.n}")
+    g = gpu_solve(ps)
+    e = oracle.eval_at_h(ps, g["h"], search=1)
+    assert np.array_equal(g["nngb"], e["nngb"].astype(np.int32))
+    o = oracle.solve(ps)
+    same = rel(g["h"], o["h"]) <= 1e-12
+    assert same.mean() >= 0.999
+    assert rel(g["rho"][same], o["rho"][same]).max() < 1e-12
+    from gpu_util import gpu_backward
+    gr = sphgen.cotangent(ps.n, 65)
+    b = gpu_backward(ps, g["h"], gr)
+    ob = oracle.backward(ps, g["h"], gr)
+    for k in ("gx", "gy", "gz", "gm"):
+        assert np.abs(b[k] - ob[k]).max() <= 1e-11 * np.abs(ob[k]).max(), k
+    s = sph.sort(*(dev_arrays(ps)[k] for k in ("x", "y", "z")),
+                 params_for(ps), dev_arrays(ps)["goff"])
+    import torch
+    torch.cuda.synchronize()
+    ok = oracle.sort(ps)
+    assert np.array_equal(s["perm"].cpu().numpy(), ok["perm"].astype(np.int32))
