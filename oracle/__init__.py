@@ -66,6 +66,7 @@ class _Cfg(C.Structure):
         ("max_iter", C.c_int32),
         ("search", C.c_int32),
         ("nthreads", C.c_int32),
+        ("kernel", C.c_int32),
     ]
 
 
@@ -81,6 +82,15 @@ def lib():
         L.oracle_kernel_dfdq.argtypes = [C.c_double]
         L.oracle_kernel_W.restype = C.c_double
         L.oracle_kernel_W.argtypes = [C.c_double, C.c_double]
+        for name in ("oracle_wendland6_f", "oracle_wendland6_dfdq"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_double]
+        for name in ("oracle_f", "oracle_dfdq"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_int32, C.c_double]
+        for name in ("oracle_sigma", "oracle_count_const"):
+            getattr(L, name).restype = C.c_double
+            getattr(L, name).argtypes = [C.c_int32]
         L.oracle_morton_periodic.argtypes = [C.c_int64, P, P, P, C.c_double, P]
         L.oracle_morton_groups.argtypes = [C.c_int64, C.c_int32, P, P, P, P, P]
         L.oracle_group_frames.argtypes = [C.c_int32, P, P, P, P, P, P]
@@ -118,6 +128,36 @@ def kernel_dfdq(q: float) -> float:
 
 def kernel_W(r: float, h: float) -> float:
     return lib().oracle_kernel_W(float(r), float(h))
+
+
+M4, WENDLAND_C6 = 0, 1
+
+
+def wendland6_f(q: float) -> float:
+    return lib().oracle_wendland6_f(float(q))
+
+
+def wendland6_dfdq(q: float) -> float:
+    return lib().oracle_wendland6_dfdq(float(q))
+
+
+def shape_f(kernel: int, q: float) -> float:
+    """f(q) of the selected kernel (M4 or WENDLAND_C6)."""
+    return lib().oracle_f(int(kernel), float(q))
+
+
+def shape_dfdq(kernel: int, q: float) -> float:
+    return lib().oracle_dfdq(int(kernel), float(q))
+
+
+def sigma(kernel: int) -> float:
+    """Normalisation: W(r, h) = sigma / h^3 f(r/h)."""
+    return lib().oracle_sigma(int(kernel))
+
+
+def count_const(kernel: int) -> float:
+    """C in n = C sum_j f(r_ij / h)."""
+    return lib().oracle_count_const(int(kernel))
 
 
 def max_threads() -> int:
@@ -190,7 +230,7 @@ def sort(ps):
                 cell_start=st, cell_count=ct)
 
 
-def _cfg(ps, mode=BAND, root_tol=1e-12, max_iter=64, search=1, nthreads=0):
+def _cfg(ps, mode=BAND, root_tol=1e-12, max_iter=64, search=1, nthreads=0, kernel=M4):
     off = None if ps.offsets is None else np.ascontiguousarray(ps.offsets, dtype=np.int64)
     c = _Cfg(
         periodic=1 if ps.periodic else 0, box=float(ps.box),
@@ -198,14 +238,14 @@ def _cfg(ps, mode=BAND, root_tol=1e-12, max_iter=64, search=1, nthreads=0):
         offsets=None if off is None else off.ctypes.data,
         n_target=float(ps.n_target), n_tol=float(ps.n_tol), mode=int(mode),
         root_tol=float(root_tol), max_iter=int(max_iter), search=int(search),
-        nthreads=int(nthreads),
+        nthreads=int(nthreads), kernel=int(kernel),
     )
     return c, off
 
 
-def eval_at_h(ps, h, search=1, nthreads=0):
+def eval_at_h(ps, h, search=1, nthreads=0, kernel=M4):
     """rho, n, dn/dh, drho/dh and the integer neighbour count at given h."""
-    c, _keep = _cfg(ps, search=search, nthreads=nthreads)
+    c, _keep = _cfg(ps, search=search, nthreads=nthreads, kernel=kernel)
     x, y, z, m, h = _d(ps.x), _d(ps.y), _d(ps.z), _d(ps.m), _d(h)
     n = x.shape[0]
     rho, nw, dndh, drhodh = (np.empty(n) for _ in range(4))
@@ -216,14 +256,14 @@ def eval_at_h(ps, h, search=1, nthreads=0):
 
 
 def solve(ps, h_init=None, subset=None, mode=BAND, root_tol=1e-12, max_iter=64, search=1,
-          nthreads=0):
+          nthreads=0, kernel=M4):
     """Per-particle h iteration; returns rho, h, nw, dndh, nngb, status, pairs.
 
     With ``subset`` (array of particle indices) only those particles are
     solved, each against the full set, and outputs follow ``subset``'s order.
     """
     c, _keep = _cfg(ps, mode=mode, root_tol=root_tol, max_iter=max_iter, search=search,
-                    nthreads=nthreads)
+                    nthreads=nthreads, kernel=kernel)
     x, y, z, m = _d(ps.x), _d(ps.y), _d(ps.z), _d(ps.m)
     h0 = _d(ps.h_init if h_init is None else h_init)
     n = x.shape[0]
@@ -238,12 +278,12 @@ def solve(ps, h_init=None, subset=None, mode=BAND, root_tol=1e-12, max_iter=64, 
     return dict(rho=rho, h=h, nw=nw, dndh=dndh, nngb=nngb, status=status, pairs=pairs)
 
 
-def backward(ps, h, grad_rho, grad_h=None, search=1, nthreads=0, x=None, m=None):
+def backward(ps, h, grad_rho, grad_h=None, search=1, nthreads=0, x=None, m=None, kernel=M4):
     """Analytic adjoint (gx, gy, gz, gm) of sum(grad_rho*rho + grad_h*h).
 
     ``x`` (an (n,3) array) and ``m`` override the set's positions / masses.
     """
-    c, _keep = _cfg(ps, search=search, nthreads=nthreads)
+    c, _keep = _cfg(ps, search=search, nthreads=nthreads, kernel=kernel)
     if x is None:
         px, py, pz = _d(ps.x), _d(ps.y), _d(ps.z)
     else:

@@ -25,9 +25,13 @@
  *     path's spatial sort; no counterpart in the paper, whose tree is given);
  *   - the analytic adjoint of the density with h held on its implicit root.
  *
- * Kernel: M4 cubic spline with compact support h (the Gadget-2 convention),
- * W(r,h) = 8/(pi h^3) f(r/h).  The paper's runs use Wendland C6; the M4
- * spline is the standard Gadget-2 kernel and is what this path evaluates.
+ * Kernels (cfg.kernel), both with compact support h, W(r,h) = sigma/h^3 f(r/h):
+ *   0  M4 cubic spline (the Gadget-2 convention), sigma = 8/pi:
+ *      f = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1);
+ *   1  Wendland C6, the kernel of the paper's runs (Sec. II-C), in its 3D
+ *      normalisation, sigma = 1365/(64 pi):  f = (1-q)^8 (1 + 8q + 25q^2 + 32q^3).
+ * The weighted neighbour count is n = (4 pi/3) h^3 sum_j W = C sum_j f with
+ * C = (4 pi/3) sigma (32/3 and 1365/48).
  *
  * Parity pins for every function here live in the CPU test-suite
  * (normalisation integral, brute force vs k-d tree, lattice sums, closed-form
@@ -61,6 +65,7 @@ typedef struct {
     int32_t max_iter;       /* 0: evaluate at h_init only */
     int32_t search;         /* 0: brute force ; 1: k-d tree */
     int32_t nthreads;       /* <= 0: OpenMP default */
+    int32_t kernel;         /* 0: M4 cubic spline ; 1: Wendland C6 */
 } orc_cfg;
 
 /* ------------------------------------------------------------------ kernel */
@@ -92,6 +97,46 @@ double oracle_kernel_dfdq(double q)
 double oracle_kernel_W(double r, double h)
 {
     return 8.0 / (ORC_PI * h * h * h) * oracle_kernel_f(r / h);
+}
+
+/* f(q) of the Wendland C6 function with support q < 1. */
+double oracle_wendland6_f(double q)
+{
+    if (q < 0.0) q = -q;
+    if (q >= 1.0) return 0.0;
+    double t = 1.0 - q;
+    double t2 = t * t, t4 = t2 * t2, t8 = t4 * t4;
+    return t8 * (1.0 + 8.0 * q + 25.0 * q * q + 32.0 * q * q * q);
+}
+
+/* df/dq of the same function: -22 q (1-q)^7 (1 + 7q + 16q^2). */
+double oracle_wendland6_dfdq(double q)
+{
+    if (q >= 1.0) return 0.0;
+    double t = 1.0 - q;
+    double t2 = t * t, t4 = t2 * t2, t7 = t4 * t2 * t;
+    return -22.0 * q * t7 * (1.0 + 7.0 * q + 16.0 * q * q);
+}
+
+/* Kernel selected by id: shape, normalisation sigma and count constant C. */
+double oracle_f(int32_t kernel, double q)
+{
+    return kernel == 1 ? oracle_wendland6_f(q) : oracle_kernel_f(q);
+}
+
+double oracle_dfdq(int32_t kernel, double q)
+{
+    return kernel == 1 ? oracle_wendland6_dfdq(q) : oracle_kernel_dfdq(q);
+}
+
+double oracle_sigma(int32_t kernel)
+{
+    return kernel == 1 ? 1365.0 / (64.0 * ORC_PI) : 8.0 / ORC_PI;
+}
+
+double oracle_count_const(int32_t kernel)
+{
+    return kernel == 1 ? 1365.0 / 48.0 : 32.0 / 3.0;
 }
 
 /* ---------------------------------------------------------------- geometry */
@@ -390,11 +435,11 @@ typedef struct {
     int64_t N;  /* pairs with r^2 < h^2   */
 } sums_t;
 
-static void add_pair(sums_t *s, double r2, double h, double mj)
+static void add_pair(sums_t *s, int32_t kernel, double r2, double h, double mj)
 {
     double q = sqrt(r2) / h;
-    double f = oracle_kernel_f(q);
-    double fp = oracle_kernel_dfdq(q);
+    double f = oracle_f(kernel, q);
+    double fp = oracle_dfdq(kernel, q);
     s->S0 += f;
     s->S1 += q * fp;
     s->R += mj * f;
@@ -511,13 +556,13 @@ static void visit(const ctx_t *k, int64_t i, double h, visit_fn fn, void *u)
     else visit_brute(k, i, h, fn, u);
 }
 
-typedef struct { sums_t s; double h; const double *m; } sum_acc;
+typedef struct { sums_t s; double h; const double *m; int32_t kernel; } sum_acc;
 
 static void sum_visit(void *u, int64_t j, double r2, const double *d)
 {
     (void)d;
     sum_acc *a = (sum_acc *)u;
-    add_pair(&a->s, r2, a->h, a->m[j]);
+    add_pair(&a->s, a->kernel, r2, a->h, a->m[j]);
 }
 
 static sums_t eval_sums(const ctx_t *k, int64_t i, double h)
@@ -526,6 +571,7 @@ static sums_t eval_sums(const ctx_t *k, int64_t i, double h)
     memset(&a, 0, sizeof(a));
     a.h = h;
     a.m = k->m;
+    a.kernel = k->c->kernel;
     visit(k, i, h, sum_visit, &a);
     return a.s;
 }
@@ -585,8 +631,8 @@ int32_t oracle_max_threads(void)
 }
 
 /* Density and its h-derivatives at given smoothing lengths (no iteration).
- * rho = 8 R/(pi h^3), n = (32/3) S0, dn/dh = -(32/3) S1/h,
- * drho/dh = -8 A/(pi h^4). Any output pointer may be NULL. */
+ * rho = sigma R/h^3, n = C S0, dn/dh = -C S1/h, drho/dh = -sigma A/h^4
+ * (M4: sigma = 8/pi, C = 32/3). Any output pointer may be NULL. */
 void oracle_eval_at_h(const orc_cfg *c, int64_t n, const double *x, const double *y,
                       const double *z, const double *m, const double *h, double *rho,
                       double *nw, double *dndh, double *drhodh, int64_t *nngb)
@@ -606,10 +652,11 @@ void oracle_eval_at_h(const orc_cfg *c, int64_t n, const double *x, const double
         }
         double hi = h[i];
         sums_t s = eval_sums(&k, i, hi);
-        if (rho) rho[i] = 8.0 * s.R / (ORC_PI * hi * hi * hi);
-        if (nw) nw[i] = (32.0 / 3.0) * s.S0;
-        if (dndh) dndh[i] = -(32.0 / 3.0) * s.S1 / hi;
-        if (drhodh) drhodh[i] = -8.0 * s.A / (ORC_PI * hi * hi * hi * hi);
+        const double sg = oracle_sigma(c->kernel), cc = oracle_count_const(c->kernel);
+        if (rho) rho[i] = sg * s.R / (hi * hi * hi);
+        if (nw) nw[i] = cc * s.S0;
+        if (dndh) dndh[i] = -cc * s.S1 / hi;
+        if (drhodh) drhodh[i] = -sg * s.A / (hi * hi * hi * hi);
         if (nngb) nngb[i] = s.N;
     }
     ctx_free(&k);
@@ -645,7 +692,7 @@ static solve_out solve_one(const ctx_t *k, int64_t i)
     int fixed = c->max_iter == 0;
     if (c->ngroups > 0) {
         int64_t g = k->dom[i];
-        double nmax = (32.0 / 3.0) * (double)(c->offsets[g + 1] - c->offsets[g]);
+        double nmax = oracle_count_const(c->kernel) * (double)(c->offsets[g + 1] - c->offsets[g]);
         if (nmax < Nt - dN) { flags |= ORC_UNREACHABLE; fixed = 1; }
     }
     if (h > hmax) h = hmax;
@@ -656,8 +703,8 @@ static solve_out solve_one(const ctx_t *k, int64_t i)
     for (;;) {
         s = eval_sums(k, i, h);
         o.pairs += s.N;
-        nwv = (32.0 / 3.0) * s.S0;
-        dndh = -(32.0 / 3.0) * s.S1 / h;
+        nwv = oracle_count_const(c->kernel) * s.S0;
+        dndh = -oracle_count_const(c->kernel) * s.S1 / h;
         if (fixed) break;
         int conv;
         if (c->mode == 0) {
@@ -688,7 +735,7 @@ static solve_out solve_one(const ctx_t *k, int64_t i)
         ++it;
     }
     o.h = h;
-    o.rho = 8.0 * s.R / (ORC_PI * h * h * h);
+    o.rho = oracle_sigma(c->kernel) * s.R / (h * h * h);
     o.nw = nwv;
     o.dndh = dndh;
     o.nngb = (int32_t)s.N;
@@ -728,19 +775,21 @@ typedef struct {
     double h, gr, lam;
     const double *m;
     double *gx, *gy, *gz, *gm;
+    int32_t kernel;
 } bw_acc;
 
 static void bw_visit(void *u, int64_t j, double r2, const double *d)
 {
     bw_acc *a = (bw_acc *)u;
     const double hi = a->h;
-    const double cW = 8.0 / (ORC_PI * hi * hi * hi);
+    const double cW = oracle_sigma(a->kernel) / (hi * hi * hi);
     double r = sqrt(r2);
     double q = r / hi;
-    a->gm[j] += a->gr * cW * oracle_kernel_f(q);
+    a->gm[j] += a->gr * cW * oracle_f(a->kernel, q);
     if (j == a->i || r == 0.0) return;
-    double fp = oracle_kernel_dfdq(q);
-    double cij = a->gr * a->m[j] * cW / hi * fp + a->lam * (32.0 / 3.0) * fp / hi;
+    double fp = oracle_dfdq(a->kernel, q);
+    double cij = a->gr * a->m[j] * cW / hi * fp
+               + a->lam * oracle_count_const(a->kernel) * fp / hi;
     /* unit vector u = (x_i - x_j)/r = -d/r */
     double ux = -d[0] / r, uy = -d[1] / r, uz = -d[2] / r;
     a->gx[a->i] += cij * ux; a->gy[a->i] += cij * uy; a->gz[a->i] += cij * uz;
@@ -751,7 +800,7 @@ static void bw_visit(void *u, int64_t j, double r2, const double *d)
  * root n_i(h_i, x) = n_i(achieved).  For a cotangent (gr, gh):
  *   lambda_i = -(gr_i drho_i/dh_i + gh_i) / (dn_i/dh_i)      (0 if dn/dh = 0)
  *   pair (i, j in N(i), j != i), q = r_ij/h_i, u = (x_i - x_j)/r_ij:
- *     c_ij = gr_i m_j 8/(pi h_i^4) f'(q) + lambda_i (32/3) f'(q) / h_i
+ *     c_ij = gr_i m_j sigma/h_i^4 f'(q) + lambda_i C f'(q) / h_i
  *     gx_i += c_ij u ;  gx_j -= c_ij u
  *   mass: gm_j += gr_i W(r_ij, h_i)   (self term included; n is number-
  *   weighted, so h does not depend on the masses).
@@ -770,8 +819,8 @@ void oracle_backward(const orc_cfg *c, int64_t n, const double *x, const double 
         if (!k.valid[i]) continue;
         double hi = h[i];
         sums_t s = eval_sums(&k, i, hi);
-        double drhodh = -8.0 * s.A / (ORC_PI * hi * hi * hi * hi);
-        double dndh = -(32.0 / 3.0) * s.S1 / hi;
+        double drhodh = -oracle_sigma(c->kernel) * s.A / (hi * hi * hi * hi);
+        double dndh = -oracle_count_const(c->kernel) * s.S1 / hi;
         double gh = grad_h ? grad_h[i] : 0.0;
         if (dndh > 0.0) lam[i] = -(grad_rho[i] * drhodh + gh) / dndh;
     }
@@ -780,6 +829,7 @@ void oracle_backward(const orc_cfg *c, int64_t n, const double *x, const double 
         if (!k.valid[i]) continue;
         bw_acc a;
         a.i = i; a.h = h[i]; a.gr = grad_rho[i]; a.lam = lam[i]; a.m = m;
+        a.kernel = c->kernel;
         a.gx = gx; a.gy = gy; a.gz = gz; a.gm = gm;
         visit(&k, i, h[i], bw_visit, &a);
     }

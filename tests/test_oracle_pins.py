@@ -67,6 +67,104 @@ def test_kernel_defining_properties():
     assert np.all(np.diff(vals) <= 0.0)
 
 
+# ------------------------------------------------- Wendland C6 (kernel 1)
+
+
+def test_wendland6_normalisation_exact():
+    # q^2 f(q) is a polynomial of degree 13 on [0, 1]: 8-point Gauss-Legendre
+    # is exact, and 4 pi sigma int_0^1 q^2 f(q) dq must be 1.  The integral
+    # itself is the rational 16/1365 (sum of Beta integrals of the monomials).
+    xg, wg = np.polynomial.legendre.leggauss(8)
+    q = 0.5 * xg + 0.5
+    tot = 0.5 * sum(w * qq * qq * oracle.wendland6_f(qq) for qq, w in zip(q, wg))
+    from fractions import Fraction
+    beta = [Fraction(math.factorial(2 + k) * math.factorial(8), math.factorial(11 + k))
+            for k in range(4)]
+    exact = sum(c * b for c, b in zip((1, 8, 25, 32), beta))
+    assert exact == Fraction(16, 1365)
+    assert abs(tot - 16.0 / 1365.0) < 1e-16
+    assert abs(4.0 * math.pi * oracle.sigma(oracle.WENDLAND_C6) * tot - 1.0) < 1e-14
+    # n = (4 pi/3) h^3 sum W: C = (4 pi/3) sigma for both kernels
+    for k in (oracle.M4, oracle.WENDLAND_C6):
+        assert abs(oracle.count_const(k) - 4.0 * math.pi / 3.0 * oracle.sigma(k)) < 1e-14
+
+
+def test_wendland6_defining_properties():
+    # (1-q)^8 P(q): f(0) = 1, f'(0) = 0, derivatives through order 7 vanish
+    # at q = 1 (so f(1 - e) = O(e^8)), positive and decreasing on [0, 1)
+    f, fp = oracle.wendland6_f, oracle.wendland6_dfdq
+    assert f(0.0) == 1.0 and fp(0.0) == 0.0
+    for q in (1.0, 1.5, 3.0):
+        assert f(q) == 0.0 and fp(q) == 0.0
+    eps = 1e-5
+    for q in np.linspace(0.01, 0.99, 37):
+        fd = (f(q + eps) - f(q - eps)) / (2 * eps)
+        assert abs(fd - fp(q)) < 1e-8, q
+    for e in (1e-1, 1e-2):
+        assert 0.0 < f(1.0 - e) < 100.0 * e ** 8
+    qs = np.linspace(0.0, 1.0, 2001)
+    vals = np.array([f(q) for q in qs])
+    assert np.all(vals >= 0.0) and np.all(np.diff(vals) <= 0.0)
+    # selection by kernel id
+    for q in (0.0, 0.3, 0.7):
+        assert oracle.shape_f(oracle.WENDLAND_C6, q) == f(q)
+        assert oracle.shape_f(oracle.M4, q) == oracle.kernel_f(q)
+        assert oracle.shape_dfdq(oracle.WENDLAND_C6, q) == fp(q)
+
+
+@pytest.mark.parametrize("y", [0.05, 0.3, 0.7])
+def test_wendland6_two_particle_root(y):
+    # n(h) = C (1 + f(d/h)) for h > d; N_t = C (1 + y): q* solves f(q) = y,
+    # found here to 40 digits from the polynomial with mpmath
+    d = 0.3
+    C = oracle.count_const(oracle.WENDLAND_C6)
+    nt = C * (1.0 + y)
+    mpmath.mp.dps = 40
+    fq = lambda q: (1 - q) ** 8 * (1 + 8 * q + 25 * q ** 2 + 32 * q ** 3) - mpmath.mpf(y)
+    qs = mpmath.findroot(fq, (mpmath.mpf("1e-9"), mpmath.mpf(1) - mpmath.mpf("1e-9")),
+                         solver="bisect")
+    h_exact = float(mpmath.mpf(d) / qs)
+    ps = _two_particles(d, nt)
+    s = oracle.solve(ps, mode=oracle.ROOT, root_tol=1e-15, search=0,
+                     kernel=oracle.WENDLAND_C6)
+    assert np.all((s["status"] >> 16) == 0)
+    np.testing.assert_allclose(s["h"], h_exact, rtol=1e-13)
+
+
+@pytest.mark.parametrize("ha", [5.0, 6.0])
+def test_wendland6_lattice_riemann_limit(ha):
+    # as for M4: rho -> m / a^3 = 1 for h >> a (2.3e-5 off at h = 5a)
+    nside = 16
+    ps = sphgen.lattice(nside, h=ha / nside)
+    e = oracle.eval_at_h(ps, ps.h_init, search=1, kernel=oracle.WENDLAND_C6)
+    assert np.ptp(e["rho"]) < 1e-13
+    assert abs(e["rho"].mean() - 1.0) < 5e-5
+
+
+def test_wendland6_poisson_statistics():
+    # E[n_i] = C + (4 pi/3) h^3 (N - 1) whatever the kernel (unit normalisation)
+    ps = sphgen.uniform(20000, seed=13)
+    h = np.full(ps.n, 0.08)
+    e = oracle.eval_at_h(ps, h, search=1, kernel=oracle.WENDLAND_C6)
+    vol = 4.0 * math.pi / 3.0 * 0.08 ** 3 * (ps.n - 1)
+    C = oracle.count_const(oracle.WENDLAND_C6)
+    assert abs(e["nw"].mean() - (C + vol)) < 0.01 * vol
+    assert np.all(e["nw"] >= C)
+
+
+def test_wendland6_self_only_and_unreachable():
+    ps = sphgen.lattice(4, h=0.1)
+    e = oracle.eval_at_h(ps, ps.h_init, search=0, kernel=oracle.WENDLAND_C6)
+    assert np.all(e["nngb"] == 1)
+    assert np.all(e["nw"] == 1365.0 / 48.0)
+    # an isolated 3-particle group reaches at most 3 C < 295 - 2
+    grp = sphgen.ParticleSet(x=np.array([0.0, 0.1, 0.2]), y=np.zeros(3), z=np.zeros(3),
+                             m=np.ones(3), h_init=np.full(3, 0.05), periodic=False, box=1.0,
+                             n_target=295.0, n_tol=2.0, offsets=np.array([0, 3]))
+    s = oracle.solve(grp, search=0, kernel=oracle.WENDLAND_C6)
+    assert np.all((s["status"] & oracle.ST_UNREACHABLE) != 0)
+
+
 # ----------------------------------------------------------- keys & sort
 
 
@@ -349,30 +447,34 @@ def test_bad_input_excluded():
 # --------------------------------------------------------------- adjoint
 
 
-def _loss(ps, gr, gh, pos=None, m=None):
+def _loss(ps, gr, gh, pos=None, m=None, kernel=oracle.M4):
     q = sphgen.ParticleSet(**{**ps.__dict__})
     if pos is not None:
         q.x, q.y, q.z = (np.ascontiguousarray(pos[:, a]) for a in range(3))
     if m is not None:
         q.m = m
-    s = oracle.solve(q, mode=oracle.ROOT, root_tol=1e-15, search=0, max_iter=200)
+    s = oracle.solve(q, mode=oracle.ROOT, root_tol=1e-15, search=0, max_iter=200,
+                     kernel=kernel)
     assert np.all((s["status"] >> 16) == 0)
     return float(np.dot(gr, s["rho"]) + np.dot(gh, s["h"])), s
 
 
+@pytest.mark.parametrize("kernel", [0, 1])
 @pytest.mark.parametrize("periodic", [True, False])
-def test_adjoint_matches_central_differences(periodic):
+def test_adjoint_matches_central_differences(periodic, kernel):
     rng = np.random.default_rng(21)
     n = 100
+    # C6 counts 28.4 for the particle itself: its target needs a few neighbours
+    nt = 16.0 if kernel == oracle.M4 else 40.0
     if periodic:
-        ps = sphgen.uniform(n, seed=22, n_target=16.0, n_tol=1.0)
+        ps = sphgen.uniform(n, seed=22, n_target=nt, n_tol=1.0)
     else:
-        ps = sphgen.groups(1, seed=23, sizes=np.array([n]), n_target=16.0, n_tol=1.0)
+        ps = sphgen.groups(1, seed=23, sizes=np.array([n]), n_target=nt, n_tol=1.0)
     ps.m = rng.uniform(0.5, 1.5, n)
     gr = rng.standard_normal(n)
     gh = rng.standard_normal(n)
-    L0, s0 = _loss(ps, gr, gh)
-    g = oracle.backward(ps, s0["h"], gr, gh, search=0)
+    L0, s0 = _loss(ps, gr, gh, kernel=kernel)
+    g = oracle.backward(ps, s0["h"], gr, gh, search=0, kernel=kernel)
     pos = ps.pos.copy()
     eps = 1e-6
     scale = np.abs(np.concatenate([g["gx"], g["gy"], g["gz"]])).max()
@@ -382,7 +484,8 @@ def test_adjoint_matches_central_differences(periodic):
             pm = pos.copy()
             pp[k, a] += eps
             pm[k, a] -= eps
-            fd = (_loss(ps, gr, gh, pos=pp)[0] - _loss(ps, gr, gh, pos=pm)[0]) / (2 * eps)
+            fd = (_loss(ps, gr, gh, pos=pp, kernel=kernel)[0]
+                  - _loss(ps, gr, gh, pos=pm, kernel=kernel)[0]) / (2 * eps)
             assert abs(fd - g[key][k]) < 2e-6 * scale, (k, a, fd, g[key][k])
     mscale = np.abs(g["gm"]).max()
     for k in rng.choice(n, 8, replace=False):
@@ -390,7 +493,8 @@ def test_adjoint_matches_central_differences(periodic):
         mm = ps.m.copy()
         mp[k] += eps
         mm[k] -= eps
-        fd = (_loss(ps, gr, gh, m=mp)[0] - _loss(ps, gr, gh, m=mm)[0]) / (2 * eps)
+        fd = (_loss(ps, gr, gh, m=mp, kernel=kernel)[0]
+              - _loss(ps, gr, gh, m=mm, kernel=kernel)[0]) / (2 * eps)
         assert abs(fd - g["gm"][k]) < 2e-6 * mscale
 
 
