@@ -8,9 +8,11 @@
  * a smoothing length" of Listing 1, self term included) together with the
  * smoothing length h_i, which is adjusted per particle until its weighted
  * neighbour count n_i = (4 pi/3) h_i^3 sum_j W(r_ij, h_i) reaches the target
- * (the recompute loop of Sec. IV-A, Listings 2 and 3).  W is the M4 cubic
- * spline with compact support h: W = 8/(pi h^3) f(r/h),
- * f(q) = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1), 0 beyond.
+ * (the recompute loop of Sec. IV-A, Listings 2 and 3).  W = sigma/h^3 f(r/h)
+ * has compact support h: by default the M4 cubic spline (sigma = 8/pi,
+ * f(q) = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1), 0 beyond), or
+ * the paper's Wendland C6 (params->kernel).  With C = (4 pi/3) sigma the
+ * weighted count is n = C sum_j f (C = 32/3 for M4, 1365/48 for Wendland C6).
  *
  * Conventions shared by every entry point:
  *  - All array arguments are DEVICE pointers on the current HIP device,
@@ -57,6 +59,14 @@ extern "C" {
                           stored relative to Morton-cell origins, compensated (Kahan)
                           sums; h iteration and convergence test in binary64 */
 
+/* kernel: the smoothing function (both with compact support h; the weighted
+ * count is n = (4 pi/3) h^3 sum_j W = C sum_j f, C = (4 pi/3) sigma) */
+#define SPH_KERNEL_M4          0  /* M4 cubic spline (Gadget-2 convention), sigma = 8/pi:
+                                     f = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (q <= 1) */
+#define SPH_KERNEL_WENDLAND_C6 1  /* Wendland C6, the kernel of the paper's runs
+                                     (Sec. II-C), sigma = 1365/(64 pi):
+                                     f = (1-q)^8 (1 + 8q + 25q^2 + 32q^3) */
+
 /* io_dtype: element type of caller arrays x, y, z, m, h_init, rho, h, nw, grads */
 #define SPH_F64    0
 #define SPH_F32    1
@@ -76,7 +86,7 @@ extern "C" {
                                          particle is never anyone's neighbour; its rho and
                                          nw are NaN, h = h_init, nngb = 0. */
 #define SPH_ST_UNREACHABLE (1 << 19)  /* isolated group of n_g particles with
-                                         (32/3) n_g < n_target - n_tol: evaluated at
+                                         C n_g < n_target - n_tol: evaluated at
                                          h_init only */
 
 /* Parameters.  Initialise with sph_default_params() and override fields. */
@@ -107,7 +117,9 @@ typedef struct {
                                before and after the density kernel (sph_density_solve)
                                or the two adjoint kernels (sph_density_backward);
                                NULL: none */
-    int32_t  reserved[8];   /* must be zero */
+    int32_t  kernel;        /* smoothing kernel, W(r, h) = sigma/h^3 f(r/h), support r < h:
+                               SPH_KERNEL_M4 (default) or SPH_KERNEL_WENDLAND_C6 */
+    int32_t  reserved[7];   /* must be zero */
 } sph_params;
 
 /* Fill *p with the defaults: FP64 compute and io, band mode, periodic unit
@@ -151,7 +163,7 @@ int sph_sort(const sph_params *params, int64_t n, int32_t n_groups,
  * repeat: evaluate at h the sums over neighbours j (r_ij^2 < h^2, minimum
  * image when periodic, same group when isolated)
  *     S0 = sum f(q), S1 = sum q f'(q), R = sum m_j f(q),   q = r_ij / h,
- * giving rho = 8R/(pi h^3), n = (32/3) S0, dn/dh = -(32/3) S1/h; stop per
+ * giving rho = sigma R/h^3, n = C S0, dn/dh = -C S1/h; stop per
  * `mode`; else set lo = h if n < N_t, else hi = h, and take the Newton step
  * h + (N_t - n)/(dn/dh) when dn/dh > 0 and the step lands strictly inside
  * (lo, hi) and within [h/2, 2h], otherwise 2h (no upper bracket yet), h/2 (no
@@ -180,7 +192,7 @@ int sph_density_solve(const sph_params *params, int64_t n, int32_t n_groups,
  *   lambda_i = -(grad_rho_i drho_i/dh_i + grad_h_i) / (dn_i/dh_i)
  *   (0 when dn_i/dh_i = 0), and for each pair j in N(i), j != i, with
  *   q = r_ij/h_i and unit vector u = (x_i - x_j)/r_ij:
- *     c_ij = grad_rho_i m_j 8 f'(q)/(pi h_i^4) + lambda_i (32/3) f'(q)/h_i,
+ *     c_ij = grad_rho_i m_j sigma f'(q)/h_i^4 + lambda_i C f'(q)/h_i,
  *     grad_x_i += c_ij u,  grad_x_j -= c_ij u,
  *     grad_m_j += grad_rho_i W(r_ij, h_i)   (self term included).
  * Computed in gather form (no floating-point atomics; bitwise reproducible).

@@ -33,6 +33,7 @@ ST_NOCONV = 1 << 16
 ST_HTOOLARGE = 1 << 17
 ST_BADINPUT = 1 << 18
 ST_UNREACHABLE = 1 << 19
+KERNEL_M4, KERNEL_WENDLAND_C6 = 0, 1
 
 EXPORTS = [
     "sph_default_params", "sph_workspace_size", "sph_sort", "sph_density_solve",
@@ -59,7 +60,8 @@ class Params(C.Structure):
         ("waves_per_cu", C.c_int32),
         ("segment", C.c_int32),
         ("prof_events", C.c_void_p * 2),
-        ("reserved", C.c_int32 * 8),
+        ("kernel", C.c_int32),
+        ("reserved", C.c_int32 * 7),
     ]
 
 

@@ -4,7 +4,9 @@
 //
 // For a cotangent (gr, gh) on (rho, h):
 //   lambda_i = -(gr_i drho_i/dh_i + gh_i) / (dn_i/dh_i)          (0 if dn/dh = 0)
-//   alpha_i = gr_i 8/(pi h_i^4), beta_i = lambda_i (32/3)/h_i, gamma_i = gr_i 8/(pi h_i^3)
+//   alpha_i = gr_i sigma/h_i^4, beta_i = lambda_i C/h_i, gamma_i = gr_i sigma/h_i^3
+//   (W = sigma/h^3 f(r/h), n = C sum f: M4 8/pi and 32/3, Wendland C6
+//   1365/(64 pi) and 1365/48)
 //   pair (i, j in N(i)): c_ij = f'(r/h_i) (alpha_i m_j + beta_i)
 //   dL/dx_k = sum_{j: r < h_k} c_kj (x_k - x_j)/r + sum_{i: r < h_i} c_ik (x_k - x_i)/r
 //   dL/dm_k = sum_{i: r < h_i} gamma_i f(r/h_i)          (self term included)
@@ -106,21 +108,9 @@ struct AdjLDS {
     AdjCand<PREC> cand[64];
 };
 
-// M4 spline f(q) and f'(q) for 0 <= q <= 1, without branches (callers clamp q
-// to 1, where both vanish, or discard the result out of range)
-template <typename T>
-__device__ inline void spline_fd(T q, T &f, T &fp) {
-    const T u = T(1) - q;
-    const T u2 = u * u;
-    const bool inner = q <= T(0.5);
-    const T fin = T(1) + q * q * (T(6) * q - T(6));
-    const T gin = q * (T(18) * q - T(12));
-    f = inner ? fin : T(2) * u2 * u;
-    fp = inner ? gin : T(-6) * u2;
-}
-
-template <int PREC, bool GROUPED>
+template <int PREC, bool GROUPED, int KERNEL>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
+    using KT = Kern<KERNEL>;
     __shared__ AdjLDS<PREC> S;
     const int l = threadIdx.x;
     const int p = l & (kAdjP - 1);  // particle slot of this lane
@@ -306,7 +296,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                             if (in1) {
                                 const double q = sqrt(r2) * hkinv;
                                 double f, fp;
-                                spline_fd<double>(q, f, fp);
+                                KT::template fd<double>(q, f, fp);
                                 acc0 += q * fp;
                                 acc1 += c.p.w * f;
                                 acc2 += c.p.w * q * fp;
@@ -316,8 +306,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                             if (in1 || in2) {
                                 const double r = sqrt(r2);
                                 double f1, fp1, f2, fp2;
-                                spline_fd<double>(fmin(r * hkinv, 1.0), f1, fp1);
-                                spline_fd<double>(fmin(r * c.h.y, 1.0), f2, fp2);
+                                KT::template fd<double>(fmin(r * hkinv, 1.0), f1, fp1);
+                                KT::template fd<double>(fmin(r * c.h.y, 1.0), f2, fp2);
                                 const double c1 = in1 ? fp1 * (ak * c.p.w + bk) : 0.0;
                                 const double c2 = in2 ? fp2 * (c.h.z * mk + c.h.w) : 0.0;
                                 acc3 += in2 ? c.g * f2 : 0.0;
@@ -342,7 +332,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                             if (in1) {
                                 const float q = fminf(__builtin_amdgcn_sqrtf(r2) * hkinvf, 1.0f);
                                 float f, fp;
-                                spline_fd<float>(q, f, fp);
+                                KT::template fd<float>(q, f, fp);
                                 const float qfp = q * fp;
                                 s0 += qfp;
                                 s1 = __builtin_fmaf(c.p.w, f, s1);
@@ -354,8 +344,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                                 const float r = __builtin_amdgcn_sqrtf(r2);
                                 const float rinv = r > 0.f ? __builtin_amdgcn_rcpf(r) : 0.f;
                                 float f1, fp1, f2, fp2;
-                                spline_fd<float>(fminf(r * hkinvf, 1.0f), f1, fp1);
-                                spline_fd<float>(fminf(r * c.h.y, 1.0f), f2, fp2);
+                                KT::template fd<float>(fminf(r * hkinvf, 1.0f), f1, fp1);
+                                KT::template fd<float>(fminf(r * c.h.y, 1.0f), f2, fp2);
                                 const float c1 = in1 ? fp1 * __builtin_fmaf(akf, c.p.w, bkf) : 0.f;
                                 const float c2 = in2 ? fp2 * __builtin_fmaf(c.h.z, mkf, c.h.w) : 0.f;
                                 s3 = __builtin_fmaf(in2 ? c.g : 0.f, f2, s3);
@@ -584,12 +574,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 if (valid) {
                     const double gr = a.grs[s], gh = a.ghs[s];
                     const double h4 = hk * hk * hk * hk;
-                    const double drhodh = -8.0 * (3.0 * acc1 + acc2) / (kPi * h4);
-                    const double dndh = -(32.0 / 3.0) * acc0 / hk;
+                    const double drhodh = -KT::sigma * (3.0 * acc1 + acc2) / h4;
+                    const double dndh = -KT::count * acc0 / hk;
                     const double lam = dndh > 0.0 ? -(gr * drhodh + gh) / dndh : 0.0;
-                    al = gr * 8.0 / (kPi * h4);
-                    be = lam * (32.0 / 3.0) / hk;
-                    ga = gr * 8.0 / (kPi * hk * hk * hk);
+                    al = gr * KT::sigma / h4;
+                    be = lam * KT::count / hk;
+                    ga = gr * KT::sigma / (hk * hk * hk);
                 }
                 a.alpha[s] = al;
                 a.beta[s] = be;
@@ -692,6 +682,7 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
     const int64_t full = (int64_t)256 * kAdjWavesPerCU;
     const dim3 grid((unsigned)(pl.grouped ? full : (a.n_items < full ? a.n_items : full)));
     const bool f32c = pl.prm.precision == SPH_FP32C;
+    const bool wc6 = pl.prm.kernel == SPH_KERNEL_WENDLAND_C6;
     if (pl.prm.prof_events[0]) {
         e = hipEventRecord((hipEvent_t)pl.prm.prof_events[0], st);
         if (e != hipSuccess) return e;
@@ -700,13 +691,22 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
         a.phase = phase;
         e = run_zero_i32(pl.ctrl, 4, st);
         if (e != hipSuccess) return e;
+#define SPH_ADJ(PR, GR)                                                                       \
+    do {                                                                                      \
+        if (wc6)                                                                              \
+            hipLaunchKernelGGL((k_adjoint<PR, GR, SPH_KERNEL_WENDLAND_C6>), grid, dim3(64), 0, \
+                               st, a);                                                        \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_adjoint<PR, GR, SPH_KERNEL_M4>), grid, dim3(64), 0, st, a); \
+    } while (0)
         if (!pl.grouped) {
-            if (f32c) hipLaunchKernelGGL((k_adjoint<SPH_FP32C, false>), grid, dim3(64), 0, st, a);
-            else hipLaunchKernelGGL((k_adjoint<SPH_FP64, false>), grid, dim3(64), 0, st, a);
+            if (f32c) SPH_ADJ(SPH_FP32C, false);
+            else SPH_ADJ(SPH_FP64, false);
         } else {
-            if (f32c) hipLaunchKernelGGL((k_adjoint<SPH_FP32C, true>), grid, dim3(64), 0, st, a);
-            else hipLaunchKernelGGL((k_adjoint<SPH_FP64, true>), grid, dim3(64), 0, st, a);
+            if (f32c) SPH_ADJ(SPH_FP32C, true);
+            else SPH_ADJ(SPH_FP64, true);
         }
+#undef SPH_ADJ
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -233,8 +233,9 @@ __device__ inline void kahan(float &s, float &c, float x) {
 // copies' sums are combined before the (replicated) h update.  Smaller P
 // means a smaller tile region (fewer candidates per particle) and a shorter
 // sequential stream per wave, at the price of more tiles.
-template <int PREC, bool GROUPED, int P>
+template <int PREC, bool GROUPED, int P, int KERNEL>
 __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
+    using KT = Kern<KERNEL>;
     constexpr int S = 64 / P;
     __shared__ double act_t[3][64];
     __shared__ double act_H[64];
@@ -316,7 +317,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         }
         if (GROUPED && mine && valid) {
             const double ng = (double)(a.goff[g + 1] - a.goff[g]);
-            if ((32.0 / 3.0) * ng < a.Nt - a.dN) {
+            if (KT::count * ng < a.Nt - a.dN) {
                 hs.flags |= SPH_ST_UNREACHABLE;
                 hs.fixed = true;
             }
@@ -516,15 +517,10 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                     const double dz = (c.z[t] - zi) + c.shz[t];
                                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                                     if (r2 < h2) {
-                                        // the spline in the form of the FP32C path (factors
-                                        // 2 and 6 applied to the totals)
+                                        // scaled pair terms (factors applied to the totals)
                                         const double q = sqrt(r2) * hinv;
-                                        const double u = 1.0 - q;
-                                        const double v = fmax(0.5 - q, 0.0);
-                                        const double u2 = u * u;
-                                        const double v2 = v * v;
-                                        const double fh = u2 * u - 4.0 * v * v2;
-                                        const double gs = q * (4.0 * v2 - u2);
+                                        double fh, gs;
+                                        KT::template terms<double>(q, q * q, fh, gs);
                                         sm.d0 += fh;
                                         sm.d1 += gs;
                                         sm.dr += c.m[t] * fh;
@@ -543,17 +539,11 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                     const float dz = cj.z - piz;
                                     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
                                     if (r2 < h2f) {
-                                        // f(q) = 2 (u^3 - 4 v^3) and q f'(q) = 6 q (4 v^2 - u^2)
-                                        // with u = 1 - q, v = max(1/2 - q, 0): one form for
-                                        // both spline pieces; the factors 2 and 6 are applied
-                                        // to the totals
-                                        const float q = __builtin_amdgcn_sqrtf(r2 * ih2);  // 1 ulp
-                                        const float u = 1.0f - q;
-                                        const float v = fminf(fmaxf(0.5f - q, 0.0f), 1.0f);
-                                        const float u2 = u * u;
-                                        const float v2 = v * v;
-                                        const float fh = __builtin_fmaf(-4.0f * v, v2, u2 * u);
-                                        const float gs = q * __builtin_fmaf(4.0f, v2, -u2);
+                                        // scaled pair terms (factors applied to the totals)
+                                        const float q2 = r2 * ih2;
+                                        const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
+                                        float fh, gs;
+                                        KT::template terms<float>(q, q2, fh, gs);
                                         pa0 += fh;
                                         pa1 += gs;
                                         par = __builtin_fmaf(cj.w, fh, par);
@@ -581,11 +571,11 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             }
             double S0, S1, R;
             if (PREC == SPH_FP64) {
-                S0 = 2.0 * sm.d0; S1 = 6.0 * sm.d1; R = 2.0 * sm.dr;
+                S0 = KT::fscale * sm.d0; S1 = KT::gscale * sm.d1; R = KT::fscale * sm.dr;
             } else {
-                S0 = 2.0 * ((double)sm.f0 - (double)sm.c0);
-                S1 = 6.0 * ((double)sm.f1 - (double)sm.c1);
-                R = 2.0 * ((double)sm.fr - (double)sm.cr);
+                S0 = KT::fscale * ((double)sm.f0 - (double)sm.c0);
+                S1 = KT::gscale * ((double)sm.f1 - (double)sm.c1);
+                R = KT::fscale * ((double)sm.fr - (double)sm.cr);
             }
             int32_t npair = sm.n;
             // combine the S copies of each particle: a butterfly of commutative
@@ -603,11 +593,11 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 cnt_passes += (uint64_t)__popcll(am);
             }
             if (!done) {
-                const double nwv = (32.0 / 3.0) * S0;
-                const double dndh = -(32.0 / 3.0) * S1 / hs.h;
+                const double nwv = KT::count * S0;
+                const double dndh = -KT::count * S1 / hs.h;
                 const double hcur = hs.h;
                 if (h_step(hs, nwv, dndh, a, hmax)) {
-                    const double rho = 8.0 * R / (kPi * hcur * hcur * hcur);
+                    const double rho = KT::sigma * R / (hcur * hcur * hcur);
                     if (kk == 0)
                         write_out(a, a.perm[b + p], rho, hcur, nwv, npair,
                                   hs.flags | (hs.it & 0xFFFF));
@@ -667,8 +657,14 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     const dim3 grid((unsigned)pl.grid), block(64);
     const bool f32c = pl.prm.precision == SPH_FP32C;
     const int P = pl.prm.segment;
-#define SPH_LAUNCH(PR, GR, PP) \
-    hipLaunchKernelGGL((k_solve<PR, GR, PP>), grid, block, 0, st, a)
+    const bool wc6 = pl.prm.kernel == SPH_KERNEL_WENDLAND_C6;
+#define SPH_LAUNCH_K(PR, GR, PP, KK) \
+    hipLaunchKernelGGL((k_solve<PR, GR, PP, KK>), grid, block, 0, st, a)
+#define SPH_LAUNCH(PR, GR, PP)                                             \
+    do {                                                                  \
+        if (wc6) SPH_LAUNCH_K(PR, GR, PP, SPH_KERNEL_WENDLAND_C6);        \
+        else SPH_LAUNCH_K(PR, GR, PP, SPH_KERNEL_M4);                     \
+    } while (0)
 #define SPH_LAUNCH_P(PR, GR)                                   \
     do {                                                      \
         if (P == 8) SPH_LAUNCH(PR, GR, 8);                    \
@@ -685,6 +681,7 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     }
 #undef SPH_LAUNCH_P
 #undef SPH_LAUNCH
+#undef SPH_LAUNCH_K
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (pl.prm.prof_events[1]) e = hipEventRecord((hipEvent_t)pl.prm.prof_events[1], st);

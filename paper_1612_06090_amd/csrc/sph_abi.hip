@@ -138,7 +138,8 @@ static int check_params(const sph_params *p, int64_t n, int32_t G, const int64_t
     if (p->waves_per_cu < 1 || p->waves_per_cu > 32) return SPH_E_INVALID;
     if (p->segment != 8 && p->segment != 16 && p->segment != 32 && p->segment != 64)
         return SPH_E_INVALID;
-    for (int k = 0; k < 8; ++k)
+    if (p->kernel != SPH_KERNEL_M4 && p->kernel != SPH_KERNEL_WENDLAND_C6) return SPH_E_INVALID;
+    for (int k = 0; k < 7; ++k)
         if (p->reserved[k] != 0) return SPH_E_INVALID;
     return SPH_OK;
 }

@@ -15,6 +15,64 @@ constexpr int kWave = 64;
 // rounds of 64 consecutive keys, so a block tile holds 4*64*ROUNDS keys.
 constexpr int kSortThreads = 256;
 
+// Smoothing kernels, W(r, h) = sigma/h^3 f(q), q = r/h < 1, weighted count
+// n = count * sum f.  Pair terms are produced in a scaled form that needs no
+// branch: f = fscale * fh and q f'(q) = gscale * gs.
+template <int K>
+struct Kern;
+
+template <>
+struct Kern<SPH_KERNEL_M4> {
+    static constexpr double sigma = 8.0 / kPi;
+    static constexpr double count = 32.0 / 3.0;
+    static constexpr double fscale = 2.0, gscale = 6.0;
+    // f = 2 (u^3 - 4 v^3), q f' = 6 q (4 v^2 - u^2), u = 1 - q, v = max(1/2 - q, 0):
+    // one form for both pieces of the spline (beyond q = 1 both vanish to rounding)
+    template <typename T>
+    __device__ static void terms(T q, T /*q2*/, T &fh, T &gs) {
+        const T u = T(1) - q;
+        const T v = fmin(fmax(T(0.5) - q, T(0)), T(1));
+        const T u2 = u * u, v2 = v * v;
+        fh = fma(T(-4) * v, v2, u2 * u);
+        gs = q * fma(T(4), v2, -u2);
+    }
+    // f and f'
+    template <typename T>
+    __device__ static void fd(T q, T &f, T &fp) {
+        const T u = T(1) - q;
+        const T v = fmin(fmax(T(0.5) - q, T(0)), T(1));
+        const T u2 = u * u, v2 = v * v;
+        f = T(2) * (u2 * u - T(4) * v * v2);
+        fp = T(6) * (T(4) * v2 - u2);
+    }
+};
+
+template <>
+struct Kern<SPH_KERNEL_WENDLAND_C6> {
+    static constexpr double sigma = 1365.0 / (64.0 * kPi);
+    static constexpr double count = 1365.0 / 48.0;
+    static constexpr double fscale = 1.0, gscale = -22.0;
+    // f = u^8 (1 + 8q + 25q^2 + 32q^3), q f' = -22 q^2 u^7 (1 + 7q + 16q^2)
+    template <typename T>
+    __device__ static void terms(T q, T q2, T &fh, T &gs) {
+        const T u = T(1) - q;
+        const T u2 = u * u, u4 = u2 * u2;
+        const T u7 = u4 * (u2 * u);
+        const T P = fma(q, fma(q, fma(T(32), q, T(25)), T(8)), T(1));
+        const T Q = fma(q, fma(T(16), q, T(7)), T(1));
+        fh = (u7 * u) * P;
+        gs = (q2 * u7) * Q;
+    }
+    template <typename T>
+    __device__ static void fd(T q, T &f, T &fp) {
+        const T u = T(1) - q;
+        const T u2 = u * u, u4 = u2 * u2;
+        const T u7 = u4 * (u2 * u);
+        f = (u7 * u) * (T(1) + q * (T(8) + q * (T(25) + T(32) * q)));
+        fp = T(-22) * q * u7 * (T(1) + q * (T(7) + T(16) * q));
+    }
+};
+
 // Particles per wave tile of the adjoint kernels.
 constexpr int kAdjTile = 16;
 

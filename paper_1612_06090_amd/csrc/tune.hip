@@ -49,8 +49,9 @@ std::string tune_key(const sph_params *p, int64_t n, int32_t G, bool has_h0) {
             if (*c == ' ' || *c == ':') *c = '_';
     }
     char buf[320];
-    snprintf(buf, sizeof(buf), "%s/p%d/io%d/m%d/per%d/nt%.17g/tol%.17g/rt%.17g/it%d/cl%d/h0%d/n%d/g%d",
-             name, p->precision, p->io_dtype, p->mode, p->periodic, p->n_target, p->n_tol,
+    snprintf(buf, sizeof(buf),
+             "%s/p%d/io%d/m%d/per%d/k%d/nt%.17g/tol%.17g/rt%.17g/it%d/cl%d/h0%d/n%d/g%d", name,
+             p->precision, p->io_dtype, p->mode, p->periodic, p->kernel, p->n_target, p->n_tol,
              p->root_tol, p->max_iter, p->cell_level, has_h0 ? 1 : 0, floor_log2(n),
              floor_log2((int64_t)G + 1));
     return std::string(buf);

@@ -62,7 +62,7 @@ def test_default_params():
     assert (p.precision, p.io_dtype, p.mode, p.periodic) == (sph.FP64, sph.F64, sph.BAND, 1)
     assert (p.box, p.n_target, p.n_tol, p.root_tol) == (1.0, 64.0, 2.0, 1e-12)
     assert (p.max_iter, p.cell_level, p.segment, p.tile_cell) == (64, -1, 16, -1)
-    assert p.waves_per_cu == 16
+    assert p.waves_per_cu == 16 and p.kernel == sph.KERNEL_M4
 
 
 def test_workspace_size_monotone_and_valid():
@@ -81,7 +81,7 @@ def test_workspace_size_monotone_and_valid():
     ("abi_version", 99), ("precision", 7), ("io_dtype", 3), ("mode", 2), ("periodic", 5),
     ("box", 0.0), ("box", float("nan")), ("n_target", 0.0), ("n_tol", -1.0),
     ("max_iter", -1), ("max_iter", 70000), ("cell_level", 22), ("cell_level", 0),
-    ("tile_cell", 3), ("tile_cell", -3), ("waves_per_cu", 0), ("segment", 12), ("segment", 128),
+    ("tile_cell", 3), ("tile_cell", -3), ("kernel", 2), ("kernel", -1), ("waves_per_cu", 0), ("segment", 12), ("segment", 128),
 ])
 def test_invalid_params_rejected(field, value):
     _lib()
