@@ -239,6 +239,32 @@ def run_large(sph, torch, steps):
             "sort": srt}
 
 
+def run_wendland(sph, torch, d, ps, steps):
+    """The paper's kernel at the paper's scale: Wendland C6 with N_t = 295 +- 2
+    on the clustered 2^20 set (FP32C and FP64), sort + solve per step."""
+    out = {"workload": "clustered2^20, Wendland C6 kernel, N_t = 295 +- 2, h_init = 2 N^-1/3"}
+    for prec, name in ((sph.FP32C, "fp32c"), (sph.FP64, "fp64")):
+        p = sph.default_params(periodic=1, box=ps.box, n_target=295.0, n_tol=2.0,
+                               precision=prec, kernel=sph.KERNEL_WENDLAND_C6)
+        ws = sph.workspace(p, ps.n, 0, d["x"].device)
+        o = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, stats=True, ws=ws)
+        torch.cuda.synchronize()
+        pairs = int(o["stats"][0].item())
+        flagged = int(((o["status"] >> 16) != 0).sum().item())
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[name] = {"ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
+                     "particles_per_s": ps.n / (ms * 1e-3), "pairs_per_step": pairs,
+                     "flagged": flagged}
+    out["fp32c_speedup_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32c"]["ms_per_step"]
+    return out
+
+
 def cpu_baseline(ps, budget_s=15.0):
     """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
     import oracle
@@ -379,6 +405,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-wendland", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "CMD"),
@@ -432,6 +459,10 @@ def main():
         bat = run_batched(sph, torch, max(3, args.steps), args.warmup)
         print(f"[bench] batched {bat}", file=sys.stderr, flush=True)
 
+    wc6 = None
+    if not args.no_wendland:
+        wc6 = run_wendland(sph, torch, d, ps, max(3, args.steps // 2))
+        print(f"[bench] wendland {wc6}", file=sys.stderr, flush=True)
     big = None
     if not args.no_large:
         big = run_large(sph, torch, 3)
@@ -485,6 +516,8 @@ def main():
         line["batched"] = bat
     if big is not None:
         line["large"] = big
+    if wc6 is not None:
+        line["wendland_c6"] = wc6
     if adj is not None:
         line["adjoint"] = adj
     if not args.no_cpu_baseline:
