@@ -770,6 +770,93 @@ void oracle_solve(const orc_cfg *c, int64_t n, const double *x, const double *y,
     ctx_free(&k);
 }
 
+/* --------------------------------------------- exact K nearest neighbours */
+
+/* The K-nearest criterion of Sec. IV-D: particle i's smoothing length is the
+ * distance of the K-th nearest particle of its domain, counting i itself as
+ * the first (the paper sorts the neighbour list, or selects with QUICKSELECT,
+ * and keeps the first K); the density is Eq. (1) at that h, where the K-th
+ * neighbour sits at q = 1 and contributes W = 0, so ties at the K-th
+ * distance do not change rho.  Done the plain way: every squared distance
+ * inside a ball that doubles from h_init until it holds at least K particles
+ * is collected, the list is sorted (qsort), and entry K-1 is taken.
+ * Flags: UNREACHABLE for a group with fewer than K valid particles (h stays
+ * h_init, rho evaluated there); H_TOO_LARGE when the periodic ball reaches the
+ * cap L/2 (1 - 2^-20) before holding K (h = the cap).  The low 16 status bits
+ * are 0 (no iteration here). */
+typedef struct { double *d2; int64_t cnt, cap; } d2_list;
+
+static void d2_visit(void *u, int64_t j, double r2, const double *d)
+{
+    (void)j; (void)d;
+    d2_list *L = (d2_list *)u;
+    if (L->cnt == L->cap) {
+        L->cap = L->cap ? 2 * L->cap : 1024;
+        L->d2 = (double *)realloc(L->d2, sizeof(double) * (size_t)L->cap);
+    }
+    L->d2[L->cnt++] = r2;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+void oracle_knn(const orc_cfg *c, int64_t n, const double *x, const double *y,
+                const double *z, const double *m, const double *h_init, int32_t K,
+                double *rho, double *h, double *nw, int32_t *nngb, int32_t *status)
+{
+    ctx_t k;
+    set_threads(c);
+    ctx_init(&k, c, n, x, y, z, m, h_init);
+    const double hmax = c->periodic ? 0.5 * c->box * (1.0 - 0x1p-20) : INFINITY;
+    const double sg = oracle_sigma(c->kernel), cc = oracle_count_const(c->kernel);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        double hi = h_init[i];
+        int32_t flags = 0;
+        if (!k.valid[i]) {
+            rho[i] = NAN; h[i] = hi; nw[i] = NAN; nngb[i] = 0; status[i] = ORC_BADINPUT;
+            continue;
+        }
+        int64_t b, e;
+        int32_t dm;
+        dom_range(&k, i, &b, &e, &dm);
+        int64_t nvalid = 0;
+        for (int64_t j = b; j < e; ++j) nvalid += k.valid[j];
+        if (hi > hmax) hi = hmax;
+        if (!c->periodic && nvalid < K) {
+            flags |= ORC_UNREACHABLE;
+        } else {
+            d2_list L = {NULL, 0, 0};
+            double r = hi;
+            for (;;) {
+                L.cnt = 0;
+                visit(&k, i, r, d2_visit, &L);
+                if (L.cnt >= K) break;
+                if (r >= hmax) { flags |= ORC_HTOOLARGE; break; }
+                r = 2.0 * r < hmax ? 2.0 * r : hmax;
+            }
+            if (flags & ORC_HTOOLARGE) {
+                hi = hmax;
+            } else {
+                qsort(L.d2, (size_t)L.cnt, sizeof(double), cmp_double);
+                hi = sqrt(L.d2[K - 1]);
+                if (hi >= hmax) { hi = hmax; flags |= ORC_HTOOLARGE; }
+            }
+            free(L.d2);
+        }
+        sums_t s = eval_sums(&k, i, hi);
+        h[i] = hi;
+        rho[i] = sg * s.R / (hi * hi * hi);
+        nw[i] = cc * s.S0;
+        nngb[i] = (int32_t)s.N;
+        status[i] = flags;
+    }
+    ctx_free(&k);
+}
+
 typedef struct {
     int64_t i;
     double h, gr, lam;

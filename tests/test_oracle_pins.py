@@ -536,3 +536,81 @@ def test_adjoint_lattice_site_symmetry():
     assert abs(g["gx"][i]) < 1e-10 * scale and abs(g["gy"][i]) < 1e-10 * scale
     assert abs(g["gz"][i]) < 1e-10 * scale
     assert abs(g["gx"].sum()) < 1e-10 * scale * ps.n
+
+
+# ------------------------------------------- exact K nearest (Sec. IV-D)
+
+
+def _brute_sorted_d2(ps):
+    # all pairwise squared distances by NumPy, minimum image wrapped once, in
+    # the evaluation order (dx*dx + dy*dy) + dz*dz; each row sorted
+    p = ps.pos
+    d = p[None, :, :] - p[:, None, :]
+    if ps.periodic:
+        L = ps.box
+        d = np.where(d > 0.5 * L, d - L, np.where(d < -0.5 * L, d + L, d))
+    r2 = (d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1]) + d[..., 2] * d[..., 2]
+    return np.sort(r2, axis=1)
+
+
+@pytest.mark.parametrize("K", [1, 2, 33, 64, 295])
+def test_knn_matches_brute_force(K):
+    ps = sphgen.uniform(700, seed=71, n_target=64.0)
+    o = oracle.knn(ps, K)
+    rows = _brute_sorted_d2(ps)
+    ref = np.sqrt(rows[:, K - 1])
+    assert np.all(o["status"] == 0)
+    np.testing.assert_array_equal(o["h"], ref)
+    # the K-th neighbour sits on the support boundary (K - 1 strictly inside,
+    # or K when sqrt(d^2)^2 rounds above d^2): the count is r^2 < h^2
+    cnt = (rows < (ref * ref)[:, None]).sum(axis=1)
+    np.testing.assert_array_equal(o["nngb"], cnt)
+    assert np.all((cnt == K - 1) | (cnt == K))
+    e = oracle.eval_at_h(ps, o["h"], search=0)   # brute-force order: sums to rounding
+    np.testing.assert_allclose(e["rho"], o["rho"], rtol=1e-14)
+
+
+def test_knn_groups_brute_force_and_unreachable():
+    ps = sphgen.groups(7, seed=72, sizes=np.array([40, 3, 120, 0, 77, 15, 16]))
+    K = 16
+    o = oracle.knn(ps, K)
+    for g, (b, e) in enumerate(zip(ps.offsets[:-1], ps.offsets[1:])):
+        if e == b:
+            continue
+        sub = sphgen.ParticleSet(x=ps.x[b:e], y=ps.y[b:e], z=ps.z[b:e], m=ps.m[b:e],
+                                 h_init=ps.h_init[b:e], periodic=False, box=1.0,
+                                 n_target=16.0, n_tol=1.0)
+        if e - b < K:
+            assert np.all((o["status"][b:e] & oracle.ST_UNREACHABLE) != 0)
+            np.testing.assert_array_equal(o["h"][b:e], ps.h_init[b:e])
+        else:
+            ref = np.sqrt(_brute_sorted_d2(sub)[:, K - 1])
+            np.testing.assert_array_equal(o["h"][b:e], ref)
+
+
+@pytest.mark.parametrize("K,shell", [(7, 1.0), (19, 2.0 ** 0.5), (27, 3.0 ** 0.5), (33, 2.0)])
+def test_knn_lattice_shells(K, shell):
+    # simple cubic lattice: 1 + 6 sites within a, + 12 at a sqrt 2, + 8 at
+    # a sqrt 3, + 6 at 2a
+    ps = sphgen.lattice(10, h=0.05)
+    o = oracle.knn(ps, K)
+    np.testing.assert_allclose(o["h"], shell * 0.1, rtol=1e-13)
+
+
+def test_knn_flags_and_order():
+    # periodic: 20 particles cannot supply 30 neighbours below the cap
+    small = sphgen.uniform(20, seed=73)
+    o = oracle.knn(small, 30)
+    assert np.all((o["status"] & oracle.ST_HTOOLARGE) != 0)
+    assert np.all(o["h"] == 0.5 * (1.0 - 2.0 ** -20))
+    # the result does not depend on the caller's order or on h_init
+    ps = sphgen.uniform(900, seed=74)
+    a = oracle.knn(ps, 40)
+    b = oracle.knn(ps, 40, h_init=np.full(ps.n, 0.01))
+    np.testing.assert_array_equal(a["h"], b["h"])
+    perm = np.random.default_rng(75).permutation(ps.n)
+    q = sphgen.ParticleSet(x=ps.x[perm], y=ps.y[perm], z=ps.z[perm], m=ps.m[perm],
+                           h_init=ps.h_init[perm], periodic=True, box=1.0, n_target=64.0,
+                           n_tol=2.0)
+    c = oracle.knn(q, 40)
+    np.testing.assert_array_equal(c["h"], a["h"][perm])
