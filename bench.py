@@ -265,6 +265,33 @@ def run_wendland(sph, torch, d, ps, steps):
     return out
 
 
+def run_knn(sph, torch, d, ps, steps, dk=16.0):
+    """The paper's own criterion at its scale: h = distance of the 295th
+    nearest particle (itself first), Wendland C6, on the clustered 2^20 set
+    (FP32C and FP64); sort + count stage + selection + evaluation per step."""
+    out = {"workload": f"clustered2^20, Wendland C6 kernel, exact K = 295 (count band "
+                       f"[K, K + {int(dk)}] then selection), h_init = 2 N^-1/3"}
+    for prec, name in ((sph.FP32C, "fp32c"), (sph.FP64, "fp64")):
+        p = sph.default_params(periodic=1, box=ps.box, n_target=295.0, n_tol=dk,
+                               precision=prec, kernel=sph.KERNEL_WENDLAND_C6, mode=sph.KNN)
+        ws = sph.workspace(p, ps.n, 0, d["x"].device)
+        o = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws)
+        torch.cuda.synchronize()
+        flagged = int(((o["status"] >> 16) != 0).sum().item())
+        iters = int((o["status"] & 0xFFFF).max().item())
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[name] = {"ms_per_step": ms, "particles_per_s": ps.n / (ms * 1e-3),
+                     "flagged": flagged, "max_count_updates": iters}
+    out["fp32c_speedup_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32c"]["ms_per_step"]
+    return out
+
+
 def cpu_baseline(ps, budget_s=15.0):
     """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
     import oracle
@@ -406,6 +433,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-wendland", action="store_true")
+    ap.add_argument("--no-knn", action="store_true")
     ap.add_argument("--profile-run", action="store_true",
                     help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "CMD"),
@@ -463,6 +491,10 @@ def main():
     if not args.no_wendland:
         wc6 = run_wendland(sph, torch, d, ps, max(3, args.steps // 2))
         print(f"[bench] wendland {wc6}", file=sys.stderr, flush=True)
+    knn = None
+    if not args.no_knn:
+        knn = run_knn(sph, torch, d, ps, max(3, args.steps // 2))
+        print(f"[bench] knn {knn}", file=sys.stderr, flush=True)
     big = None
     if not args.no_large:
         big = run_large(sph, torch, 3)
@@ -518,6 +550,8 @@ def main():
         line["large"] = big
     if wc6 is not None:
         line["wendland_c6"] = wc6
+    if knn is not None:
+        line["exact_k"] = knn
     if adj is not None:
         line["adjoint"] = adj
     if not args.no_cpu_baseline:

@@ -75,6 +75,20 @@ extern "C" {
 #define SPH_BAND   0   /* stop when |n - n_target| <= n_tol */
 #define SPH_ROOT   1   /* stop when |n - n_target| <= root_tol * n_target, or when the
                           bracket [lo, hi] has shrunk to 4 ulp(h) */
+#define SPH_KNN    2   /* exact K nearest (Sec. IV-D): h = the distance of the K-th
+                          nearest particle of the particle's set, the particle itself
+                          counted first, K = n_target (an integer in [2, 2^20]); rho,
+                          nw and nngb are evaluated at that h (where the K-th neighbour
+                          has W = 0).  If K particles coincide, h = 0 and rho is not
+                          finite.  Found by iterating h on the integer count
+                          N = #(r < h) into [K, K + n_tol] (n_tol an integer in
+                          [0, 48]) and selecting the K-th smallest distance among
+                          those N.  FP32C selects from binary32 coordinates with
+                          binary64 differences.  The low status bits count the
+                          count-stage updates; NOCONV also marks a particle whose
+                          selection did not find K inside the count-stage h.
+                          sph_density_backward rejects this mode (SPH_E_UNSUPPORTED):
+                          h is not a smooth function of the positions. */
 
 /* status_out[i]: low 16 bits = number of h updates made, high bits = flags */
 #define SPH_ST_ITER_MASK   0xFFFF

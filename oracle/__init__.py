@@ -105,7 +105,7 @@ def lib():
         L.oracle_backward.argtypes = [C.POINTER(_Cfg), C.c_int64, P, P, P, P, P, P, P,
                                       P, P, P, P]
         L.oracle_knn.argtypes = [C.POINTER(_Cfg), C.c_int64, P, P, P, P, P, C.c_int32,
-                                 P, P, P, P, P]
+                                 P, C.c_int64, P, P, P, P, P]
         L.oracle_max_threads.restype = C.c_int32
         L.oracle_max_threads.argtypes = []
         _lib = L
@@ -280,18 +280,22 @@ def solve(ps, h_init=None, subset=None, mode=BAND, root_tol=1e-12, max_iter=64, 
     return dict(rho=rho, h=h, nw=nw, dndh=dndh, nngb=nngb, status=status, pairs=pairs)
 
 
-def knn(ps, K, h_init=None, search=1, nthreads=0, kernel=M4):
+def knn(ps, K, h_init=None, subset=None, search=1, nthreads=0, kernel=M4):
     """Exact K-nearest criterion: h = distance of the K-th nearest particle
     (the particle itself first), rho etc. at that h; dict(rho, h, nw, nngb,
-    status)."""
+    status).  With ``subset`` only the listed particles are done (each against
+    the full set) and outputs follow ``subset``'s order."""
     c, _keep = _cfg(ps, search=search, nthreads=nthreads, kernel=kernel)
     x, y, z, m = _d(ps.x), _d(ps.y), _d(ps.z), _d(ps.m)
     h0 = _d(ps.h_init if h_init is None else h_init)
     n = x.shape[0]
-    rho, h, nw = (np.empty(n) for _ in range(3))
-    nngb = np.empty(n, dtype=np.int32)
-    status = np.empty(n, dtype=np.int32)
-    lib().oracle_knn(C.byref(c), n, _p(x), _p(y), _p(z), _p(m), _p(h0), int(K), _p(rho),
+    sub = None if subset is None else np.ascontiguousarray(subset, dtype=np.int64)
+    cnt = n if sub is None else sub.shape[0]
+    rho, h, nw = (np.empty(cnt) for _ in range(3))
+    nngb = np.empty(cnt, dtype=np.int32)
+    status = np.empty(cnt, dtype=np.int32)
+    lib().oracle_knn(C.byref(c), n, _p(x), _p(y), _p(z), _p(m), _p(h0), int(K),
+                     None if sub is None else sub.ctypes.data_as(C.c_void_p), cnt, _p(rho),
                      _p(h), _p(nw), _p(nngb), _p(status))
     return dict(rho=rho, h=h, nw=nw, nngb=nngb, status=status)
 

@@ -783,7 +783,8 @@ void oracle_solve(const orc_cfg *c, int64_t n, const double *x, const double *y,
  * Flags: UNREACHABLE for a group with fewer than K valid particles (h stays
  * h_init, rho evaluated there); H_TOO_LARGE when the periodic ball reaches the
  * cap L/2 (1 - 2^-20) before holding K (h = the cap).  The low 16 status bits
- * are 0 (no iteration here). */
+ * are 0 (no iteration here).  subset == NULL: every particle, outputs indexed
+ * by particle; else the listed ones, outputs indexed by position in subset. */
 typedef struct { double *d2; int64_t cnt, cap; } d2_list;
 
 static void d2_visit(void *u, int64_t j, double r2, const double *d)
@@ -805,6 +806,7 @@ static int cmp_double(const void *a, const void *b)
 
 void oracle_knn(const orc_cfg *c, int64_t n, const double *x, const double *y,
                 const double *z, const double *m, const double *h_init, int32_t K,
+                const int64_t *subset, int64_t nsub,
                 double *rho, double *h, double *nw, int32_t *nngb, int32_t *status)
 {
     ctx_t k;
@@ -812,12 +814,14 @@ void oracle_knn(const orc_cfg *c, int64_t n, const double *x, const double *y,
     ctx_init(&k, c, n, x, y, z, m, h_init);
     const double hmax = c->periodic ? 0.5 * c->box * (1.0 - 0x1p-20) : INFINITY;
     const double sg = oracle_sigma(c->kernel), cc = oracle_count_const(c->kernel);
+    const int64_t cnt = subset ? nsub : n;
 #pragma omp parallel for schedule(dynamic, 4)
-    for (int64_t i = 0; i < n; ++i) {
+    for (int64_t u = 0; u < cnt; ++u) {
+        const int64_t i = subset ? subset[u] : u;
         double hi = h_init[i];
         int32_t flags = 0;
         if (!k.valid[i]) {
-            rho[i] = NAN; h[i] = hi; nw[i] = NAN; nngb[i] = 0; status[i] = ORC_BADINPUT;
+            rho[u] = NAN; h[u] = hi; nw[u] = NAN; nngb[u] = 0; status[u] = ORC_BADINPUT;
             continue;
         }
         int64_t b, e;
@@ -848,11 +852,11 @@ void oracle_knn(const orc_cfg *c, int64_t n, const double *x, const double *y,
             free(L.d2);
         }
         sums_t s = eval_sums(&k, i, hi);
-        h[i] = hi;
-        rho[i] = sg * s.R / (hi * hi * hi);
-        nw[i] = cc * s.S0;
-        nngb[i] = (int32_t)s.N;
-        status[i] = flags;
+        h[u] = hi;
+        rho[u] = sg * s.R / (hi * hi * hi);
+        nw[u] = cc * s.S0;
+        nngb[u] = (int32_t)s.N;
+        status[u] = flags;
     }
     ctx_free(&k);
 }

@@ -18,7 +18,7 @@ import os
 __all__ = [
     "LIB_PATH", "Params", "SPHError", "load", "default_params", "workspace_size", "sort",
     "density_solve", "density_backward", "autotune", "density", "SPHDensity", "status_string",
-    "FP64", "FP32C", "F64", "F32", "BAND", "ROOT",
+    "FP64", "FP32C", "F64", "F32", "BAND", "ROOT", "KNN", "KERNEL_M4", "KERNEL_WENDLAND_C6",
     "ST_NOCONV", "ST_HTOOLARGE", "ST_BADINPUT", "ST_UNREACHABLE",
 ]
 
@@ -26,7 +26,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsph.so")
 
 FP64, FP32C = 0, 1
 F64, F32 = 0, 1
-BAND, ROOT = 0, 1
+BAND, ROOT, KNN = 0, 1, 2
 ABI_VERSION = 1
 OK, E_INVALID, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4
 ST_NOCONV = 1 << 16

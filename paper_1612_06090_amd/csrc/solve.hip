@@ -63,6 +63,10 @@ struct SolveArgs {
     int32_t *nngb, *status;
     int32_t *queue;
     uint64_t *stats;
+    // exact-K stages: the count stage's h and status, the selected h
+    double *knn_h;
+    int32_t *knn_st;
+    double *sh_out;
 };
 
 // Values every lane of the wave already holds (results of a full-wave
@@ -87,9 +91,46 @@ struct HState {
 };
 
 // One update of the h iteration.  Returns true when the particle is finished.
-__device__ inline bool h_step(HState &s, double nwv, double dndh, const SolveArgs &a,
-                              double hmax) {
+// Exact-K mode iterates on the integer count N = #(r < h) towards the band
+// [K, K + dK] with a volume-ratio step h (K' / N)^(1/3), K' the band centre,
+// under the same bracket safeguards; the result only has to bracket the K-th
+// distance, so the path does not affect what is returned.
+template <bool KNN>
+__device__ inline bool h_step(HState &s, double nwv, double dndh, int32_t ncount,
+                              const SolveArgs &a, double hmax) {
     if (s.fixed) return true;
+    if (KNN) {
+        const double N = (double)ncount;
+        if (N >= a.Nt && N <= a.Nt + a.dN) return true;
+        if (N < a.Nt) s.lo = s.h; else s.hi = s.h;
+        // Out of updates, or the bracket has closed on a tie (several
+        // neighbours at one distance make the count jump over the band): the
+        // upper end holds more than K + dK, and the selection stage takes the
+        // K-th from there if its list can rank it
+        const bool closed = s.lo > 0.0 && s.hi < INFINITY &&
+                            s.hi - s.lo <= 4.0 * (nextafter(s.hi, INFINITY) - s.hi);
+        if (s.it >= a.max_iter || closed) {
+            if (s.hi < INFINITY) s.h = s.hi;
+            else s.flags |= SPH_ST_NOCONV;
+            return true;
+        }
+        double hn = s.h * cbrt((a.Nt + 0.5 * a.dN + 0.5) / fmax(N, 1.0));
+        if (!(hn > s.lo && hn < s.hi && hn >= 0.5 * s.h && hn <= 2.0 * s.h)) {
+            if (s.hi == INFINITY) hn = 2.0 * s.h;
+            else if (s.lo == 0.0) hn = 0.5 * s.h;
+            else hn = 0.5 * (s.lo + s.hi);
+        }
+        if (hn >= hmax) {
+            if (s.h == hmax) {
+                s.flags |= SPH_ST_HTOOLARGE;
+                return true;
+            }
+            hn = hmax;
+        }
+        s.h = hn;
+        s.it += 1;
+        return false;
+    }
     bool conv;
     if (a.mode == SPH_BAND) {
         conv = fabs(nwv - a.Nt) <= a.dN;
@@ -233,9 +274,66 @@ __device__ inline void kahan(float &s, float &c, float x) {
 // copies' sums are combined before the (replicated) h update.  Smaller P
 // means a smaller tile region (fewer candidates per particle) and a shorter
 // sequential stream per wave, at the price of more tiles.
-template <int PREC, bool GROUPED, int P, int KERNEL>
+// Selection heap of the exact-K mode: per lane, a min-heap of the 64 largest
+// squared distances inside h, slot i of lane l at [i * 64 + l].
+constexpr int kSelCap = 64;
+
+__device__ inline void sel_insert(double *H, int l, int &hc, double x) {
+    if (hc < kSelCap) {
+        int i = hc++;
+        while (i > 0) {
+            const int q = (i - 1) >> 1;
+            const double pv = H[q * 64 + l];
+            if (pv <= x) break;
+            H[i * 64 + l] = pv;
+            i = q;
+        }
+        H[i * 64 + l] = x;
+    } else if (x > H[l]) {
+        int i = 0;
+        for (;;) {
+            int c = 2 * i + 1;
+            if (c >= kSelCap) break;
+            double cv = H[c * 64 + l];
+            if (c + 1 < kSelCap && H[(c + 1) * 64 + l] < cv) { ++c; cv = H[c * 64 + l]; }
+            if (cv >= x) break;
+            H[i * 64 + l] = cv;
+            i = c;
+        }
+        H[i * 64 + l] = x;
+    }
+}
+
+// Remove the heap minimum (heap of size hc > 0).
+__device__ inline void sel_pop(double *H, int l, int &hc) {
+    const double x = H[(hc - 1) * 64 + l];
+    --hc;
+    int i = 0;
+    for (;;) {
+        int c = 2 * i + 1;
+        if (c >= hc) break;
+        double cv = H[c * 64 + l];
+        if (c + 1 < hc && H[(c + 1) * 64 + l] < cv) { ++c; cv = H[c * 64 + l]; }
+        if (cv >= x) break;
+        H[i * 64 + l] = cv;
+        i = c;
+    }
+    if (hc > 0) H[i * 64 + l] = x;
+}
+
+// STAGE 0: the density solve of the band and root modes.  Exact K runs three
+// launches: 1 iterates h on the integer count into the band [K, K + dK]
+// (writes knn_h, knn_st); 2 selects (one lane per particle, P = 64): at the
+// count-stage h of each particle the squared distances inside h go through the
+// lane's heap, and the K-th smallest becomes the particle's h (writes sh_out,
+// knn_st); 3 evaluates at that h with the status of knn_st.  The stage is a
+// template argument so that the band-mode kernel carries none of it.
+template <int PREC, bool GROUPED, int P, int KERNEL, int STAGE = 0>
 __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     using KT = Kern<KERNEL>;
+    constexpr bool SEL = STAGE == 2;
+    static_assert(!SEL || P == 64, "the selection pass holds one particle per lane");
+    __shared__ double selheap[SEL ? 64 * kSelCap : 1];
     constexpr int S = 64 / P;
     __shared__ double act_t[3][64];
     __shared__ double act_H[64];
@@ -285,12 +383,19 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         int32_t qxi = 0, qyi = 0, qzi = 0;    // FP32C grid coordinates
         float fxi = 0.f, fyi = 0.f, fzi = 0.f;
         HState hs;
-        hs.h = mine ? a.sh0[s] : 1.0;
+        hs.h = mine ? (SEL ? a.knn_h[s] : a.sh0[s]) : 1.0;
         hs.lo = 0.0;
         hs.hi = INFINITY;
         hs.it = 0;
         hs.flags = 0;
-        hs.fixed = a.max_iter == 0;
+        hs.fixed = a.max_iter == 0 || STAGE >= 2;
+        // exact-K stages 2 and 3 carry the count stage's status
+        const int32_t st_in = (STAGE >= 2 && mine) ? a.knn_st[s] : 0;
+        if (STAGE == 3) {
+            hs.flags = st_in & ~0xFFFF;
+            hs.it = st_in & 0xFFFF;
+        }
+        int sel_n = 0, sel_hc = 0;  // selection: in-range count, heap size
         bool valid = false;
         if (mine) {
             if (PREC == SPH_FP64) {
@@ -313,17 +418,24 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             }
         };
         if (mine && !valid && kk == 0) {
-            write_out(a, a.perm[s], NAN, hs.h, NAN, 0, SPH_ST_BADINPUT);
+            if (SEL) a.sh_out[s] = hs.h;
+            else write_out(a, a.perm[s], NAN, hs.h, NAN, 0, SPH_ST_BADINPUT);
+            if (STAGE == 1) { a.knn_h[s] = hs.h; a.knn_st[s] = SPH_ST_BADINPUT; }
         }
-        if (GROUPED && mine && valid) {
+        if (GROUPED && mine && valid && STAGE <= 1) {
             const double ng = (double)(a.goff[g + 1] - a.goff[g]);
-            if (KT::count * ng < a.Nt - a.dN) {
+            if (STAGE == 1 ? ng < a.Nt : KT::count * ng < a.Nt - a.dN) {
                 hs.flags |= SPH_ST_UNREACHABLE;
                 hs.fixed = true;
             }
         }
         if (hs.h > hmax) hs.h = hmax;
         bool done = !(mine && valid);
+        if (SEL && mine && valid && (st_in >> 16) != 0) {
+            // flagged by the count stage: h passes through unchanged
+            a.sh_out[s] = hs.h;
+            done = true;
+        }
 
         for (;;) {
             // active particles (bits 0..P-1: the lanes of copy 0)
@@ -505,7 +617,38 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                         // candidates per copy, rounded up to the unroll of 4: the slots
                         // past mc hold padding, and 4 * ceil(mc / 4S) * S <= 64
                         const int nu = (((mc + S - 1) / S) + 3) & ~3;
-                        if (in_sub) {
+                        if (SEL && in_sub) {
+                            // selection: squared distances inside h into the heap
+                            if (PREC == SPH_FP64) {
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
+                                for (int t = 0; t < mc; ++t) {
+                                    const double dx = (c.x[t] - xi) + c.shx[t];
+                                    const double dy = (c.y[t] - yi) + c.shy[t];
+                                    const double dz = (c.z[t] - zi) + c.shz[t];
+                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                                    if (r2 < h2) {
+                                        ++sel_n;
+                                        sel_insert(selheap, l, sel_hc, r2);
+                                    }
+                                }
+                            } else {
+                                // binary32 coordinates, differences and squares in
+                                // binary64 (grid units)
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
+                                const double hq2 = hq * hq;
+                                for (int t = 0; t < mc; ++t) {
+                                    const float4 cj = c.c[t];
+                                    const double dx = (double)cj.x - (double)pix;
+                                    const double dy = (double)cj.y - (double)piy;
+                                    const double dz = (double)cj.z - (double)piz;
+                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                                    if (r2 < hq2) {
+                                        ++sel_n;
+                                        sel_insert(selheap, l, sel_hc, r2);
+                                    }
+                                }
+                            }
+                        } else if (in_sub) {
                             if (PREC == SPH_FP64) {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
                                 const double hinv = 1.0 / hs.h;
@@ -592,15 +735,38 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 cnt_cands += pass_cands;
                 cnt_passes += (uint64_t)__popcll(am);
             }
-            if (!done) {
+            if (SEL && !done) {
+                // the K-th smallest of the sel_n distances inside h is the
+                // (sel_n - K + 1)-th largest: pop the heap down to that rank
+                const int rank = sel_n - (int)a.Nt + 1;
+                double hk = hs.h;
+                int32_t stt = st_in;
+                if (rank >= 1 && rank <= sel_hc) {
+                    while (sel_hc > rank) sel_pop(selheap, l, sel_hc);
+                    hk = PREC == SPH_FP64 ? sqrt(selheap[l]) : sqrt(selheap[l]) / sc;
+                } else {
+                    stt |= SPH_ST_NOCONV;  // the count stage's h did not hold K
+                }
+                a.sh_out[b + p] = hk;
+                a.knn_st[b + p] = stt;
+                done = true;
+            }
+            if (!SEL && !done) {
                 const double nwv = KT::count * S0;
                 const double dndh = -KT::count * S1 / hs.h;
                 const double hcur = hs.h;
-                if (h_step(hs, nwv, dndh, a, hmax)) {
+                if (h_step<STAGE == 1>(hs, nwv, dndh, npair, a, hmax)) {
                     const double rho = KT::sigma * R / (hcur * hcur * hcur);
-                    if (kk == 0)
-                        write_out(a, a.perm[b + p], rho, hcur, nwv, npair,
-                                  hs.flags | (hs.it & 0xFFFF));
+                    const int32_t stout = hs.flags | (hs.it & 0xFFFF);
+                    if (kk == 0) {
+                        write_out(a, a.perm[b + p], rho, hcur, nwv, npair, stout);
+                        if (STAGE == 1) {
+                            // hs.h differs from hcur only where the count
+                            // stage hands its upper bracket to the selection
+                            a.knn_h[b + p] = hs.h;
+                            a.knn_st[b + p] = stout;
+                        }
+                    }
                     done = true;
                 }
             }
@@ -613,53 +779,17 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     }
 }
 
-hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw,
-                     int32_t *nngb, int32_t *status, uint64_t *stats, hipStream_t st) {
-    SolveArgs a;
-    a.n = pl.n;
-    a.G = pl.G;
-    a.goff = goff;
-    a.skeys = pl.skeys;
-    a.perm = pl.perm;
-    a.sx = pl.sx; a.sy = pl.sy; a.sz = pl.sz; a.sm = pl.sm; a.sh0 = pl.sh0;
-    a.qx = pl.qx; a.qy = pl.qy; a.qz = pl.qz;
-    a.fx = pl.fx; a.fy = pl.fy; a.fz = pl.fz; a.fm = pl.fm;
-    a.table = pl.table;
-    a.Ld = pl.Ld;
-    a.frame = pl.frame;
-    a.gitems = pl.gitems;
-    a.gorder = pl.gorder;
-    a.n_items = pl.n_items;
-    a.seg = pl.prm.segment;
-    a.box = pl.prm.box;
-    a.bits = pl.bits;
-    a.Nt = pl.prm.n_target;
-    a.dN = pl.prm.n_tol;
-    a.root_tol = pl.prm.root_tol;
-    a.mode = pl.prm.mode;
-    a.max_iter = pl.prm.max_iter;
-    a.cell_exp = pl.prm.tile_cell;
-    a.out_f32 = pl.prm.io_dtype == SPH_F32;
-    a.rho = rho; a.h = h; a.nw = nw;
-    a.nngb = nngb; a.status = status;
-    a.queue = pl.ctrl;
-    a.stats = stats;
-    hipError_t e = run_zero_i32(pl.ctrl, 4, st);
-    if (e != hipSuccess) return e;
-    if (stats) {
-        e = run_zero_u64(stats, 4, st);
-        if (e != hipSuccess) return e;
-    }
-    if (pl.prm.prof_events[0]) {
-        e = hipEventRecord((hipEvent_t)pl.prm.prof_events[0], st);
-        if (e != hipSuccess) return e;
-    }
-    const dim3 grid((unsigned)pl.grid), block(64);
+// One launch of the density kernel with the arguments in `a`; the grid and
+// tile size come from the plan (`seg` particles per work item); `stage` as the
+// kernel's STAGE.
+template <int STAGE>
+static void launch_stage(const Plan &pl, const SolveArgs &a, int P, const dim3 grid,
+                         hipStream_t st) {
+    const dim3 block(64);
     const bool f32c = pl.prm.precision == SPH_FP32C;
-    const int P = pl.prm.segment;
     const bool wc6 = pl.prm.kernel == SPH_KERNEL_WENDLAND_C6;
 #define SPH_LAUNCH_K(PR, GR, PP, KK) \
-    hipLaunchKernelGGL((k_solve<PR, GR, PP, KK>), grid, block, 0, st, a)
+    hipLaunchKernelGGL((k_solve<PR, GR, PP, KK, STAGE>), grid, block, 0, st, a)
 #define SPH_LAUNCH(PR, GR, PP)                                             \
     do {                                                                  \
         if (wc6) SPH_LAUNCH_K(PR, GR, PP, SPH_KERNEL_WENDLAND_C6);        \
@@ -682,7 +812,110 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
 #undef SPH_LAUNCH_P
 #undef SPH_LAUNCH
 #undef SPH_LAUNCH_K
-    e = hipGetLastError();
+}
+
+static hipError_t launch_solve(const Plan &pl, SolveArgs &a, int seg, int64_t grid_n, int stage,
+                               hipStream_t st) {
+    hipError_t e = run_zero_i32(pl.ctrl, 4, st);
+    if (e != hipSuccess) return e;
+    a.queue = pl.ctrl;
+    a.seg = seg;
+    const dim3 grid((unsigned)grid_n), block(64);
+    const bool f32c = pl.prm.precision == SPH_FP32C;
+    if (stage == 2) {
+        // the selection pass needs distances only: one kernel shape per precision
+        if (!pl.grouped) {
+            if (f32c)
+                hipLaunchKernelGGL((k_solve<SPH_FP32C, false, 64, SPH_KERNEL_M4, 2>), grid,
+                                   block, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_solve<SPH_FP64, false, 64, SPH_KERNEL_M4, 2>), grid,
+                                   block, 0, st, a);
+        } else {
+            if (f32c)
+                hipLaunchKernelGGL((k_solve<SPH_FP32C, true, 64, SPH_KERNEL_M4, 2>), grid,
+                                   block, 0, st, a);
+            else
+                hipLaunchKernelGGL((k_solve<SPH_FP64, true, 64, SPH_KERNEL_M4, 2>), grid,
+                                   block, 0, st, a);
+        }
+    } else if (stage == 1) {
+        launch_stage<1>(pl, a, seg, grid, st);
+    } else if (stage == 3) {
+        launch_stage<3>(pl, a, seg, grid, st);
+    } else {
+        launch_stage<0>(pl, a, seg, grid, st);
+    }
+    return hipGetLastError();
+}
+
+hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw,
+                     int32_t *nngb, int32_t *status, uint64_t *stats, hipStream_t st) {
+    SolveArgs a;
+    a.n = pl.n;
+    a.G = pl.G;
+    a.goff = goff;
+    a.skeys = pl.skeys;
+    a.perm = pl.perm;
+    a.sx = pl.sx; a.sy = pl.sy; a.sz = pl.sz; a.sm = pl.sm; a.sh0 = pl.sh0;
+    a.qx = pl.qx; a.qy = pl.qy; a.qz = pl.qz;
+    a.fx = pl.fx; a.fy = pl.fy; a.fz = pl.fz; a.fm = pl.fm;
+    a.table = pl.table;
+    a.Ld = pl.Ld;
+    a.frame = pl.frame;
+    a.gitems = pl.gitems;
+    a.gorder = pl.gorder;
+    a.n_items = pl.n_items;
+    a.box = pl.prm.box;
+    a.bits = pl.bits;
+    a.Nt = pl.prm.n_target;
+    a.dN = pl.prm.n_tol;
+    a.root_tol = pl.prm.root_tol;
+    a.mode = pl.prm.mode;
+    a.max_iter = pl.prm.max_iter;
+    a.cell_exp = pl.prm.tile_cell;
+    a.out_f32 = pl.prm.io_dtype == SPH_F32;
+    a.rho = rho; a.h = h; a.nw = nw;
+    a.nngb = nngb; a.status = status;
+    a.stats = stats;
+    a.knn_h = pl.knn_h;
+    a.knn_st = pl.knn_st;
+    a.sh_out = pl.sh0;
+    hipError_t e = hipSuccess;
+    if (stats) {
+        e = run_zero_u64(stats, 4, st);
+        if (e != hipSuccess) return e;
+    }
+    if (pl.prm.prof_events[0]) {
+        e = hipEventRecord((hipEvent_t)pl.prm.prof_events[0], st);
+        if (e != hipSuccess) return e;
+    }
+    const int seg = pl.prm.segment;
+    if (pl.prm.mode != SPH_KNN) {
+        e = launch_solve(pl, a, seg, pl.grid, 0, st);
+    } else {
+        // exact K: count band, selection of the K-th distance (one particle per
+        // lane), evaluation at that distance
+        const int64_t full = (int64_t)256 * pl.prm.waves_per_cu;
+        e = launch_solve(pl, a, seg, pl.grid, 1, st);
+        if (e == hipSuccess && pl.grouped) {
+            pl.prm.segment = 64;
+            e = run_group_items(pl, goff, st);
+        }
+        if (e == hipSuccess) {
+            a.n_items = ceil_div(pl.n, 64);
+            const int64_t g2 = pl.grouped ? full : (a.n_items < full ? a.n_items : full);
+            e = launch_solve(pl, a, 64, g2 > 0 ? g2 : 1, 2, st);
+        }
+        if (e == hipSuccess && pl.grouped) {
+            pl.prm.segment = seg;
+            e = run_group_items(pl, goff, st);
+        }
+        if (e == hipSuccess) {
+            a.n_items = pl.n_items;
+            e = launch_solve(pl, a, seg, pl.grid, 3, st);
+        }
+    }
     if (e != hipSuccess) return e;
     if (pl.prm.prof_events[1]) e = hipEventRecord((hipEvent_t)pl.prm.prof_events[1], st);
     return e;

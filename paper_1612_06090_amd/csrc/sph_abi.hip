@@ -109,6 +109,10 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
     pl.adj = (double *)take(5 * 8 * N);
     pl.rmq_levels = ceil_log2_i64((int64_t)N) + 1;
     pl.rmq = (float *)take(4 * N * (size_t)pl.rmq_levels);
+    if (p->mode == SPH_KNN) {
+        pl.knn_h = (double *)take(8 * N);
+        pl.knn_st = (int32_t *)take(4 * N);
+    }
     pl.total = off;
     return SPH_OK;
 }
@@ -118,7 +122,7 @@ static int check_params(const sph_params *p, int64_t n, int32_t G, const int64_t
     if (p->abi_version != SPH_ABI_VERSION) return SPH_E_INVALID;
     if (p->precision != SPH_FP64 && p->precision != SPH_FP32C) return SPH_E_INVALID;
     if (p->io_dtype != SPH_F64 && p->io_dtype != SPH_F32) return SPH_E_INVALID;
-    if (p->mode != SPH_BAND && p->mode != SPH_ROOT) return SPH_E_INVALID;
+    if (p->mode != SPH_BAND && p->mode != SPH_ROOT && p->mode != SPH_KNN) return SPH_E_INVALID;
     if (p->periodic != 0 && p->periodic != 1) return SPH_E_INVALID;
     if (n < 0 || n >= ((int64_t)1 << 31) - 1) return SPH_E_INVALID;
     if (p->periodic) {
@@ -131,6 +135,13 @@ static int check_params(const sph_params *p, int64_t n, int32_t G, const int64_t
     if (!(p->n_tol >= 0.0) || !isfinite(p->n_tol)) return SPH_E_INVALID;
     if (p->mode == SPH_ROOT && (!(p->root_tol > 0.0) || !isfinite(p->root_tol)))
         return SPH_E_INVALID;
+    if (p->mode == SPH_KNN) {
+        // K an integer in [2, 2^20] (K = 1 would give h = 0, the particle itself), the
+        // count band slack an integer in [0, 48]
+        if (p->n_target != floor(p->n_target) || p->n_target < 2.0 || p->n_target > 1048576.0)
+            return SPH_E_INVALID;
+        if (p->n_tol != floor(p->n_tol) || p->n_tol > 48.0) return SPH_E_INVALID;
+    }
     if (p->max_iter < 0 || p->max_iter > 65535) return SPH_E_INVALID;
     const int bits = p->periodic ? 21 : 16;
     if (p->cell_level < -1 || p->cell_level > bits || p->cell_level == 0) return SPH_E_INVALID;
@@ -259,6 +270,7 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
                          void *grad_m, void *ws, size_t ws_bytes, void *stream) {
     int rc = check_params(params, n, n_groups, group_offsets);
     if (rc != SPH_OK) return rc;
+    if (params->mode == SPH_KNN) return SPH_E_UNSUPPORTED;
     if (n == 0) return SPH_OK;
     if (!x || !y || !z || !m || !h || !grad_rho || !grad_x || !grad_y || !grad_z || !grad_m)
         return SPH_E_INVALID;

@@ -122,6 +122,8 @@ struct Plan {
     double *adj = nullptr;       // adjoint, sorted order: alpha, beta, gamma, grad_rho, grad_h (5 x n)
     float *rmq = nullptr;        // adjoint: range-max table of h (grid units), rmq_levels x n
     int rmq_levels = 0;
+    double *knn_h = nullptr;     // exact-K mode: count-stage h and status, sorted order
+    int32_t *knn_st = nullptr;
     // after sorting
     uint64_t *skeys = nullptr;
     int32_t *perm = nullptr;

@@ -78,7 +78,7 @@ def test_workspace_size_monotone_and_valid():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("abi_version", 99), ("precision", 7), ("io_dtype", 3), ("mode", 2), ("periodic", 5),
+    ("abi_version", 99), ("precision", 7), ("io_dtype", 3), ("mode", 3), ("periodic", 5),
     ("box", 0.0), ("box", float("nan")), ("n_target", 0.0), ("n_tol", -1.0),
     ("max_iter", -1), ("max_iter", 70000), ("cell_level", 22), ("cell_level", 0),
     ("tile_cell", 3), ("tile_cell", -3), ("kernel", 2), ("kernel", -1), ("waves_per_cu", 0), ("segment", 12), ("segment", 128),
@@ -90,6 +90,35 @@ def test_invalid_params_rejected(field, value):
     out = C.c_size_t(0)
     rc = sph.load().sph_workspace_size(C.byref(p), 100, 0, C.byref(out))
     assert rc == sph.E_INVALID
+
+
+@pytest.mark.parametrize("k,dk,ok", [
+    (64.0, 2.0, True), (2.0, 0.0, True), (1048576.0, 48.0, True),
+    (1.0, 2.0, False), (0.0, 2.0, False), (32.5, 2.0, False), (1048577.0, 2.0, False),
+    (64.0, 1.5, False), (64.0, 49.0, False), (64.0, -1.0, False),
+])
+def test_knn_params(k, dk, ok):
+    # exact-K mode: K an integer in [2, 2^20], the count slack an integer in [0, 48]
+    _lib()
+    p = sph.default_params(mode=sph.KNN, n_target=k, n_tol=dk)
+    out = C.c_size_t(0)
+    rc = sph.load().sph_workspace_size(C.byref(p), 1000, 0, C.byref(out))
+    assert rc == (sph.OK if ok else sph.E_INVALID)
+    if ok:
+        # the count stage keeps its h and status beside the band-mode workspace
+        band = sph.workspace_size(sph.default_params(n_target=k, n_tol=dk), 1000)
+        assert out.value >= band + 12 * 1000
+
+
+def test_knn_backward_unsupported():
+    # h of the K-th neighbour is not differentiable in the positions: refused on the host
+    lib = _lib()
+    p = sph.default_params(mode=sph.KNN, n_target=32.0, n_tol=2.0)
+    fake = C.c_void_p(0x1000)
+    rc = lib.sph_density_backward(C.byref(p), 10, 0, None, fake, fake, fake, fake, fake, None,
+                                  fake, fake, fake, fake, fake, C.c_void_p(0x100000), 1 << 30,
+                                  None)
+    assert rc == sph.E_UNSUPPORTED
 
 
 def test_invalid_calls_rejected_before_any_launch():

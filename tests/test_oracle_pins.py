@@ -614,3 +614,8 @@ def test_knn_flags_and_order():
                            n_tol=2.0)
     c = oracle.knn(q, 40)
     np.testing.assert_array_equal(c["h"], a["h"][perm])
+    # a subset gives the same rows as the full run
+    sub = np.array([5, 0, 899, 5, 431])
+    d = oracle.knn(ps, 40, subset=sub)
+    for k in ("h", "rho", "nngb", "status"):
+        np.testing.assert_array_equal(d[k], a[k][sub])
