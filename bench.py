@@ -265,7 +265,7 @@ def run_wendland(sph, torch, d, ps, steps):
     return out
 
 
-def run_knn(sph, torch, d, ps, steps, dk=16.0):
+def run_knn(sph, torch, d, ps, steps, dk=14.0):
     """The paper's own criterion at its scale: h = distance of the 295th
     nearest particle (itself first), Wendland C6, on the clustered 2^20 set
     (FP32C and FP64); sort + count stage + selection + evaluation per step."""
@@ -398,27 +398,42 @@ def summarize_traffic(fetch_csv, write_csv, cmd):
 
 
 TRACE_MD = os.path.join(ROOT, "profiles", "k_solve_clustered2p20_kernel_trace.md")
+TRACE_KNN_MD = os.path.join(ROOT, "profiles", "k_solve_exactK295_clustered2p20_kernel_trace.md")
 
 
-def summarize_trace(stats_csv, cmd):
+def summarize_trace(stats_csv, cmd, which="headline"):
     """Kernel-time table from rocprofv3 --kernel-trace --stats (kernel_stats.csv)."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    out = ["# k_solve on clustered2^20 — rocprofv3 kernel trace", "",
-           "Command (GPU box, repo root):", "", "    " + cmd, "",
-           "Workload: the 2^20-particle clustered set (200 Plummer spheres + 30% background), "
-           "N_t = 64 +- 2; one call = keys + radix sort + permute + dense cell table + "
-           "density/h solve. `k_solve<1, ...>` is the FP32C solve, `k_solve<0, ...>` the FP64 "
-           "one, both with 16-particle tiles.", "",
-           f"Solve source sha256: `{solve_source_sha()}`", "",
-           "| Kernel | Calls | Avg (us) | Share |", "|---|---|---|---|"]
+    if which == "knn":
+        path = TRACE_KNN_MD
+        head = ["# Exact-K stages on clustered2^20 (K = 295, Wendland C6) — rocprofv3 "
+                "kernel trace", "",
+                "Command (GPU box, repo root):", "", "    " + cmd, "",
+                "Workload: the 2^20-particle clustered set, h = distance of the 295th "
+                "nearest particle (itself first), Wendland C6, count band [K, K + 14]. "
+                "One call = sort + three launches of the density kernel, told apart by "
+                "its last template argument: 1 the count stage (h iterated on the "
+                "integer count), 2 the selection of the K-th distance (one particle per "
+                "lane), 3 the evaluation at that h. `k_solve<1, ...>` is FP32C, "
+                "`k_solve<0, ...>` FP64.", ""]
+    else:
+        path = TRACE_MD
+        head = ["# k_solve on clustered2^20 — rocprofv3 kernel trace", "",
+                "Command (GPU box, repo root):", "", "    " + cmd, "",
+                "Workload: the 2^20-particle clustered set (200 Plummer spheres + 30% "
+                "background), N_t = 64 +- 2; one call = keys + radix sort + permute + dense "
+                "cell table + density/h solve. `k_solve<1, ...>` is the FP32C solve, "
+                "`k_solve<0, ...>` the FP64 one, both with 16-particle tiles.", ""]
+    out = head + [f"Solve source sha256: `{solve_source_sha()}`", "",
+                  "| Kernel | Calls | Avg (us) | Share |", "|---|---|---|---|"]
     for r in rows[:14]:
         name = r["Name"].split("(")[0]
         out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
                    f"{float(r['Percentage']):.2f}% |")
-    os.makedirs(os.path.dirname(TRACE_MD), exist_ok=True)
-    open(TRACE_MD, "w").write("\n".join(out) + "\n")
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    open(path, "w").write("\n".join(out) + "\n")
     print("\n".join(out))
 
 
@@ -434,14 +449,19 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-wendland", action="store_true")
     ap.add_argument("--no-knn", action="store_true")
+    ap.add_argument("--only-knn", action="store_true",
+                    help="only the exact-K leg (for a kernel trace of its stages)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
-    ap.add_argument("--summarize-trace", nargs=2, metavar=("STATS_CSV", "CMD"),
-                    help="write the kernel-trace summary from rocprofv3 --stats output")
+    ap.add_argument("--summarize-trace", nargs="+", metavar="ARG",
+                    help="STATS_CSV CMD [headline|knn]: write the kernel-trace summary "
+                         "from rocprofv3 --stats output")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
                     help="write the k_solve traffic summary from two --pmc runs")
     args = ap.parse_args()
     if args.summarize_trace:
+        if len(args.summarize_trace) not in (2, 3):
+            ap.error("--summarize-trace takes STATS_CSV CMD [headline|knn]")
         summarize_trace(*args.summarize_trace)
         return
     if args.summarize_traffic:
@@ -468,6 +488,10 @@ def main():
          for k in ("x", "y", "z", "m", "h_init")}
     ev = HipEvents()
     print(f"[bench] n={ps.n} steps={args.steps} warmup={args.warmup}", file=sys.stderr, flush=True)
+    if args.only_knn:
+        print(json.dumps({"exact_k": run_knn(sph, torch, d, ps, max(3, args.steps // 2))}),
+              flush=True)
+        return
     f32 = run_form(sph, torch, d, ps, sph.FP32C, args.steps, args.warmup, ev)
     print(f"[bench] fp32c {f32}", file=sys.stderr, flush=True)
     f64 = None

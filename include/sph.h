@@ -84,9 +84,15 @@ extern "C" {
                           N = #(r < h) into [K, K + n_tol] (n_tol an integer in
                           [0, 48]) and selecting the K-th smallest distance among
                           those N.  FP32C selects from binary32 coordinates with
-                          binary64 differences.  The low status bits count the
+                          binary64 differences.  The selection keeps the 16, 32 or
+                          64 largest distances inside the count-stage h (for n_tol
+                          up to 14, 30, 48); where ties make the count jump over the
+                          band, the count stage hands over a bracket end holding up
+                          to that many more than K.  The low status bits count the
                           count-stage updates; NOCONV also marks a particle whose
-                          selection did not find K inside the count-stage h.
+                          selection could not rank the K-th distance (the count
+                          stage ran out of updates away from the band, or more
+                          particles tie at the K-th distance than the heap holds).
                           sph_density_backward rejects this mode (SPH_E_UNSUPPORTED):
                           h is not a smooth function of the positions. */
 

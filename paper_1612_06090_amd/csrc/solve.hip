@@ -34,6 +34,8 @@
 //           convergence test and the h update stay binary64.
 #include "sph_internal.h"
 
+#include <type_traits>
+
 namespace sph {
 
 constexpr int kMaxRegionCells = 512;  // split tiles whose region needs more cells
@@ -65,6 +67,7 @@ struct SolveArgs {
     uint64_t *stats;
     // exact-K stages: the count stage's h and status, the selected h
     double *knn_h;
+    int32_t sel_cap;  // entries of the selection heap (16, 32 or 64)
     int32_t *knn_st;
     double *sh_out;
 };
@@ -88,13 +91,28 @@ struct HState {
     double h, lo, hi;
     int it, flags;
     bool fixed;
+    // exact-K count stage: counts at the bracket ends, bracket width before
+    // the last step
+    int nlo, nhi;
+    double wprev;
 };
+
 
 // One update of the h iteration.  Returns true when the particle is finished.
 // Exact-K mode iterates on the integer count N = #(r < h) towards the band
-// [K, K + dK] with a volume-ratio step h (K' / N)^(1/3), K' the band centre,
-// under the same bracket safeguards; the result only has to bracket the K-th
-// distance, so the path does not affect what is returned.
+// [K, K + dK].  Until both ends are bracketed it takes the volume-ratio step
+// h (K' / N)^(1/3) (K' the band centre) within [h/8, 2h] (a count far above
+// the band is a reliable measure of how much to shrink; growing is capped
+// harder, a sphere that reaches a clump can overshoot); once bracketed it
+// interpolates log N linearly in log h between the ends (the count's local
+// power law, which is steep where the sphere reaches a clump and makes the
+// plain volume step oscillate), kept 5% inside the bracket, and bisects
+// whenever the previous step did not halve the bracket.  Any h whose count
+// lies in [K, K + sel_cap - 1] lets the selection stage find the K-th
+// distance, so the upper end is handed over once the bracket is narrower than
+// 2^-10 h and its count within reach of the selection heap (ties: the count
+// jumps over the band), or when the updates run out; the
+// path does not affect what is returned.
 template <bool KNN>
 __device__ inline bool h_step(HState &s, double nwv, double dndh, int32_t ncount,
                               const SolveArgs &a, double hmax) {
@@ -102,23 +120,34 @@ __device__ inline bool h_step(HState &s, double nwv, double dndh, int32_t ncount
     if (KNN) {
         const double N = (double)ncount;
         if (N >= a.Nt && N <= a.Nt + a.dN) return true;
-        if (N < a.Nt) s.lo = s.h; else s.hi = s.h;
-        // Out of updates, or the bracket has closed on a tie (several
-        // neighbours at one distance make the count jump over the band): the
-        // upper end holds more than K + dK, and the selection stage takes the
-        // K-th from there if its list can rank it
-        const bool closed = s.lo > 0.0 && s.hi < INFINITY &&
-                            s.hi - s.lo <= 4.0 * (nextafter(s.hi, INFINITY) - s.hi);
-        if (s.it >= a.max_iter || closed) {
+        if (N < a.Nt) { s.lo = s.h; s.nlo = ncount; } else { s.hi = s.h; s.nhi = ncount; }
+        const bool br = s.lo > 0.0 && s.hi < INFINITY;
+        const bool narrow = br && s.hi - s.lo <= 0x1p-10 * s.hi &&
+                            (double)s.nhi - a.Nt < (double)a.sel_cap;
+        const bool closed = br && s.hi - s.lo <= 4.0 * (nextafter(s.hi, INFINITY) - s.hi);
+        if (narrow || closed || s.it >= a.max_iter) {
             if (s.hi < INFINITY) s.h = s.hi;
             else s.flags |= SPH_ST_NOCONV;
             return true;
         }
-        double hn = s.h * cbrt((a.Nt + 0.5 * a.dN + 0.5) / fmax(N, 1.0));
-        if (!(hn > s.lo && hn < s.hi && hn >= 0.5 * s.h && hn <= 2.0 * s.h)) {
-            if (s.hi == INFINITY) hn = 2.0 * s.h;
-            else if (s.lo == 0.0) hn = 0.5 * s.h;
-            else hn = 0.5 * (s.lo + s.hi);
+        const double Kc = a.Nt + 0.5 * a.dN + 0.5;
+        double hn;
+        if (br) {
+            const double w = s.hi - s.lo;
+            if (w > 0.5 * s.wprev || s.nlo < 1) {
+                hn = 0.5 * (s.lo + s.hi);
+            } else {
+                // binary32 is ample for a step that is checked against the bracket
+                const float lnlo = __logf((float)s.nlo);
+                float t = (__logf((float)Kc) - lnlo) / (__logf((float)s.nhi) - lnlo);
+                t = fminf(fmaxf(t, 0.05f), 0.95f);
+                hn = s.lo * (double)__expf(t * __logf((float)(s.hi / s.lo)));
+                if (!(hn > s.lo && hn < s.hi)) hn = 0.5 * (s.lo + s.hi);
+            }
+            s.wprev = w;
+        } else {
+            hn = s.h * cbrt(Kc / fmax(N, 1.0));
+            hn = fmin(fmax(hn, 0.125 * s.h), 2.0 * s.h);
         }
         if (hn >= hmax) {
             if (s.h == hmax) {
@@ -274,45 +303,50 @@ __device__ inline void kahan(float &s, float &c, float x) {
 // copies' sums are combined before the (replicated) h update.  Smaller P
 // means a smaller tile region (fewer candidates per particle) and a shorter
 // sequential stream per wave, at the price of more tiles.
-// Selection heap of the exact-K mode: per lane, a min-heap of the 64 largest
-// squared distances inside h, slot i of lane l at [i * 64 + l].
-constexpr int kSelCap = 64;
-
-__device__ inline void sel_insert(double *H, int l, int &hc, double x) {
-    if (hc < kSelCap) {
+// Selection heap of the exact-K mode: per lane, a min-heap of the CAP largest
+// squared distances inside h (binary64 for FP64, binary32 for FP32C: rounding
+// is monotone, so the order is kept and only the selected value is rounded),
+// slot i of lane l at [i * 64 + l].  `hmin` mirrors the root in a register, so
+// a candidate below it costs one compare.
+template <int CAP, typename T>
+__device__ inline void sel_insert(T *H, int l, int &hc, T x, T &hmin) {
+    if (hc < CAP) {
         int i = hc++;
         while (i > 0) {
             const int q = (i - 1) >> 1;
-            const double pv = H[q * 64 + l];
+            const T pv = H[q * 64 + l];
             if (pv <= x) break;
             H[i * 64 + l] = pv;
             i = q;
         }
         H[i * 64 + l] = x;
-    } else if (x > H[l]) {
+        hmin = H[l];
+    } else if (x > hmin) {
         int i = 0;
         for (;;) {
             int c = 2 * i + 1;
-            if (c >= kSelCap) break;
-            double cv = H[c * 64 + l];
-            if (c + 1 < kSelCap && H[(c + 1) * 64 + l] < cv) { ++c; cv = H[c * 64 + l]; }
+            if (c >= CAP) break;
+            T cv = H[c * 64 + l];
+            if (c + 1 < CAP && H[(c + 1) * 64 + l] < cv) { ++c; cv = H[c * 64 + l]; }
             if (cv >= x) break;
             H[i * 64 + l] = cv;
             i = c;
         }
         H[i * 64 + l] = x;
+        hmin = H[l];
     }
 }
 
 // Remove the heap minimum (heap of size hc > 0).
-__device__ inline void sel_pop(double *H, int l, int &hc) {
-    const double x = H[(hc - 1) * 64 + l];
+template <typename T>
+__device__ inline void sel_pop(T *H, int l, int &hc) {
+    const T x = H[(hc - 1) * 64 + l];
     --hc;
     int i = 0;
     for (;;) {
         int c = 2 * i + 1;
         if (c >= hc) break;
-        double cv = H[c * 64 + l];
+        T cv = H[c * 64 + l];
         if (c + 1 < hc && H[(c + 1) * 64 + l] < cv) { ++c; cv = H[c * 64 + l]; }
         if (cv >= x) break;
         H[i * 64 + l] = cv;
@@ -328,12 +362,13 @@ __device__ inline void sel_pop(double *H, int l, int &hc) {
 // lane's heap, and the K-th smallest becomes the particle's h (writes sh_out,
 // knn_st); 3 evaluates at that h with the status of knn_st.  The stage is a
 // template argument so that the band-mode kernel carries none of it.
-template <int PREC, bool GROUPED, int P, int KERNEL, int STAGE = 0>
+template <int PREC, bool GROUPED, int P, int KERNEL, int STAGE = 0, int CAP = 64>
 __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     using KT = Kern<KERNEL>;
     constexpr bool SEL = STAGE == 2;
     static_assert(!SEL || P == 64, "the selection pass holds one particle per lane");
-    __shared__ double selheap[SEL ? 64 * kSelCap : 1];
+    using HeapT = typename std::conditional<PREC == SPH_FP64, double, float>::type;
+    __shared__ HeapT selheap[SEL ? 64 * CAP : 1];
     constexpr int S = 64 / P;
     __shared__ double act_t[3][64];
     __shared__ double act_H[64];
@@ -388,6 +423,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         hs.hi = INFINITY;
         hs.it = 0;
         hs.flags = 0;
+        hs.nlo = hs.nhi = 0;
+        hs.wprev = INFINITY;
         hs.fixed = a.max_iter == 0 || STAGE >= 2;
         // exact-K stages 2 and 3 carry the count stage's status
         const int32_t st_in = (STAGE >= 2 && mine) ? a.knn_st[s] : 0;
@@ -396,6 +433,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             hs.it = st_in & 0xFFFF;
         }
         int sel_n = 0, sel_hc = 0;  // selection: in-range count, heap size
+        HeapT sel_min = 0;          // selection: the heap's root
         bool valid = false;
         if (mine) {
             if (PREC == SPH_FP64) {
@@ -628,14 +666,18 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                                     if (r2 < h2) {
                                         ++sel_n;
-                                        sel_insert(selheap, l, sel_hc, r2);
+                                        sel_insert<CAP>(selheap, l, sel_hc, (HeapT)r2, sel_min);
                                     }
                                 }
                             } else {
                                 // binary32 coordinates, differences and squares in
-                                // binary64 (grid units)
+                                // binary64 (grid units).  The sphere is widened by a
+                                // relative 2^-19 so that it holds every particle the
+                                // count stage's binary32 test counted inside h (its
+                                // rounding stays below 2^-21 of r^2): the list then
+                                // holds at least K, and its order is the binary64 one
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
-                                const double hq2 = hq * hq;
+                                const double hq2 = hq * hq * (1.0 + 0x1p-18);
                                 for (int t = 0; t < mc; ++t) {
                                     const float4 cj = c.c[t];
                                     const double dx = (double)cj.x - (double)pix;
@@ -644,7 +686,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                                     if (r2 < hq2) {
                                         ++sel_n;
-                                        sel_insert(selheap, l, sel_hc, r2);
+                                        sel_insert<CAP>(selheap, l, sel_hc, (HeapT)r2, sel_min);
                                     }
                                 }
                             }
@@ -743,7 +785,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 int32_t stt = st_in;
                 if (rank >= 1 && rank <= sel_hc) {
                     while (sel_hc > rank) sel_pop(selheap, l, sel_hc);
-                    hk = PREC == SPH_FP64 ? sqrt(selheap[l]) : sqrt(selheap[l]) / sc;
+                    const double d2 = (double)selheap[l];
+                    hk = PREC == SPH_FP64 ? sqrt(d2) : sqrt(d2) / sc;
                 } else {
                     stt |= SPH_ST_NOCONV;  // the count stage's h did not hold K
                 }
@@ -823,22 +866,25 @@ static hipError_t launch_solve(const Plan &pl, SolveArgs &a, int seg, int64_t gr
     const dim3 grid((unsigned)grid_n), block(64);
     const bool f32c = pl.prm.precision == SPH_FP32C;
     if (stage == 2) {
-        // the selection pass needs distances only: one kernel shape per precision
+        // the selection pass needs distances only: one kernel shape per
+        // precision and heap size
+#define SPH_SEL(PR, GR, CP) \
+    hipLaunchKernelGGL((k_solve<PR, GR, 64, SPH_KERNEL_M4, 2, CP>), grid, block, 0, st, a)
+#define SPH_SEL_CAP(PR, GR)                                  \
+    do {                                                    \
+        if (a.sel_cap == 16) SPH_SEL(PR, GR, 16);           \
+        else if (a.sel_cap == 32) SPH_SEL(PR, GR, 32);      \
+        else SPH_SEL(PR, GR, 64);                           \
+    } while (0)
         if (!pl.grouped) {
-            if (f32c)
-                hipLaunchKernelGGL((k_solve<SPH_FP32C, false, 64, SPH_KERNEL_M4, 2>), grid,
-                                   block, 0, st, a);
-            else
-                hipLaunchKernelGGL((k_solve<SPH_FP64, false, 64, SPH_KERNEL_M4, 2>), grid,
-                                   block, 0, st, a);
+            if (f32c) SPH_SEL_CAP(SPH_FP32C, false);
+            else SPH_SEL_CAP(SPH_FP64, false);
         } else {
-            if (f32c)
-                hipLaunchKernelGGL((k_solve<SPH_FP32C, true, 64, SPH_KERNEL_M4, 2>), grid,
-                                   block, 0, st, a);
-            else
-                hipLaunchKernelGGL((k_solve<SPH_FP64, true, 64, SPH_KERNEL_M4, 2>), grid,
-                                   block, 0, st, a);
+            if (f32c) SPH_SEL_CAP(SPH_FP32C, true);
+            else SPH_SEL_CAP(SPH_FP64, true);
         }
+#undef SPH_SEL_CAP
+#undef SPH_SEL
     } else if (stage == 1) {
         launch_stage<1>(pl, a, seg, grid, st);
     } else if (stage == 3) {
@@ -879,6 +925,10 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     a.nngb = nngb; a.status = status;
     a.stats = stats;
     a.knn_h = pl.knn_h;
+    // the selection ranks up to dK + 1 (one more where FP32C's widened sphere
+    // takes in a particle at the edge); a narrow count-stage bracket is handed
+    // over only while its count stays within the heap
+    a.sel_cap = pl.prm.n_tol + 2.0 <= 16.0 ? 16 : (pl.prm.n_tol + 2.0 <= 32.0 ? 32 : 64);
     a.knn_st = pl.knn_st;
     a.sh_out = pl.sh0;
     hipError_t e = hipSuccess;
