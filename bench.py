@@ -292,6 +292,44 @@ def run_knn(sph, torch, d, ps, steps, dk=14.0):
     return out
 
 
+def run_aos(sph, torch, d, ps, steps):
+    """Array-of-structs interop (Sec. IV-B) on the headline workload: the same
+    FP32C sort + solve reading x, y, z, m, h_init from 224-byte particle structs
+    and writing rho, h, nw, nngb, status back into them, against packed arrays.
+    Alternating rounds; the best round of each."""
+    n = ps.n
+    p = sph.default_params(periodic=1, box=ps.box, n_target=ps.n_target, n_tol=ps.n_tol,
+                           precision=sph.FP32C)
+    ws = sph.workspace(p, n, 0, d["x"].device)
+    S = torch.zeros((n, 28), dtype=torch.float64, device=d["x"].device)
+    for c, k in ((0, "x"), (1, "y"), (2, "z"), (6, "m"), (8, "h_init")):
+        S[:, c] = d[k]
+    iv = S.view(torch.int32)
+    out = dict(rho=S[:, 9], h=S[:, 10], nw=S[:, 11], nngb=iv[:, 24], status=iv[:, 25])
+
+    def packed():
+        sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws)
+
+    def aos():
+        sph.density_solve(S[:, 0], S[:, 1], S[:, 2], S[:, 6], S[:, 8], p, ws=ws, out=out)
+
+    best = {"packed": float("inf"), "aos": float("inf")}
+    for _ in range(3):
+        for name, fn in (("packed", packed), ("aos", aos)):
+            fn()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            for _ in range(steps):
+                fn()
+            b.record()
+            torch.cuda.synchronize()
+            best[name] = min(best[name], a.elapsed_time(b) / steps)
+    return {"workload": "clustered2^20 FP32C sort + solve; inputs and outputs in 224-byte "
+                        "particle structs (stride 224) vs packed arrays",
+            "packed_ms": best["packed"], "aos_ms": best["aos"],
+            "overhead": best["aos"] / best["packed"] - 1.0}
+
+
 def cpu_baseline(ps, budget_s=15.0):
     """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
     import oracle
@@ -449,6 +487,7 @@ def main():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-wendland", action="store_true")
     ap.add_argument("--no-knn", action="store_true")
+    ap.add_argument("--no-aos", action="store_true")
     ap.add_argument("--only-knn", action="store_true",
                     help="only the exact-K leg (for a kernel trace of its stages)")
     ap.add_argument("--profile-run", action="store_true",
@@ -515,6 +554,10 @@ def main():
     if not args.no_wendland:
         wc6 = run_wendland(sph, torch, d, ps, max(3, args.steps // 2))
         print(f"[bench] wendland {wc6}", file=sys.stderr, flush=True)
+    aos = None
+    if not args.no_aos:
+        aos = run_aos(sph, torch, d, ps, max(3, args.steps // 2))
+        print(f"[bench] aos {aos}", file=sys.stderr, flush=True)
     knn = None
     if not args.no_knn:
         knn = run_knn(sph, torch, d, ps, max(3, args.steps // 2))
@@ -576,6 +619,8 @@ def main():
         line["wendland_c6"] = wc6
     if knn is not None:
         line["exact_k"] = knn
+    if aos is not None:
+        line["aos"] = aos
     if adj is not None:
         line["adjoint"] = adj
     if not args.no_cpu_baseline:

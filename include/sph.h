@@ -114,7 +114,7 @@ typedef struct {
     uint32_t abi_version;   /* must be SPH_ABI_VERSION */
     int32_t  precision;     /* SPH_FP64 | SPH_FP32C */
     int32_t  io_dtype;      /* SPH_F64 | SPH_F32 */
-    int32_t  mode;          /* SPH_BAND | SPH_ROOT */
+    int32_t  mode;          /* SPH_BAND | SPH_ROOT | SPH_KNN */
     int32_t  periodic;      /* 1: one periodic cube [0, box)^3 (n_groups must be 0);
                                0: isolated groups given by group_offsets */
     int32_t  max_iter;      /* h updates allowed per particle, 0..65535 (default 64);
@@ -139,7 +139,21 @@ typedef struct {
                                NULL: none */
     int32_t  kernel;        /* smoothing kernel, W(r, h) = sigma/h^3 f(r/h), support r < h:
                                SPH_KERNEL_M4 (default) or SPH_KERNEL_WENDLAND_C6 */
-    int32_t  reserved[7];   /* must be zero */
+    int32_t  in_stride;     /* bytes from particle i to i + 1 in every per-particle input
+                               (x, y, z, m, h_init; h, grad_rho, grad_h of the backward);
+                               0 = packed arrays (the element size).  A caller that keeps
+                               an array of particle structs (Sec. IV-B) passes the struct
+                               size and points each input at its field: the library's
+                               own gather into sorted arrays reads the structs directly.
+                               A multiple of the element size (8 for SPH_F64, 4 for
+                               SPH_F32), at most 65536 */
+    int32_t  out_stride;    /* the same for every per-particle output (rho, h, nw, nngb,
+                               status; grad_x .. grad_m), which are written through the
+                               sort permutation straight into the caller's structs.
+                               0 = packed (floating outputs at the element size, nngb
+                               and status at 4 bytes); else a multiple of the element
+                               size (and of 4), at most 65536, shared by all outputs */
+    int32_t  reserved[5];   /* must be zero */
 } sph_params;
 
 /* Fill *p with the defaults: FP64 compute and io, band mode, periodic unit

@@ -61,7 +61,9 @@ class Params(C.Structure):
         ("segment", C.c_int32),
         ("prof_events", C.c_void_p * 2),
         ("kernel", C.c_int32),
-        ("reserved", C.c_int32 * 7),
+        ("in_stride", C.c_int32),
+        ("out_stride", C.c_int32),
+        ("reserved", C.c_int32 * 5),
     ]
 
 
@@ -175,13 +177,40 @@ def _check_dev(*ts):
             continue
         if not t.is_cuda:
             raise ValueError("libsph works on GPU tensors only")
-        if not t.is_contiguous():
-            raise ValueError("arrays must be contiguous")
+        if t.dtype == _torch().int64 and not t.is_contiguous():
+            raise ValueError("group offsets must be contiguous")
         if dev is None:
             dev = t.device
         elif t.device != dev:
             raise ValueError("all arrays must be on one device")
     return dev
+
+
+def _stride_bytes(*ts):
+    """Common byte stride of 1-D per-particle tensors (0: all packed).
+
+    Packed arrays have stride 1; fields of an array of particle structs are
+    strided views (e.g. ``P[:, 0]`` of an (n, k) tensor) that must share one
+    byte stride, the struct size.
+    """
+    seen = set()
+    for t in ts:
+        if t is None:
+            continue
+        if t.dim() != 1:
+            raise ValueError("per-particle arrays must be 1-D")
+        if t.shape[0] > 1:
+            seen.add(0 if t.stride(0) == 1 else t.stride(0) * t.element_size())
+    if len(seen) > 1:
+        raise ValueError("per-particle arrays must all be packed or share one byte stride")
+    return seen.pop() if seen else 0
+
+
+def _with_strides(params: Params, ins: int, outs: int) -> Params:
+    q = Params.from_buffer_copy(params)
+    q.in_stride = ins
+    q.out_stride = outs
+    return q
 
 
 def _io(params: Params):
@@ -207,6 +236,7 @@ def sort(x, y, z, params: Params | None = None, group_offsets=None, cells=True):
     cst = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if cells else None
     ccn = torch.empty(max(n, 1), dtype=torch.int32, device=dev) if cells else None
     nc = torch.zeros(1, dtype=torch.int32, device=dev) if cells else None
+    params = _with_strides(params, _stride_bytes(x, y, z), 0)
     rc = load().sph_sort(C.byref(params), n, G, _ptr(group_offsets), _ptr(x), _ptr(y), _ptr(z),
                          _ptr(keys), _ptr(perm), _ptr(cid), _ptr(cst), _ptr(ccn), _ptr(nc),
                          _ptr(ws), ws.numel(), _stream(dev))
@@ -220,8 +250,14 @@ def sort(x, y, z, params: Params | None = None, group_offsets=None, cells=True):
 
 
 def density_solve(x, y, z, m, h_init=None, params: Params | None = None, group_offsets=None,
-                  stats=False, ws=None):
-    """``sph_density_solve``: returns dict(rho, h, nw, nngb, status[, stats])."""
+                  stats=False, ws=None, out=None):
+    """``sph_density_solve``: returns dict(rho, h, nw, nngb, status[, stats]).
+
+    Inputs may be strided views into an array of particle structs (one common
+    byte stride); ``out`` may hold preallocated outputs (rho and h required;
+    nw, nngb, status optional), also strided views sharing one byte stride,
+    which the library then writes in place.
+    """
     torch = _torch()
     params = params or default_params()
     dev = _check_dev(x, y, z, m, h_init, group_offsets)
@@ -230,27 +266,38 @@ def density_solve(x, y, z, m, h_init=None, params: Params | None = None, group_o
     if ws is None:
         ws = workspace(params, n, G, dev)
     dt = _io(params)
-    rho = torch.empty(n, dtype=dt, device=dev)
-    h = torch.empty(n, dtype=dt, device=dev)
-    nw = torch.empty(n, dtype=dt, device=dev)
-    nngb = torch.empty(n, dtype=torch.int32, device=dev)
-    status = torch.empty(n, dtype=torch.int32, device=dev)
+    if out is None:
+        rho = torch.empty(n, dtype=dt, device=dev)
+        h = torch.empty(n, dtype=dt, device=dev)
+        nw = torch.empty(n, dtype=dt, device=dev)
+        nngb = torch.empty(n, dtype=torch.int32, device=dev)
+        status = torch.empty(n, dtype=torch.int32, device=dev)
+    else:
+        rho, h = out["rho"], out["h"]
+        nw, nngb, status = out.get("nw"), out.get("nngb"), out.get("status")
+        _check_dev(rho, h, nw, nngb, status)
+    prm = _with_strides(params, _stride_bytes(x, y, z, m, h_init),
+                        _stride_bytes(rho, h, nw, nngb, status))
     st = torch.zeros(4, dtype=torch.int64, device=dev) if stats else None
-    rc = load().sph_density_solve(C.byref(params), n, G, _ptr(group_offsets), _ptr(x), _ptr(y),
+    rc = load().sph_density_solve(C.byref(prm), n, G, _ptr(group_offsets), _ptr(x), _ptr(y),
                                   _ptr(z), _ptr(m), _ptr(h_init), _ptr(rho), _ptr(h), _ptr(nw),
                                   _ptr(nngb), _ptr(status), _ptr(st), _ptr(ws), ws.numel(),
                                   _stream(dev))
     if rc != OK:
         raise SPHError(rc, "sph_density_solve")
-    out = dict(rho=rho, h=h, nw=nw, nngb=nngb, status=status)
+    res = dict(rho=rho, h=h, nw=nw, nngb=nngb, status=status)
     if stats:
-        out["stats"] = st
-    return out
+        res["stats"] = st
+    return res
 
 
 def density_backward(x, y, z, m, h, grad_rho, grad_h=None, params: Params | None = None,
-                     group_offsets=None, ws=None):
-    """``sph_density_backward``: returns dict(gx, gy, gz, gm)."""
+                     group_offsets=None, ws=None, out=None):
+    """``sph_density_backward``: returns dict(gx, gy, gz, gm).
+
+    Strided inputs and preallocated strided ``out`` (gx, gy, gz, gm) as in
+    ``density_solve``.
+    """
     torch = _torch()
     params = params or default_params()
     dev = _check_dev(x, y, z, m, h, grad_rho, grad_h, group_offsets)
@@ -259,8 +306,14 @@ def density_backward(x, y, z, m, h, grad_rho, grad_h=None, params: Params | None
     if ws is None:
         ws = workspace(params, n, G, dev)
     dt = _io(params)
-    gx, gy, gz, gm = (torch.empty(n, dtype=dt, device=dev) for _ in range(4))
-    rc = load().sph_density_backward(C.byref(params), n, G, _ptr(group_offsets), _ptr(x), _ptr(y),
+    if out is None:
+        gx, gy, gz, gm = (torch.empty(n, dtype=dt, device=dev) for _ in range(4))
+    else:
+        gx, gy, gz, gm = out["gx"], out["gy"], out["gz"], out["gm"]
+        _check_dev(gx, gy, gz, gm)
+    prm = _with_strides(params, _stride_bytes(x, y, z, m, h, grad_rho, grad_h),
+                        _stride_bytes(gx, gy, gz, gm))
+    rc = load().sph_density_backward(C.byref(prm), n, G, _ptr(group_offsets), _ptr(x), _ptr(y),
                                      _ptr(z), _ptr(m), _ptr(h), _ptr(grad_rho), _ptr(grad_h),
                                      _ptr(gx), _ptr(gy), _ptr(gz), _ptr(gm), _ptr(ws),
                                      ws.numel(), _stream(dev))
@@ -283,6 +336,7 @@ def autotune(x, y, z, m, h_init=None, params: Params | None = None, group_offset
     h = torch.empty(max(n, 1), dtype=dt, device=dev)
     best = Params()
     ms = C.c_float(0.0)
+    params = _with_strides(params, _stride_bytes(x, y, z, m, h_init), 0)
     rc = load().sph_autotune(C.byref(params), n, G, _ptr(group_offsets), _ptr(x), _ptr(y),
                              _ptr(z), _ptr(m), _ptr(h_init), _ptr(rho), _ptr(h), _ptr(ws),
                              ws.numel(), _stream(dev), C.byref(best), C.byref(ms))

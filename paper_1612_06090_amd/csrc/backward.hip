@@ -61,6 +61,7 @@ struct AdjArgs {
     int32_t phase;
     int32_t out_f32;
     void *gx, *gy, *gz, *gm;
+    int64_t ost;  // byte stride of the gradient outputs
     int32_t *queue;
 };
 
@@ -591,11 +592,11 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
             // the sums hold c (x_k - x_j)/r: unit vectors, the same in grid units
             if (valid) { g0 = acc0; g1 = acc1; g2 = acc2; g3 = acc3; }
             if (a.out_f32) {
-                st<float>(a.gx, oi, g0); st<float>(a.gy, oi, g1);
-                st<float>(a.gz, oi, g2); st<float>(a.gm, oi, g3);
+                st<float>(a.gx, oi, g0, a.ost); st<float>(a.gy, oi, g1, a.ost);
+                st<float>(a.gz, oi, g2, a.ost); st<float>(a.gm, oi, g3, a.ost);
             } else {
-                st<double>(a.gx, oi, g0); st<double>(a.gy, oi, g1);
-                st<double>(a.gz, oi, g2); st<double>(a.gm, oi, g3);
+                st<double>(a.gx, oi, g0, a.ost); st<double>(a.gy, oi, g1, a.ost);
+                st<double>(a.gz, oi, g2, a.ost); st<double>(a.gm, oi, g3, a.ost);
             }
         }
     }
@@ -604,12 +605,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
 // sorted-order cotangents
 template <typename T>
 __global__ void k_adj_gather(int64_t n, const int32_t *perm, const void *gr, const void *gh,
-                             double *grs, double *ghs) {
+                             int64_t ins, double *grs, double *ghs) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = perm[s];
-    grs[s] = ld<T>(gr, i);
-    ghs[s] = gh ? ld<T>(gh, i) : 0.0;
+    grs[s] = ld<T>(gr, i, ins);
+    ghs[s] = gh ? ld<T>(gh, i, ins) : 0.0;
 }
 
 // level 0 of the range-max table: h in grid units, rounded up to binary32
@@ -644,10 +645,10 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
     double *grs = pl.adj + 3 * n, *ghs = pl.adj + 4 * n;
     if (pl.prm.io_dtype == SPH_F32)
         hipLaunchKernelGGL(k_adj_gather<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm, grad_rho,
-                           grad_h, grs, ghs);
+                           grad_h, pl.in_stride, grs, ghs);
     else
         hipLaunchKernelGGL(k_adj_gather<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm, grad_rho,
-                           grad_h, grs, ghs);
+                           grad_h, pl.in_stride, grs, ghs);
     hipLaunchKernelGGL(k_rmq_base, dim3(nbk), dim3(256), 0, st, n, pl.sh0, pl.skeys, pl.grouped,
                        pl.prm.box, pl.frame, pl.rmq);
     for (int k = 1; k < pl.rmq_levels; ++k)
@@ -678,6 +679,7 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
     a.grs = grs; a.ghs = ghs;
     a.out_f32 = pl.prm.io_dtype == SPH_F32;
     a.gx = gx; a.gy = gy; a.gz = gz; a.gm = gm;
+    a.ost = pl.out_stride;
     a.queue = pl.ctrl;
     const int64_t full = (int64_t)256 * kAdjWavesPerCU;
     const dim3 grid((unsigned)(pl.grouped ? full : (a.n_items < full ? a.n_items : full)));

@@ -63,6 +63,7 @@ struct SolveArgs {
     int32_t out_f32;
     void *rho, *h, *nw;
     int32_t *nngb, *status;
+    int64_t ost, ost_i;  // byte strides of the floating and the int32 outputs
     int32_t *queue;
     uint64_t *stats;
     // exact-K stages: the count stage's h and status, the selected h
@@ -201,16 +202,16 @@ __device__ inline bool h_step(HState &s, double nwv, double dndh, int32_t ncount
 __device__ inline void write_out(const SolveArgs &a, int64_t i, double rho, double h, double nw,
                                  int32_t nngb, int32_t status) {
     if (a.out_f32) {
-        st<float>(a.rho, i, rho);
-        st<float>(a.h, i, h);
-        if (a.nw) st<float>(a.nw, i, nw);
+        st<float>(a.rho, i, rho, a.ost);
+        st<float>(a.h, i, h, a.ost);
+        if (a.nw) st<float>(a.nw, i, nw, a.ost);
     } else {
-        st<double>(a.rho, i, rho);
-        st<double>(a.h, i, h);
-        if (a.nw) st<double>(a.nw, i, nw);
+        st<double>(a.rho, i, rho, a.ost);
+        st<double>(a.h, i, h, a.ost);
+        if (a.nw) st<double>(a.nw, i, nw, a.ost);
     }
-    if (a.nngb) a.nngb[i] = nngb;
-    if (a.status) a.status[i] = status;
+    if (a.nngb) st_i32(a.nngb, i, nngb, a.ost_i);
+    if (a.status) st_i32(a.status, i, status, a.ost_i);
 }
 
 // Smallest level-L cell side 2^e (grid units) with 2^e >= v, e >= 0.
@@ -923,6 +924,8 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     a.out_f32 = pl.prm.io_dtype == SPH_F32;
     a.rho = rho; a.h = h; a.nw = nw;
     a.nngb = nngb; a.status = status;
+    a.ost = pl.out_stride;
+    a.ost_i = pl.out_stride_i;
     a.stats = stats;
     a.knn_h = pl.knn_h;
     // the selection ranks up to dK + 1 (one more where FP32C's widened sphere

@@ -24,13 +24,13 @@ namespace sph {
 
 template <typename T>
 __global__ void k_keys_periodic(int64_t n, const void *x, const void *y, const void *z,
-                                double box, uint64_t *keys, int32_t *vals) {
+                                int64_t ins, double box, uint64_t *keys, int32_t *vals) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double s = 2097152.0 / box;
-    const uint32_t qx = quantise(ld<T>(x, i) * s, 1u << 21);
-    const uint32_t qy = quantise(ld<T>(y, i) * s, 1u << 21);
-    const uint32_t qz = quantise(ld<T>(z, i) * s, 1u << 21);
+    const uint32_t qx = quantise(ld<T>(x, i, ins) * s, 1u << 21);
+    const uint32_t qy = quantise(ld<T>(y, i, ins) * s, 1u << 21);
+    const uint32_t qz = quantise(ld<T>(z, i, ins) * s, 1u << 21);
     keys[i] = morton3(qx, qy, qz);
     vals[i] = (int32_t)i;
 }
@@ -41,13 +41,14 @@ __global__ void k_keys_periodic(int64_t n, const void *x, const void *y, const v
 template <typename T>
 __global__ __launch_bounds__(256) void k_group_frames(int32_t G, const int64_t *goff,
                                                       const void *x, const void *y,
-                                                      const void *z, double *frame) {
+                                                      const void *z, int64_t ins,
+                                                      double *frame) {
     const int g = blockIdx.x;
     if (g >= G) return;
     const int64_t b = goff[g], e = goff[g + 1];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-        const double p[3] = {ld<T>(x, i), ld<T>(y, i), ld<T>(z, i)};
+        const double p[3] = {ld<T>(x, i, ins), ld<T>(y, i, ins), ld<T>(z, i, ins)};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (!isfinite(p[a])) continue;
@@ -99,16 +100,16 @@ __device__ inline int32_t group_of(const int64_t *goff, int32_t G, int64_t i) {
 
 template <typename T>
 __global__ void k_keys_groups(int64_t n, int32_t G, const int64_t *goff, const void *x,
-                              const void *y, const void *z, const double *frame,
+                              const void *y, const void *z, int64_t ins, const double *frame,
                               uint64_t *keys, int32_t *vals) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t g = group_of(goff, G, i);
     const double *f = frame + 8 * (int64_t)g;
     const double sc = f[6];
-    const uint32_t qx = quantise((ld<T>(x, i) - f[0]) * sc, 1u << 16);
-    const uint32_t qy = quantise((ld<T>(y, i) - f[1]) * sc, 1u << 16);
-    const uint32_t qz = quantise((ld<T>(z, i) - f[2]) * sc, 1u << 16);
+    const uint32_t qx = quantise((ld<T>(x, i, ins) - f[0]) * sc, 1u << 16);
+    const uint32_t qy = quantise((ld<T>(y, i, ins) - f[1]) * sc, 1u << 16);
+    const uint32_t qz = quantise((ld<T>(z, i, ins) - f[2]) * sc, 1u << 16);
     keys[i] = ((uint64_t)(uint32_t)g << 48) | morton3(qx, qy, qz);
     vals[i] = (int32_t)i;
 }
@@ -279,21 +280,21 @@ hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const
     if (!pl.grouped) {
         if (f32)
             hipLaunchKernelGGL(k_keys_periodic<float>, dim3(nbk), dim3(256), 0, st, n, x, y, z,
-                               pl.prm.box, pl.keysA, pl.valsA);
+                               pl.in_stride, pl.prm.box, pl.keysA, pl.valsA);
         else
             hipLaunchKernelGGL(k_keys_periodic<double>, dim3(nbk), dim3(256), 0, st, n, x, y, z,
-                               pl.prm.box, pl.keysA, pl.valsA);
+                               pl.in_stride, pl.prm.box, pl.keysA, pl.valsA);
     } else {
         if (f32) {
             hipLaunchKernelGGL(k_group_frames<float>, dim3(pl.G), dim3(256), 0, st, pl.G, goff,
-                               x, y, z, pl.frame);
+                               x, y, z, pl.in_stride, pl.frame);
             hipLaunchKernelGGL(k_keys_groups<float>, dim3(nbk), dim3(256), 0, st, n, pl.G, goff,
-                               x, y, z, pl.frame, pl.keysA, pl.valsA);
+                               x, y, z, pl.in_stride, pl.frame, pl.keysA, pl.valsA);
         } else {
             hipLaunchKernelGGL(k_group_frames<double>, dim3(pl.G), dim3(256), 0, st, pl.G, goff,
-                               x, y, z, pl.frame);
+                               x, y, z, pl.in_stride, pl.frame);
             hipLaunchKernelGGL(k_keys_groups<double>, dim3(nbk), dim3(256), 0, st, n, pl.G,
-                               goff, x, y, z, pl.frame, pl.keysA, pl.valsA);
+                               goff, x, y, z, pl.in_stride, pl.frame, pl.keysA, pl.valsA);
         }
     }
     hipError_t e = hipGetLastError();
@@ -330,14 +331,14 @@ __device__ inline bool valid_input(bool periodic, double box, double x, double y
 template <typename T>
 __global__ void k_permute64(int64_t n, const int32_t *perm, const uint64_t *skeys,
                             const void *x, const void *y, const void *z, const void *m,
-                            const void *h0, bool grouped, double box, const double *frame,
+                            const void *h0, int64_t ins, bool grouped, double box, const double *frame,
                             const int64_t *goff, double *sx, double *sy, double *sz, double *sm,
                             double *sh0) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = perm[s];
-    double xv = ld<T>(x, i), yv = ld<T>(y, i), zv = ld<T>(z, i), mv = ld<T>(m, i);
-    const double hv = h0 ? ld<T>(h0, i) : default_h(grouped, box, n, frame, goff, skeys[s]);
+    double xv = ld<T>(x, i, ins), yv = ld<T>(y, i, ins), zv = ld<T>(z, i, ins), mv = ld<T>(m, i, ins);
+    const double hv = h0 ? ld<T>(h0, i, ins) : default_h(grouped, box, n, frame, goff, skeys[s]);
     if (!valid_input(!grouped, box, xv, yv, zv, mv, hv)) {
         xv = NAN; yv = NAN; zv = NAN;
     }
@@ -349,14 +350,14 @@ __global__ void k_permute64(int64_t n, const int32_t *perm, const uint64_t *skey
 template <typename T>
 __global__ void k_permute32(int64_t n, const int32_t *perm, const uint64_t *skeys,
                             const void *x, const void *y, const void *z, const void *m,
-                            const void *h0, bool grouped, double box, const double *frame,
+                            const void *h0, int64_t ins, bool grouped, double box, const double *frame,
                             const int64_t *goff, int32_t *qx, int32_t *qy, int32_t *qz,
                             float *fx, float *fy, float *fz, float *fm, double *sh0) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = perm[s];
-    const double xv = ld<T>(x, i), yv = ld<T>(y, i), zv = ld<T>(z, i), mv = ld<T>(m, i);
-    const double hv = h0 ? ld<T>(h0, i) : default_h(grouped, box, n, frame, goff, skeys[s]);
+    const double xv = ld<T>(x, i, ins), yv = ld<T>(y, i, ins), zv = ld<T>(z, i, ins), mv = ld<T>(m, i, ins);
+    const double hv = h0 ? ld<T>(h0, i, ins) : default_h(grouped, box, n, frame, goff, skeys[s]);
     double tx, ty, tz;
     uint32_t nmax;
     if (!grouped) {
@@ -386,20 +387,20 @@ hipError_t run_permute(Plan &pl, const int64_t *goff, const void *x, const void 
     if (!fp32c) {
         if (f32)
             hipLaunchKernelGGL(k_permute64<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
-                               pl.skeys, x, y, z, m, h0, pl.grouped, pl.prm.box, pl.frame, goff,
+                               pl.skeys, x, y, z, m, h0, pl.in_stride, pl.grouped, pl.prm.box, pl.frame, goff,
                                pl.sx, pl.sy, pl.sz, pl.sm, pl.sh0);
         else
             hipLaunchKernelGGL(k_permute64<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
-                               pl.skeys, x, y, z, m, h0, pl.grouped, pl.prm.box, pl.frame, goff,
+                               pl.skeys, x, y, z, m, h0, pl.in_stride, pl.grouped, pl.prm.box, pl.frame, goff,
                                pl.sx, pl.sy, pl.sz, pl.sm, pl.sh0);
     } else {
         if (f32)
             hipLaunchKernelGGL(k_permute32<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
-                               pl.skeys, x, y, z, m, h0, pl.grouped, pl.prm.box, pl.frame, goff,
+                               pl.skeys, x, y, z, m, h0, pl.in_stride, pl.grouped, pl.prm.box, pl.frame, goff,
                                pl.qx, pl.qy, pl.qz, pl.fx, pl.fy, pl.fz, pl.fm, pl.sh0);
         else
             hipLaunchKernelGGL(k_permute32<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
-                               pl.skeys, x, y, z, m, h0, pl.grouped, pl.prm.box, pl.frame, goff,
+                               pl.skeys, x, y, z, m, h0, pl.in_stride, pl.grouped, pl.prm.box, pl.frame, goff,
                                pl.qx, pl.qy, pl.qz, pl.fx, pl.fy, pl.fz, pl.fm, pl.sh0);
     }
     return hipGetLastError();

@@ -56,6 +56,10 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
     const int64_t full = (int64_t)256 * p->waves_per_cu;
     pl.grid = (int)(pl.grouped ? full : (pl.n_items < full ? pl.n_items : full));
     if (pl.grid < 1) pl.grid = 1;
+    const int64_t es = p->io_dtype == SPH_F32 ? 4 : 8;
+    pl.in_stride = p->in_stride ? p->in_stride : es;
+    pl.out_stride = p->out_stride ? p->out_stride : es;
+    pl.out_stride_i = p->out_stride ? p->out_stride : 4;
 
     const bool f32c = p->precision == SPH_FP32C;
     const size_t N = (size_t)(n > 0 ? n : 1);
@@ -150,10 +154,20 @@ static int check_params(const sph_params *p, int64_t n, int32_t G, const int64_t
     if (p->segment != 8 && p->segment != 16 && p->segment != 32 && p->segment != 64)
         return SPH_E_INVALID;
     if (p->kernel != SPH_KERNEL_M4 && p->kernel != SPH_KERNEL_WENDLAND_C6) return SPH_E_INVALID;
-    for (int k = 0; k < 7; ++k)
+    // strides: 0 (packed) or a positive multiple of the element size (and of 4 for
+    // the int32 outputs), at most 64 KiB
+    const int es = p->io_dtype == SPH_F32 ? 4 : 8;
+    if (p->in_stride < 0 || p->in_stride > 65536 || p->in_stride % es != 0)
+        return SPH_E_INVALID;
+    if (p->out_stride < 0 || p->out_stride > 65536 || p->out_stride % es != 0)
+        return SPH_E_INVALID;
+    for (int k = 0; k < 5; ++k)
         if (p->reserved[k] != 0) return SPH_E_INVALID;
     return SPH_OK;
 }
+
+// Caller arrays must be aligned to their elements.
+static bool aligned(const void *p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
 
 static int check_ws(const sph_params *p, int64_t n, int32_t G, void *ws, size_t bytes, Plan *pl) {
     if (!ws) return SPH_E_INVALID;
@@ -219,6 +233,10 @@ int sph_sort(const sph_params *params, int64_t n, int32_t n_groups, const int64_
         return SPH_OK;
     }
     if (!x || !y || !z || !keys_out || !perm_out) return SPH_E_INVALID;
+    {
+        const uintptr_t es = params->io_dtype == SPH_F32 ? 4 : 8;
+        if (!aligned(x, es) || !aligned(y, es) || !aligned(z, es)) return SPH_E_INVALID;
+    }
     Plan pl;
     rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
     if (rc != SPH_OK) return rc;
@@ -246,6 +264,13 @@ int sph_density_solve(const sph_params *params, int64_t n, int32_t n_groups,
         return SPH_OK;
     }
     if (!x || !y || !z || !m || !rho_out || !h_out) return SPH_E_INVALID;
+    {
+        const uintptr_t es = params->io_dtype == SPH_F32 ? 4 : 8;
+        if (!aligned(x, es) || !aligned(y, es) || !aligned(z, es) || !aligned(m, es) ||
+            !aligned(h_init, es) || !aligned(rho_out, es) || !aligned(h_out, es) ||
+            !aligned(nw_out, es) || !aligned(nngb_out, 4) || !aligned(status_out, 4))
+            return SPH_E_INVALID;
+    }
     Plan pl;
     rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
     if (rc != SPH_OK) return rc;
@@ -274,6 +299,14 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
     if (n == 0) return SPH_OK;
     if (!x || !y || !z || !m || !h || !grad_rho || !grad_x || !grad_y || !grad_z || !grad_m)
         return SPH_E_INVALID;
+    {
+        const uintptr_t es = params->io_dtype == SPH_F32 ? 4 : 8;
+        if (!aligned(x, es) || !aligned(y, es) || !aligned(z, es) || !aligned(m, es) ||
+            !aligned(h, es) || !aligned(grad_rho, es) || !aligned(grad_h, es) ||
+            !aligned(grad_x, es) || !aligned(grad_y, es) || !aligned(grad_z, es) ||
+            !aligned(grad_m, es))
+            return SPH_E_INVALID;
+    }
     Plan pl;
     rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
     if (rc != SPH_OK) return rc;

@@ -99,6 +99,9 @@ struct Plan {
     int64_t nb_scan_t = 0;    // scan blocks over table_n
     int64_t n_items = 0;      // work items of the density kernel (periodic)
     int grid = 0;             // persistent grid size
+    // byte strides of the caller's per-particle arrays: inputs (x, y, z, m,
+    // h_init, cotangents), floating outputs, int32 outputs
+    int64_t in_stride = 8, out_stride = 8, out_stride_i = 4;
 
     uint64_t *keysA = nullptr, *keysB = nullptr;
     int32_t *valsA = nullptr, *valsB = nullptr;
@@ -181,14 +184,21 @@ __device__ inline uint32_t quantise(double t, uint32_t nmax) {
     return (uint32_t)floor(t);
 }
 
+// Caller arrays: element i of p sits at byte i * stride (the packed stride is
+// the element size; an array of particle structs gives the struct size, with
+// p pointing at the field).
 template <typename T>
-__device__ inline double ld(const void *p, int64_t i) {
-    return (double)static_cast<const T *>(p)[i];
+__device__ inline double ld(const void *p, int64_t i, int64_t stride) {
+    return (double)*reinterpret_cast<const T *>(static_cast<const char *>(p) + i * stride);
 }
 
 template <typename T>
-__device__ inline void st(void *p, int64_t i, double v) {
-    static_cast<T *>(p)[i] = (T)v;
+__device__ inline void st(void *p, int64_t i, double v, int64_t stride) {
+    *reinterpret_cast<T *>(static_cast<char *>(p) + i * stride) = (T)v;
+}
+
+__device__ inline void st_i32(int32_t *p, int64_t i, int32_t v, int64_t stride) {
+    *reinterpret_cast<int32_t *>(reinterpret_cast<char *>(p) + i * stride) = v;
 }
 
 __device__ inline int lane_id() { return __lane_id(); }

@@ -82,6 +82,8 @@ def test_workspace_size_monotone_and_valid():
     ("box", 0.0), ("box", float("nan")), ("n_target", 0.0), ("n_tol", -1.0),
     ("max_iter", -1), ("max_iter", 70000), ("cell_level", 22), ("cell_level", 0),
     ("tile_cell", 3), ("tile_cell", -3), ("kernel", 2), ("kernel", -1), ("waves_per_cu", 0), ("segment", 12), ("segment", 128),
+    ("in_stride", 4), ("in_stride", -8), ("in_stride", 65544), ("in_stride", 12),
+    ("out_stride", 20), ("out_stride", -224), ("out_stride", 1 << 20),
 ])
 def test_invalid_params_rejected(field, value):
     _lib()
@@ -108,6 +110,29 @@ def test_knn_params(k, dk, ok):
         # the count stage keeps its h and status beside the band-mode workspace
         band = sph.workspace_size(sph.default_params(n_target=k, n_tol=dk), 1000)
         assert out.value >= band + 12 * 1000
+
+
+def test_strides_accepted_and_alignment_checked():
+    # strided (array-of-structs) I/O: multiples of the element size up to 64 KiB
+    lib = _lib()
+    out = C.c_size_t(0)
+    for dt, es in ((sph.F64, 8), (sph.F32, 4)):
+        for st in (0, es, 3 * es, 224, 65536):
+            p = sph.default_params(io_dtype=dt, in_stride=st, out_stride=st)
+            assert lib.sph_workspace_size(C.byref(p), 100, 0, C.byref(out)) == sph.OK
+    # misaligned caller pointers are refused before anything is enqueued
+    p = sph.default_params(in_stride=224, out_stride=224)
+    ok, odd = C.c_void_p(0x1000), C.c_void_p(0x1004)
+    ws = C.c_void_p(0x100000)
+    for args in ((odd, ok, ok, ok, ok, ok), (ok, ok, ok, ok, odd, ok), (ok, ok, ok, ok, ok, odd)):
+        x, y, z, m, rho, h = args
+        assert lib.sph_density_solve(C.byref(p), 10, 0, None, x, y, z, m, None, rho, h, None,
+                                     None, None, None, ws, 1 << 30, None) == sph.E_INVALID
+    assert lib.sph_density_solve(C.byref(p), 10, 0, None, ok, ok, ok, ok, None, ok, ok, None,
+                                 C.c_void_p(0x1002), None, None, ws, 1 << 30,
+                                 None) == sph.E_INVALID
+    assert lib.sph_sort(C.byref(p), 10, 0, None, odd, ok, ok, ok, ok, None, None, None, None,
+                        ws, 1 << 30, None) == sph.E_INVALID
 
 
 def test_knn_backward_unsupported():
