@@ -106,6 +106,7 @@ def lib():
                                       P, P, P, P]
         L.oracle_knn.argtypes = [C.POINTER(_Cfg), C.c_int64, P, P, P, P, P, C.c_int32,
                                  P, C.c_int64, P, P, P, P, P]
+        L.oracle_scatter.argtypes = [C.POINTER(_Cfg), C.c_int64, P, P, P, P, P, P, P, P]
         L.oracle_max_threads.restype = C.c_int32
         L.oracle_max_threads.argtypes = []
         _lib = L
@@ -298,6 +299,24 @@ def knn(ps, K, h_init=None, subset=None, search=1, nthreads=0, kernel=M4):
                      None if sub is None else sub.ctypes.data_as(C.c_void_p), cnt, _p(rho),
                      _p(h), _p(nw), _p(nngb), _p(status))
     return dict(rho=rho, h=h, nw=nw, nngb=nngb, status=status)
+
+
+def scatter(ps, h, search=1, nthreads=0, kernel=M4):
+    """Eq. (1) with the neighbour's own h_j: dict(rho_s, rho_sym, nngb_s).
+
+    rho_s_i = sum_j m_j W(r_ij, h_j) over r_ij < h_j (self included);
+    rho_sym_i = (sum_j m_j W(r_ij, h_i) + rho_s_i) / 2; nngb_s_i = number of
+    j whose sphere holds i.
+    """
+    c, _keep = _cfg(ps, search=search, nthreads=nthreads, kernel=kernel)
+    x, y, z, m = _d(ps.x), _d(ps.y), _d(ps.z), _d(ps.m)
+    h = _d(h)
+    n = x.shape[0]
+    rs, rsym = np.empty(n), np.empty(n)
+    cnt = np.empty(n, dtype=np.int64)
+    lib().oracle_scatter(C.byref(c), n, _p(x), _p(y), _p(z), _p(m), _p(h), _p(rs), _p(rsym),
+                         cnt.ctypes.data_as(C.c_void_p))
+    return dict(rho_s=rs, rho_sym=rsym, nngb_s=cnt)
 
 
 def backward(ps, h, grad_rho, grad_h=None, search=1, nthreads=0, x=None, m=None, kernel=M4):

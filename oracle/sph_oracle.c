@@ -861,6 +861,62 @@ void oracle_knn(const orc_cfg *c, int64_t n, const double *x, const double *y,
     ctx_free(&k);
 }
 
+/* ------------------------------------------------ scatter and symmetric form */
+
+/* Eq. (1) as printed: rho_i = sum_j m_j W(r_ij, h_j), every particle j
+ * spreading its mass over its own sphere r < h_j (the particle itself
+ * included, r = 0).  Done the plain way: a serial loop over j that visits
+ * every i inside j's sphere and adds m_j W(r_ij, h_j) to rho_s[i].  The
+ * symmetric form averages it with the gather form at i's own h:
+ * rho_sym_i = (rho_g_i + rho_s_i) / 2, rho_g_i = sum_j m_j W(r_ij, h_i).
+ * Invalid particles get NaN and are nobody's neighbour; nngb_s[i] counts the
+ * j whose sphere holds i. */
+typedef struct { double mj, hj; int32_t kernel; double *rho; int64_t *cnt; } scat_acc;
+
+static void scat_visit(void *u, int64_t i, double r2, const double *d)
+{
+    (void)d;
+    scat_acc *a = (scat_acc *)u;
+    const double hj = a->hj;
+    const double q = sqrt(r2) / hj;
+    a->rho[i] += a->mj * oracle_sigma(a->kernel) / (hj * hj * hj) * oracle_f(a->kernel, q);
+    a->cnt[i] += 1;
+}
+
+void oracle_scatter(const orc_cfg *c, int64_t n, const double *x, const double *y,
+                    const double *z, const double *m, const double *h, double *rho_s,
+                    double *rho_sym, int64_t *nngb_s)
+{
+    ctx_t k;
+    set_threads(c);
+    ctx_init(&k, c, n, x, y, z, m, h);
+    int64_t *cnt = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) rho_s[i] = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        if (!k.valid[j]) continue;
+        scat_acc a = {m[j], h[j], c->kernel, rho_s, cnt};
+        visit(&k, j, h[j], scat_visit, &a);
+    }
+    const double sg = oracle_sigma(c->kernel);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; ++i) {
+        if (!k.valid[i]) {
+            rho_s[i] = NAN;
+            if (rho_sym) rho_sym[i] = NAN;
+            if (nngb_s) nngb_s[i] = 0;
+            continue;
+        }
+        if (rho_sym) {
+            const double hi = h[i];
+            sums_t sg_i = eval_sums(&k, i, hi);
+            rho_sym[i] = 0.5 * (sg * sg_i.R / (hi * hi * hi) + rho_s[i]);
+        }
+        if (nngb_s) nngb_s[i] = cnt[i];
+    }
+    free(cnt);
+    ctx_free(&k);
+}
+
 typedef struct {
     int64_t i;
     double h, gr, lam;

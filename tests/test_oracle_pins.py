@@ -619,3 +619,95 @@ def test_knn_flags_and_order():
     d = oracle.knn(ps, 40, subset=sub)
     for k in ("h", "rho", "nngb", "status"):
         np.testing.assert_array_equal(d[k], a[k][sub])
+
+
+# ------------------------------------------------------------- scatter form
+
+def _w_textbook(kernel, r, h):
+    """W(r, h) written from the kernel definitions (piecewise), vectorised."""
+    q = r / h
+    if kernel == oracle.M4:
+        f = np.where(q < 0.5, 1.0 - 6.0 * q ** 2 + 6.0 * q ** 3,
+                     np.where(q < 1.0, 2.0 * (1.0 - q) ** 3, 0.0))
+        return 8.0 / (math.pi * h ** 3) * f
+    f = np.where(q < 1.0, (1.0 - q) ** 8 * (1.0 + 8.0 * q + 25.0 * q ** 2 + 32.0 * q ** 3), 0.0)
+    return 1365.0 / (64.0 * math.pi * h ** 3) * f
+
+
+def _brute_scatter(ps, h, kernel):
+    """Eq. (1) with h_j by NumPy over all pairs (minimum image when periodic)."""
+    P = np.stack([ps.x, ps.y, ps.z], 1)
+    n = ps.n
+    rho_s = np.zeros(n)
+    dom = np.zeros(n, dtype=np.int64)
+    if ps.offsets is not None:
+        for g in range(len(ps.offsets) - 1):
+            dom[ps.offsets[g]:ps.offsets[g + 1]] = g
+    for i in range(n):
+        d = P - P[i]
+        if ps.periodic:
+            d -= ps.box * np.round(d / ps.box)
+        r = np.sqrt((d ** 2).sum(1))
+        ok = (r < h) & (dom == dom[i])
+        rho_s[i] = (ps.m[ok] * _w_textbook(kernel, r[ok], h[ok])).sum()
+    return rho_s
+
+
+@pytest.mark.parametrize("kernel", [oracle.M4, oracle.WENDLAND_C6])
+@pytest.mark.parametrize("kind", ["periodic", "groups"])
+def test_scatter_brute_force(kernel, kind):
+    # random per-particle h (not a solved set): h_j, not h_i, must pick the pairs
+    rng = np.random.default_rng(95)
+    if kind == "periodic":
+        ps = sphgen.uniform(300, seed=96)
+        h = rng.uniform(0.05, 0.3, ps.n)
+    else:
+        ps = sphgen.groups(5, seed=97, lo=20, hi=120)
+        h = rng.uniform(0.005, 0.1, ps.n)
+    ps.m = rng.uniform(0.5, 2.0, ps.n) / ps.n
+    o = oracle.scatter(ps, h, search=1, kernel=kernel)
+    b = _brute_scatter(ps, h, kernel)
+    np.testing.assert_allclose(o["rho_s"], b, rtol=1e-12, atol=0)
+    o0 = oracle.scatter(ps, h, search=0, kernel=kernel)
+    np.testing.assert_allclose(o0["rho_s"], b, rtol=1e-12, atol=0)
+
+
+def test_scatter_two_particles_closed_form():
+    # h_1 = 0.1 < r = 0.2 < h_2 = 0.3: particle 2's sphere holds particle 1
+    # but not the other way round
+    ps = sphgen.ParticleSet(x=np.array([0.4, 0.6]), y=np.array([0.5, 0.5]),
+                            z=np.array([0.5, 0.5]), m=np.array([1.0, 3.0]),
+                            h_init=np.array([0.1, 0.3]), periodic=True, box=1.0,
+                            n_target=8.0, n_tol=1.0)
+    h = np.array([0.1, 0.3])
+    o = oracle.scatter(ps, h)
+    c = 8.0 / math.pi
+    q = 0.2 / 0.3
+    w12 = c / 0.3 ** 3 * 2.0 * (1.0 - q) ** 3    # W(0.2, h_2), outer spline piece
+    assert o["rho_s"][0] == pytest.approx(1.0 * c / 0.1 ** 3 + 3.0 * w12, rel=1e-14)
+    assert o["rho_s"][1] == pytest.approx(3.0 * c / 0.3 ** 3, rel=1e-14)
+    # the gather form at h_1 sees only particle 1 itself; at h_2 both
+    assert o["rho_sym"][0] == pytest.approx(0.5 * (c / 0.1 ** 3 + o["rho_s"][0]), rel=1e-14)
+    assert o["rho_sym"][1] == pytest.approx(
+        0.5 * (3.0 * c / 0.3 ** 3 + 1.0 * w12 + o["rho_s"][1]), rel=1e-14)
+    assert list(o["nngb_s"]) == [2, 1]
+
+
+def test_scatter_invariants():
+    ps = sphgen.plummer_mixture(3000, 4, seed=98, n_target=32.0, n_tol=1.0)
+    ps.m = np.random.default_rng(99).uniform(0.5, 2.0, ps.n) / ps.n
+    h = oracle.solve(ps)["h"]
+    o = oracle.scatter(ps, h)
+    g = oracle.eval_at_h(ps, h)
+    # sum_i m_i rho_s,i = sum_ij m_i m_j W(r_ij, h_j) = sum_i m_i rho_g,i (swap i, j)
+    a, b = float(np.dot(ps.m, o["rho_s"])), float(np.dot(ps.m, g["rho"]))
+    assert a == pytest.approx(b, rel=1e-12)
+    # the pair relation r_ij < h_j counted from either side
+    assert int(o["nngb_s"].sum()) == int(g["nngb"].sum())
+    np.testing.assert_allclose(o["rho_sym"], 0.5 * (g["rho"] + o["rho_s"]), rtol=1e-14)
+    # one h for all: scatter, gather and symmetric forms coincide
+    hu = np.full(ps.n, float(np.median(h)))
+    u = oracle.scatter(ps, hu)
+    gu = oracle.eval_at_h(ps, hu)
+    np.testing.assert_allclose(u["rho_s"], gu["rho"], rtol=1e-12)
+    np.testing.assert_allclose(u["rho_sym"], gu["rho"], rtol=1e-12)
