@@ -330,6 +330,52 @@ def run_aos(sph, torch, d, ps, steps):
             "overhead": best["aos"] / best["packed"] - 1.0}
 
 
+# scatter form: per in-range pair (r < h_i or r < h_j) one square root, two
+# kernel shapes (q, f: 9 each for M4) and three accumulations
+FLOP_SCAT_PAIR = 24.0
+
+
+def run_scatter(sph, torch, d, ps, steps):
+    """Eq. (1) with each neighbour's own h_j (and the symmetric average) on the
+    clustered 2^20 set at the h of the FP32C solve: sort + walk per call."""
+    p = sph.default_params(periodic=1, box=ps.box, n_target=ps.n_target, n_tol=ps.n_tol,
+                           precision=sph.FP32C)
+    f = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p)
+    h = f["h"]
+    ws = sph.workspace(p, ps.n, 0, d["x"].device)
+    o = sph.density_scatter(d["x"], d["y"], d["z"], d["m"], h, p, ws=ws)
+    torch.cuda.synchronize()
+    pairs_s = int(o["nngb_s"].to(torch.int64).sum().item())
+    pairs_g = int(f["nngb"].to(torch.int64).sum().item())
+    ev = HipEvents()
+    kms = []
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        e0, e1 = ev.create(), ev.create()
+        p.prof_events[0], p.prof_events[1] = e0, e1
+        sph.density_scatter(d["x"], d["y"], d["z"], d["m"], h, p, ws=ws)
+        kms.append((e0, e1))
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    kernel_ms = float(np.mean([ev.elapsed_ms(x, y) for x, y in kms]))
+    for x, y in kms:
+        ev.hip.hipEventDestroy(x)
+        ev.hip.hipEventDestroy(y)
+    # pairs with r < h_i or r < h_j: at most the sum of both counts
+    flop = FLOP_SCAT_PAIR * max(pairs_s, pairs_g)
+    return {"workload": "clustered2^20 at the FP32C solve's h: rho_s = sum_j m_j W(r_ij, h_j), "
+                        "rho_sym, counts; FP32C; sort + walk per call",
+            "ms_per_call": ms, "kernel_ms": kernel_ms,
+            "interactions_per_s": pairs_s / (ms * 1e-3), "pairs_scatter": pairs_s,
+            "pairs_gather": pairs_g,
+            "roofline": {"bound": "alu", "achieved": flop / (kernel_ms * 1e-3) / 1e12,
+                         "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                         "frac": flop / (kernel_ms * 1e-3) / PEAK_FP32,
+                         "kernel": "k_adjoint (scatter phase)", "flop_per_launch": flop}}
+
+
 def cpu_baseline(ps, budget_s=15.0):
     """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
     import oracle
@@ -488,6 +534,7 @@ def main():
     ap.add_argument("--no-wendland", action="store_true")
     ap.add_argument("--no-knn", action="store_true")
     ap.add_argument("--no-aos", action="store_true")
+    ap.add_argument("--no-scatter", action="store_true")
     ap.add_argument("--only-knn", action="store_true",
                     help="only the exact-K leg (for a kernel trace of its stages)")
     ap.add_argument("--profile-run", action="store_true",
@@ -554,6 +601,10 @@ def main():
     if not args.no_wendland:
         wc6 = run_wendland(sph, torch, d, ps, max(3, args.steps // 2))
         print(f"[bench] wendland {wc6}", file=sys.stderr, flush=True)
+    scat = None
+    if not args.no_scatter:
+        scat = run_scatter(sph, torch, d, ps, max(3, args.steps // 2))
+        print(f"[bench] scatter {scat}", file=sys.stderr, flush=True)
     aos = None
     if not args.no_aos:
         aos = run_aos(sph, torch, d, ps, max(3, args.steps // 2))
@@ -621,6 +672,8 @@ def main():
         line["exact_k"] = knn
     if aos is not None:
         line["aos"] = aos
+    if scat is not None:
+        line["scatter"] = scat
     if adj is not None:
         line["adjoint"] = adj
     if not args.no_cpu_baseline:

@@ -238,6 +238,24 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
                          void *grad_x, void *grad_y, void *grad_z, void *grad_m,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* Scatter form of the density, Eq. (1) as printed (each neighbour j with its
+ * own smoothing length h_j), at given h (e.g. sph_density_solve's h_out):
+ *   rho_s_out[i]   = sum_{j: r_ij < h_j} m_j W(r_ij, h_j)     (i included)
+ *   rho_sym_out[i] = (sum_{j: r_ij < h_i} m_j W(r_ij, h_i) + rho_s_out[i]) / 2
+ *   nngb_s_out[i]  = number of j with r_ij < h_j (int32)
+ * with the minimum image when periodic and the same group when isolated.
+ * rho_sym_out and nngb_s_out may be NULL.  Particles with invalid inputs
+ * (non-finite x/y/z/m/h, h <= 0, periodic coordinates outside [0, L)) get NaN
+ * and 0 and are nobody's neighbour.  The mode and the h-iteration fields of
+ * params are not used.  Computed in gather form over each particle's
+ * reverse neighbours (no atomics; bitwise reproducible); outputs in caller
+ * order, io_dtype, overwritten. */
+int sph_density_scatter(const sph_params *params, int64_t n, int32_t n_groups,
+                        const int64_t *group_offsets,
+                        const void *x, const void *y, const void *z, const void *m,
+                        const void *h, void *rho_s_out, void *rho_sym_out,
+                        int32_t *nngb_s_out, void *ws, size_t ws_bytes, void *stream);
+
 /* Launch-parameter autotuner of sph_density_solve (the batched persistent form
  * whose per-item work is uneven and unknown in advance: the dynamic scheduling
  * of Sec. IV-A).  Times sph_density_solve on the given input for every

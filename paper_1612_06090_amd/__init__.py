@@ -17,7 +17,8 @@ import os
 
 __all__ = [
     "LIB_PATH", "Params", "SPHError", "load", "default_params", "workspace_size", "sort",
-    "density_solve", "density_backward", "autotune", "density", "SPHDensity", "status_string",
+    "density_solve", "density_backward", "density_scatter", "autotune", "density", "SPHDensity",
+    "status_string",
     "FP64", "FP32C", "F64", "F32", "BAND", "ROOT", "KNN", "KERNEL_M4", "KERNEL_WENDLAND_C6",
     "ST_NOCONV", "ST_HTOOLARGE", "ST_BADINPUT", "ST_UNREACHABLE",
 ]
@@ -37,7 +38,8 @@ KERNEL_M4, KERNEL_WENDLAND_C6 = 0, 1
 
 EXPORTS = [
     "sph_default_params", "sph_workspace_size", "sph_sort", "sph_density_solve",
-    "sph_density_backward", "sph_autotune", "sph_status_string", "sph_last_hip_error",
+    "sph_density_backward", "sph_density_scatter", "sph_autotune", "sph_status_string",
+    "sph_last_hip_error",
     "sph_last_hip_error_string",
 ]
 
@@ -103,6 +105,8 @@ def load():
     L.sph_density_solve.restype = C.c_int
     L.sph_density_backward.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P]
     L.sph_density_backward.restype = C.c_int
+    L.sph_density_scatter.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, P, SZ, P]
+    L.sph_density_scatter.restype = C.c_int
     L.sph_autotune.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, SZ, P, PP,
                                C.POINTER(C.c_float)]
     L.sph_autotune.restype = C.c_int
@@ -320,6 +324,38 @@ def density_backward(x, y, z, m, h, grad_rho, grad_h=None, params: Params | None
     if rc != OK:
         raise SPHError(rc, "sph_density_backward")
     return dict(gx=gx, gy=gy, gz=gz, gm=gm)
+
+
+def density_scatter(x, y, z, m, h, params: Params | None = None, group_offsets=None, ws=None,
+                    out=None):
+    """``sph_density_scatter``: Eq. (1) with each neighbour's own h_j.
+
+    Returns dict(rho_s, rho_sym, nngb_s); strided inputs and preallocated
+    strided ``out`` (rho_s required, rho_sym and nngb_s optional) as in
+    ``density_solve``.
+    """
+    torch = _torch()
+    params = params or default_params()
+    dev = _check_dev(x, y, z, m, h, group_offsets)
+    n = x.shape[0]
+    G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    if ws is None:
+        ws = workspace(params, n, G, dev)
+    dt = _io(params)
+    if out is None:
+        rs = torch.empty(n, dtype=dt, device=dev)
+        rsym = torch.empty(n, dtype=dt, device=dev)
+        cnt = torch.empty(n, dtype=torch.int32, device=dev)
+    else:
+        rs, rsym, cnt = out["rho_s"], out.get("rho_sym"), out.get("nngb_s")
+        _check_dev(rs, rsym, cnt)
+    prm = _with_strides(params, _stride_bytes(x, y, z, m, h), _stride_bytes(rs, rsym, cnt))
+    rc = load().sph_density_scatter(C.byref(prm), n, G, _ptr(group_offsets), _ptr(x), _ptr(y),
+                                    _ptr(z), _ptr(m), _ptr(h), _ptr(rs), _ptr(rsym), _ptr(cnt),
+                                    _ptr(ws), ws.numel(), _stream(dev))
+    if rc != OK:
+        raise SPHError(rc, "sph_density_scatter")
+    return dict(rho_s=rs, rho_sym=rsym, nngb_s=cnt)
 
 
 def autotune(x, y, z, m, h_init=None, params: Params | None = None, group_offsets=None, ws=None):

@@ -61,7 +61,7 @@ struct AdjArgs {
     int32_t phase;
     int32_t out_f32;
     void *gx, *gy, *gz, *gm;
-    int64_t ost;  // byte stride of the gradient outputs
+    int64_t ost, ost_i;  // byte strides of the floating and int32 outputs
     int32_t *queue;
 };
 
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
         const int64_t gbase = GROUPED ? a.goff[g] : 0;
         const int64_t gend = GROUPED ? a.goff[g + 1] : a.n;
         float hall = 0.f;  // largest h of the set (phase 2: any sphere may reach)
-        if (a.phase == 2 && vm != 0)
+        if (a.phase >= 2 && vm != 0)
             hall = uniform_f(range_hmax(a, (int32_t)gbase, (int32_t)gend));
 
         // Particle ranges of the tile, each walked on its own.  A range whose
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
 
             int wsz = 0;   // work stack size (uniform)
             int nl = 0;    // leaves collected (uniform)
-            float Rroot = a.phase == 2 && hall > Ht ? hall : Ht;
+            float Rroot = a.phase >= 2 && hall > Ht ? hall : Ht;
             Rroot = Rroot * (1.0f + 0x1p-12f) + 1.0f;
 
             // one candidate of the leaf list (flat index gidx) into registers
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                     const double hj = a.sh[j];
                     const double aj = a.phase == 2 ? a.alpha[j] : 0.0;
                     const double bj = a.phase == 2 ? a.beta[j] : 0.0;
-                    const double gj = a.phase == 2 ? a.gamma[j] : 0.0;
+                    const double gj = a.phase >= 2 ? a.gamma[j] : 0.0;
                     if constexpr (PREC == SPH_FP64) {
                         c.p = make_double4(a.sx[j], a.sy[j], a.sz[j], a.sm[j]);
                         c.s = make_double4((double)sh0 * a.box, (double)sh1 * a.box,
@@ -302,6 +302,18 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                                 acc1 += c.p.w * f;
                                 acc2 += c.p.w * q * fp;
                             }
+                        } else if (a.phase == 3) {
+                            // scatter form: gather sum at h_k, spread sum at h_j
+                            const bool in2 = r2 < c.h.x * c.h.x;
+                            if (in1 || in2) {
+                                const double r = sqrt(r2);
+                                double f1, fp1, f2, fp2;
+                                KT::template fd<double>(fmin(r * hkinv, 1.0), f1, fp1);
+                                KT::template fd<double>(fmin(r * c.h.y, 1.0), f2, fp2);
+                                acc0 += in1 ? c.p.w * f1 : 0.0;
+                                acc1 += in2 ? c.g * f2 : 0.0;
+                                acc2 += in2 ? 1.0 : 0.0;
+                            }
                         } else {
                             const bool in2 = r2 < c.h.x * c.h.x;
                             if (in1 || in2) {
@@ -338,6 +350,17 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                                 s0 += qfp;
                                 s1 = __builtin_fmaf(c.p.w, f, s1);
                                 s2 = __builtin_fmaf(c.p.w, qfp, s2);
+                            }
+                        } else if (a.phase == 3) {
+                            const bool in2 = r2 < c.h.x * c.h.x;
+                            if (in1 || in2) {
+                                const float r = __builtin_amdgcn_sqrtf(r2);
+                                float f1, fp1, f2, fp2;
+                                KT::template fd<float>(fminf(r * hkinvf, 1.0f), f1, fp1);
+                                KT::template fd<float>(fminf(r * c.h.y, 1.0f), f2, fp2);
+                                s0 = __builtin_fmaf(in1 ? c.p.w : 0.f, f1, s0);
+                                s1 = __builtin_fmaf(in2 ? c.g : 0.f, f2, s1);
+                                s2 += in2 ? 1.f : 0.f;
                             }
                         } else {
                             const bool in2 = r2 < c.h.x * c.h.x;
@@ -394,7 +417,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 const float side = (float)sd;
                 const float lo0 = (float)(c0 * sd - t0), lo1 = (float)(c1 * sd - t1),
                             lo2 = (float)(c2 * sd - t2);
-                const float hm = a.phase == 2 ? range_hmax(a, st, en) : 0.f;
+                const float hm = a.phase >= 2 ? range_hmax(a, st, en) : 0.f;
                 // slack covers the binary32 rounding of tile coordinates (up to
                 // 2^-3 grid units at 2^21) and of the node corners
                 const float slack = side * 0x1p-12f + 1.0f;
@@ -586,6 +609,26 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 a.beta[s] = be;
                 a.gamma[s] = ga;
             }
+        } else if (a.phase == 3) {
+            if (mine && kk == 0) {
+                // gx: rho_s, gy: rho_sym (optional), gz: int32 count (optional)
+                const int64_t oi = a.perm[s];
+                double rs = NAN, rsym = NAN;
+                int32_t cnt = 0;
+                if (valid) {
+                    rs = acc1;
+                    rsym = 0.5 * (KT::sigma * acc0 / (hk * hk * hk) + acc1);
+                    cnt = (int32_t)acc2;
+                }
+                if (a.out_f32) {
+                    st<float>(a.gx, oi, rs, a.ost);
+                    if (a.gy) st<float>(a.gy, oi, rsym, a.ost);
+                } else {
+                    st<double>(a.gx, oi, rs, a.ost);
+                    if (a.gy) st<double>(a.gy, oi, rsym, a.ost);
+                }
+                if (a.gz) st_i32(static_cast<int32_t *>(a.gz), oi, cnt, a.ost_i);
+            }
         } else if (mine && kk == 0) {
             const int64_t oi = a.perm[s];
             double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
@@ -635,28 +678,19 @@ __global__ void k_rmq_level(int64_t n, int k, float *t) {
     t[(int64_t)k * n + s] = u > v ? u : v;
 }
 
-hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void *grad_rho,
-                        const void *grad_h, void *gx, void *gy, void *gz, void *gm,
-                        hipStream_t st) {
-    (void)h;
+// the range-max table of h over the sorted order (all levels)
+static hipError_t build_rmq(Plan &pl, hipStream_t st) {
     const int64_t n = pl.n;
     const unsigned nbk = (unsigned)ceil_div(n, 256);
-    double *alpha = pl.adj, *beta = pl.adj + n, *gamma = pl.adj + 2 * n;
-    double *grs = pl.adj + 3 * n, *ghs = pl.adj + 4 * n;
-    if (pl.prm.io_dtype == SPH_F32)
-        hipLaunchKernelGGL(k_adj_gather<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm, grad_rho,
-                           grad_h, pl.in_stride, grs, ghs);
-    else
-        hipLaunchKernelGGL(k_adj_gather<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm, grad_rho,
-                           grad_h, pl.in_stride, grs, ghs);
     hipLaunchKernelGGL(k_rmq_base, dim3(nbk), dim3(256), 0, st, n, pl.sh0, pl.skeys, pl.grouped,
                        pl.prm.box, pl.frame, pl.rmq);
     for (int k = 1; k < pl.rmq_levels; ++k)
         hipLaunchKernelGGL(k_rmq_level, dim3(nbk), dim3(256), 0, st, n, k, pl.rmq);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
 
-    AdjArgs a;
+static void adj_args(const Plan &pl, const int64_t *goff, AdjArgs &a) {
+    const int64_t n = pl.n;
     a.n = n;
     a.G = pl.G;
     a.goff = goff;
@@ -675,24 +709,22 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
     a.rmq_levels = pl.rmq_levels;
     a.box = pl.prm.box;
     a.bits = pl.bits;
-    a.alpha = alpha; a.beta = beta; a.gamma = gamma;
-    a.grs = grs; a.ghs = ghs;
+    a.alpha = pl.adj; a.beta = pl.adj + n; a.gamma = pl.adj + 2 * n;
+    a.grs = pl.adj + 3 * n; a.ghs = pl.adj + 4 * n;
     a.out_f32 = pl.prm.io_dtype == SPH_F32;
-    a.gx = gx; a.gy = gy; a.gz = gz; a.gm = gm;
     a.ost = pl.out_stride;
+    a.ost_i = pl.out_stride_i;
     a.queue = pl.ctrl;
+}
+
+// one launch of the walk kernel for phase a.phase
+static hipError_t launch_adjoint(const Plan &pl, AdjArgs &a, hipStream_t st) {
+    hipError_t e = run_zero_i32(pl.ctrl, 4, st);
+    if (e != hipSuccess) return e;
     const int64_t full = (int64_t)256 * kAdjWavesPerCU;
     const dim3 grid((unsigned)(pl.grouped ? full : (a.n_items < full ? a.n_items : full)));
     const bool f32c = pl.prm.precision == SPH_FP32C;
     const bool wc6 = pl.prm.kernel == SPH_KERNEL_WENDLAND_C6;
-    if (pl.prm.prof_events[0]) {
-        e = hipEventRecord((hipEvent_t)pl.prm.prof_events[0], st);
-        if (e != hipSuccess) return e;
-    }
-    for (int phase = 1; phase <= 2; ++phase) {
-        a.phase = phase;
-        e = run_zero_i32(pl.ctrl, 4, st);
-        if (e != hipSuccess) return e;
 #define SPH_ADJ(PR, GR)                                                                       \
     do {                                                                                      \
         if (wc6)                                                                              \
@@ -701,17 +733,89 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
         else                                                                                  \
             hipLaunchKernelGGL((k_adjoint<PR, GR, SPH_KERNEL_M4>), grid, dim3(64), 0, st, a); \
     } while (0)
-        if (!pl.grouped) {
-            if (f32c) SPH_ADJ(SPH_FP32C, false);
-            else SPH_ADJ(SPH_FP64, false);
-        } else {
-            if (f32c) SPH_ADJ(SPH_FP32C, true);
-            else SPH_ADJ(SPH_FP64, true);
-        }
+    if (!pl.grouped) {
+        if (f32c) SPH_ADJ(SPH_FP32C, false);
+        else SPH_ADJ(SPH_FP64, false);
+    } else {
+        if (f32c) SPH_ADJ(SPH_FP32C, true);
+        else SPH_ADJ(SPH_FP64, true);
+    }
 #undef SPH_ADJ
-        e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void *grad_rho,
+                        const void *grad_h, void *gx, void *gy, void *gz, void *gm,
+                        hipStream_t st) {
+    (void)h;
+    const int64_t n = pl.n;
+    const unsigned nbk = (unsigned)ceil_div(n, 256);
+    double *grs = pl.adj + 3 * n, *ghs = pl.adj + 4 * n;
+    if (pl.prm.io_dtype == SPH_F32)
+        hipLaunchKernelGGL(k_adj_gather<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm, grad_rho,
+                           grad_h, pl.in_stride, grs, ghs);
+    else
+        hipLaunchKernelGGL(k_adj_gather<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm, grad_rho,
+                           grad_h, pl.in_stride, grs, ghs);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = build_rmq(pl, st);
+    if (e != hipSuccess) return e;
+    AdjArgs a;
+    adj_args(pl, goff, a);
+    a.gx = gx; a.gy = gy; a.gz = gz; a.gm = gm;
+    if (pl.prm.prof_events[0]) {
+        e = hipEventRecord((hipEvent_t)pl.prm.prof_events[0], st);
         if (e != hipSuccess) return e;
     }
+    for (int phase = 1; phase <= 2 && e == hipSuccess; ++phase) {
+        a.phase = phase;
+        e = launch_adjoint(pl, a, st);
+    }
+    if (e != hipSuccess) return e;
+    if (pl.prm.prof_events[1]) e = hipEventRecord((hipEvent_t)pl.prm.prof_events[1], st);
+    return e;
+}
+
+// gamma_j = m_j sigma / h_j^3 (sorted order; 0 for invalid particles), from the
+// masses the walk itself uses (binary32 in FP32C)
+template <int KERNEL>
+__global__ void k_scatter_coef(int64_t n, const double *sm, const float *fm, const double *sh,
+                               const double *sx, const float *fx, double *gamma) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const double h = sh[s];
+    const bool valid = sm ? !isnan(sx[s]) : !isnan(fx[s]);
+    const double m = sm ? sm[s] : (double)fm[s];
+    gamma[s] = valid ? m * Kern<KERNEL>::sigma / (h * h * h) : 0.0;
+}
+
+hipError_t run_scatter(Plan &pl, const int64_t *goff, void *rho_s, void *rho_sym,
+                       int32_t *nngb_s, hipStream_t st) {
+    const int64_t n = pl.n;
+    const unsigned nbk = (unsigned)ceil_div(n, 256);
+    const bool f32c = pl.prm.precision == SPH_FP32C;
+    double *gamma = pl.adj + 2 * n;
+    const double *sm = f32c ? nullptr : pl.sm;
+    const float *fm = f32c ? pl.fm : nullptr;
+    if (pl.prm.kernel == SPH_KERNEL_WENDLAND_C6)
+        hipLaunchKernelGGL(k_scatter_coef<SPH_KERNEL_WENDLAND_C6>, dim3(nbk), dim3(256), 0, st,
+                           n, sm, fm, pl.sh0, pl.sx, pl.fx, gamma);
+    else
+        hipLaunchKernelGGL(k_scatter_coef<SPH_KERNEL_M4>, dim3(nbk), dim3(256), 0, st, n, sm, fm,
+                           pl.sh0, pl.sx, pl.fx, gamma);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = build_rmq(pl, st);
+    if (e != hipSuccess) return e;
+    AdjArgs a;
+    adj_args(pl, goff, a);
+    a.gx = rho_s; a.gy = rho_sym; a.gz = nngb_s; a.gm = nullptr;
+    a.phase = 3;
+    if (pl.prm.prof_events[0]) {
+        e = hipEventRecord((hipEvent_t)pl.prm.prof_events[0], st);
+        if (e != hipSuccess) return e;
+    }
+    e = launch_adjoint(pl, a, st);
+    if (e != hipSuccess) return e;
     if (pl.prm.prof_events[1]) e = hipEventRecord((hipEvent_t)pl.prm.prof_events[1], st);
     return e;
 }

@@ -159,6 +159,8 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
 hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void *grad_rho,
                         const void *grad_h, void *gx, void *gy, void *gz, void *gm,
                         hipStream_t st);
+hipError_t run_scatter(Plan &pl, const int64_t *goff, void *rho_s, void *rho_sym,
+                       int32_t *nngb_s, hipStream_t st);
 
 // ---------------------------------------------------------------- helpers
 

@@ -1,0 +1,167 @@
+"""Scatter form of Eq. (1) (each neighbour with its own h_j) and the symmetric
+average, on the GPU against the oracle.
+
+FP64: rho_s and rho_sym within 1e-12 of the oracle (summation order differs),
+the count of spheres holding each particle exact.  FP32C: binary32 pair terms
+and masses folded into binary64 per chunk; coordinates are binary32 offsets
+from the walk range's origin, rounded to 2^-24 of up to ~6 times the range's
+largest h, so q = r/h_j carries an error of ~2^-20 H/h_j.  With solved h
+(smooth across neighbours) that gives 1e-5 relative (measured ~2e-6); with h
+drawn at random over a factor 50 the smallest spheres see errors 50 times
+larger, so those cases ask 1e-4 (measured 1.4e-5).  Counts equal up to
+particles at a sphere's edge (|r - h_j| within that rounding), allowed for at
+most 1 in 10^4 particles.  Invariant at
+any size: sum_i m_i rho_s,i = sum_i m_i rho_g,i (the pair sum with i and j
+swapped), against the density solve's own rho at the same h.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1612_06090_amd as sph
+import sphgen
+from gpu_util import dev_arrays, gpu_solve, params_for, rel, say
+
+pytestmark = pytest.mark.gpu
+
+
+def _scatter(ps, h, io="float64", **kw):
+    import torch
+    p = params_for(ps, io_dtype=sph.F32 if io == "float32" else sph.F64, **kw)
+    d = dev_arrays(ps, io)
+    ht = torch.tensor(np.asarray(h), dtype=d["x"].dtype, device="cuda")
+    o = sph.density_scatter(d["x"], d["y"], d["z"], d["m"], ht, p, d["goff"])
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in o.items()}
+
+
+def _case(name):
+    rng = np.random.default_rng(70)
+    if name == "uniform4096_solved":
+        ps = sphgen.config("uniform4096")
+        return ps, oracle.solve(ps)["h"], oracle.M4
+    if name == "uniform3000_random_h":
+        ps = sphgen.uniform(3000, seed=71)
+        ps.m = rng.uniform(0.5, 2.0, ps.n) / ps.n
+        return ps, rng.uniform(0.05, 0.2, ps.n), oracle.M4
+    if name == "clustered32k_solved":
+        ps = sphgen.plummer_mixture(1 << 15, 20, seed=72)
+        return ps, gpu_solve(ps)["h"], oracle.M4
+    if name == "groups60_random_h":
+        ps = sphgen.groups(60, seed=73, lo=10, hi=3000)
+        return ps, rng.uniform(0.001, 0.05, ps.n), oracle.M4
+    if name == "clustered32k_wc6":
+        ps = sphgen.plummer_mixture(1 << 15, 20, seed=74, n_target=295.0)
+        return ps, gpu_solve(ps, kernel=sph.KERNEL_WENDLAND_C6)["h"], oracle.WENDLAND_C6
+    raise KeyError(name)
+
+
+NAMES = ["uniform4096_solved", "uniform3000_random_h", "clustered32k_solved",
+         "groups60_random_h", "clustered32k_wc6"]
+
+
+def _kern(k):
+    return sph.KERNEL_WENDLAND_C6 if k == oracle.WENDLAND_C6 else sph.KERNEL_M4
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_scatter_fp64(name):
+    ps, h, kern = _case(name)
+    say(f"[scatter fp64] {name} n={ps.n}")
+    g = _scatter(ps, h, kernel=_kern(kern))
+    o = oracle.scatter(ps, h, kernel=kern)
+    assert rel(g["rho_s"], o["rho_s"]).max() < 1e-12
+    assert rel(g["rho_sym"], o["rho_sym"]).max() < 1e-12
+    assert np.array_equal(g["nngb_s"], o["nngb_s"].astype(np.int32))
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_scatter_fp32c(name):
+    ps, h, kern = _case(name)
+    g = _scatter(ps, h, precision=sph.FP32C, kernel=_kern(kern))
+    o = oracle.scatter(ps, h, kernel=kern)
+    d1, d2 = rel(g["rho_s"], o["rho_s"]).max(), rel(g["rho_sym"], o["rho_sym"]).max()
+    flips = int((g["nngb_s"] != o["nngb_s"]).sum())
+    say(f"  fp32c max rel rho_s {d1:.2e} rho_sym {d2:.2e} count flips {flips}")
+    tol = 1e-4 if name.endswith("random_h") else 1e-5
+    assert d1 <= tol and d2 <= tol
+    assert flips <= max(1, ps.n // 10000)
+
+
+def test_scatter_invariant_and_uniform_h():
+    import torch
+    ps = sphgen.plummer_mixture(1 << 14, 10, seed=75)
+    ps.m = np.random.default_rng(76).uniform(0.5, 2.0, ps.n) / ps.n
+    f = gpu_solve(ps)
+    g = _scatter(ps, f["h"])
+    a, b = float(np.dot(ps.m, g["rho_s"])), float(np.dot(ps.m, f["rho"]))
+    assert a == pytest.approx(b, rel=1e-12)
+    assert int(g["nngb_s"].astype(np.int64).sum()) == int(f["nngb"].astype(np.int64).sum())
+    # one h for all: the scatter, gather and symmetric forms coincide
+    hu = np.full(ps.n, float(np.median(f["h"])))
+    u = _scatter(ps, hu)
+    e = oracle.eval_at_h(ps, hu)
+    assert rel(u["rho_s"], e["rho"]).max() < 1e-12
+    assert rel(u["rho_sym"], e["rho"]).max() < 1e-12
+
+
+def test_scatter_bad_input_f32_io_and_empty():
+    import torch
+    rng = np.random.default_rng(77)
+    ps = sphgen.uniform(2000, seed=78)
+    h = rng.uniform(0.05, 0.2, ps.n)
+    ps.x[3] = np.nan
+    h[8] = 0.0
+    g = _scatter(ps, h)
+    o = oracle.scatter(ps, h)
+    assert np.isnan(g["rho_s"][3]) and np.isnan(g["rho_s"][8]) and g["nngb_s"][8] == 0
+    ok = np.isfinite(o["rho_s"])
+    assert np.array_equal(np.isfinite(g["rho_s"]), ok)
+    assert rel(g["rho_s"][ok], o["rho_s"][ok]).max() < 1e-12
+    # binary32 io: the oracle takes the same rounded inputs
+    q = sphgen.uniform(2000, seed=79)
+    for k in ("x", "y", "z", "m"):
+        setattr(q, k, np.asarray(getattr(q, k), dtype=np.float32).astype(np.float64))
+    hq = np.asarray(h, dtype=np.float32).astype(np.float64)
+    g32 = _scatter(q, hq, io="float32")
+    o32 = oracle.scatter(q, hq)
+    ok32 = np.isfinite(o32["rho_s"])   # particle 8 keeps h = 0: invalid
+    assert np.array_equal(np.isfinite(g32["rho_s"]), ok32) and not ok32[8]
+    assert rel(g32["rho_s"][ok32].astype(np.float64), o32["rho_s"][ok32]).max() <= 2.0 ** -23
+    z = torch.empty(0, dtype=torch.float64, device="cuda")
+    e = sph.density_scatter(z, z, z, z, z)
+    torch.cuda.synchronize()
+    assert e["rho_s"].numel() == 0
+
+
+def test_scatter_aos_bit_identical():
+    import torch
+    ps, h, kern = _case("clustered32k_solved")
+    p = params_for(ps)
+    d = dev_arrays(ps)
+    ht = torch.tensor(h, dtype=torch.float64, device="cuda")
+    a = sph.density_scatter(d["x"], d["y"], d["z"], d["m"], ht, p)
+    S = torch.full((ps.n, 28), 7.25, dtype=torch.float64, device="cuda")
+    S[:, 0], S[:, 1], S[:, 2], S[:, 6], S[:, 10] = d["x"], d["y"], d["z"], d["m"], ht
+    iv = S.view(torch.int32)
+    out = dict(rho_s=S[:, 18], rho_sym=S[:, 19], nngb_s=iv[:, 40])
+    sph.density_scatter(S[:, 0], S[:, 1], S[:, 2], S[:, 6], S[:, 10], p, out=out)
+    torch.cuda.synchronize()
+    assert torch.equal(out["rho_s"], a["rho_s"]) and torch.equal(out["rho_sym"], a["rho_sym"])
+    assert torch.equal(out["nngb_s"], a["nngb_s"])
+    keep = [c for c in range(28) if c not in (0, 1, 2, 6, 10, 18, 19, 20)]
+    assert bool((S[:, keep] == 7.25).all())
+
+
+def test_scatter_clustered2p20_fp32c():
+    # the benchmarked set at full size, h from the FP32C solve; the oracle over
+    # the whole set
+    ps = sphgen.config("clustered2^20")
+    say(f"[scatter fp32c] clustered2^20 n={ps.n}")
+    h = gpu_solve(ps, precision=sph.FP32C)["h"]
+    g = _scatter(ps, h, precision=sph.FP32C)
+    o = oracle.scatter(ps, h)
+    d1, d2 = rel(g["rho_s"], o["rho_s"]).max(), rel(g["rho_sym"], o["rho_sym"]).max()
+    flips = int((g["nngb_s"] != o["nngb_s"]).sum())
+    say(f"  max rel rho_s {d1:.2e} rho_sym {d2:.2e} count flips {flips}")
+    assert d1 <= 1e-5 and d2 <= 1e-5 and flips <= ps.n // 10000
