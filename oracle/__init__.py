@@ -338,3 +338,15 @@ def backward(ps, h, grad_rho, grad_h=None, search=1, nthreads=0, x=None, m=None,
     lib().oracle_backward(C.byref(c), n, _p(px), _p(py), _p(pz), _p(mm), _p(h), _p(gr), _p(gh),
                           _p(gx), _p(gy), _p(gz), _p(gm))
     return dict(gx=gx, gy=gy, gz=gz, gm=gm)
+
+
+def pressure_force(ps, h, rho, P, search=1, nthreads=0, kernel=M4):
+    """Pressure acceleration of the variational (grad-h) SPH equations with each
+    h held on its count constraint: a_k = -(1/m_k) dE/dx_k for the thermal
+    energy E = sum_i m_i u_i(rho_i) with du_i/drho_i = P_i/rho_i^2, which is
+    the adjoint of the density with cotangent m_i P_i/rho_i^2 (implicit h
+    included).  dict(ax, ay, az)."""
+    m = _d(ps.m)
+    gr = m * _d(P) / _d(rho) ** 2
+    g = backward(ps, h, gr, None, search=search, nthreads=nthreads, kernel=kernel)
+    return dict(ax=-g["gx"] / m, ay=-g["gy"] / m, az=-g["gz"] / m)

@@ -711,3 +711,81 @@ def test_scatter_invariants():
     gu = oracle.eval_at_h(ps, hu)
     np.testing.assert_allclose(u["rho_s"], gu["rho"], rtol=1e-12)
     np.testing.assert_allclose(u["rho_sym"], gu["rho"], rtol=1e-12)
+
+
+# ----------------------------------------------------- pressure force (grad-h)
+
+def _energy(ps, A, gamma, pos=None, kernel=oracle.M4):
+    """E = sum_i m_i A_i rho_i^(gamma-1)/(gamma-1) at the converged h (root mode)."""
+    q = ps
+    if pos is not None:
+        q = sphgen.ParticleSet(x=pos[:, 0], y=pos[:, 1], z=pos[:, 2], m=ps.m,
+                               h_init=ps.h_init, periodic=ps.periodic, box=ps.box,
+                               n_target=ps.n_target, n_tol=ps.n_tol, offsets=ps.offsets)
+    s = oracle.solve(q, mode=oracle.ROOT, root_tol=1e-15, search=0, max_iter=200,
+                     kernel=kernel)
+    assert np.all((s["status"] >> 16) == 0)
+    return float(np.sum(ps.m * A * s["rho"] ** (gamma - 1.0)) / (gamma - 1.0)), s
+
+
+@pytest.mark.parametrize("periodic", [True, False])
+def test_force_is_minus_energy_gradient(periodic):
+    # polytropic gas P = A rho^gamma: m_k a_k = -dE/dx_k, by central differences
+    rng = np.random.default_rng(41)
+    n, gamma = 90, 5.0 / 3.0
+    if periodic:
+        ps = sphgen.uniform(n, seed=42, n_target=16.0, n_tol=1.0)
+    else:
+        ps = sphgen.groups(1, seed=43, sizes=np.array([n]), n_target=16.0, n_tol=1.0)
+    ps.m = rng.uniform(0.5, 1.5, n)
+    A = rng.uniform(0.5, 2.0, n)
+    E0, s0 = _energy(ps, A, gamma)
+    P = A * s0["rho"] ** gamma
+    f = oracle.pressure_force(ps, s0["h"], s0["rho"], P, search=0)
+    F = np.stack([f["ax"], f["ay"], f["az"]], 1) * ps.m[:, None]
+    pos = ps.pos.copy()
+    eps = 1e-6
+    scale = np.abs(F).max()
+    for k in rng.choice(n, 10, replace=False):
+        for a in range(3):
+            pp, pm = pos.copy(), pos.copy()
+            pp[k, a] += eps
+            pm[k, a] -= eps
+            fd = (_energy(ps, A, gamma, pp)[0] - _energy(ps, A, gamma, pm)[0]) / (2 * eps)
+            assert abs(-fd - F[k, a]) < 2e-6 * scale, (k, a, -fd, F[k, a])
+
+
+def test_force_conservation_and_symmetry():
+    rng = np.random.default_rng(44)
+    # isolated groups: total momentum and angular momentum change vanish
+    ps = sphgen.groups(2, seed=45, sizes=np.array([300, 120]), n_target=32.0, n_tol=1.0)
+    ps.m = rng.uniform(0.5, 1.5, ps.n)
+    s = oracle.solve(ps, mode=oracle.ROOT, root_tol=1e-14)
+    P = rng.uniform(0.5, 2.0, ps.n) * s["rho"] ** (5.0 / 3.0)
+    f = oracle.pressure_force(ps, s["h"], s["rho"], P)
+    F = np.stack([f["ax"], f["ay"], f["az"]], 1) * ps.m[:, None]
+    for a, b in zip(ps.offsets[:-1], ps.offsets[1:]):
+        scale = np.abs(F[a:b]).sum()
+        assert np.all(np.abs(F[a:b].sum(0)) < 1e-12 * scale)
+        r = ps.pos[a:b] - ps.pos[a:b].mean(0)
+        torque = np.cross(r, F[a:b]).sum(0)
+        assert np.all(np.abs(torque) < 1e-12 * (np.abs(r).max() * scale))
+    # periodic: total momentum change vanishes
+    u = sphgen.uniform(500, seed=46, n_target=32.0, n_tol=1.0)
+    su = oracle.solve(u, mode=oracle.ROOT, root_tol=1e-14)
+    Pu = rng.uniform(0.5, 2.0, u.n)
+    fu = oracle.pressure_force(u, su["h"], su["rho"], Pu)
+    Fu = np.stack([fu["ax"], fu["ay"], fu["az"]], 1) * u.m[:, None]
+    assert np.all(np.abs(Fu.sum(0)) < 1e-12 * np.abs(Fu).sum())
+    # a uniform lattice at uniform pressure: no force on any site
+    lat = sphgen.lattice(8, h=0.3, n_target=40.0, n_tol=1.0)
+    sl = oracle.solve(lat, mode=oracle.ROOT, root_tol=1e-14)
+    fl = oracle.pressure_force(lat, sl["h"], sl["rho"], np.ones(lat.n))
+    assert np.abs(np.stack([fl["ax"], fl["ay"], fl["az"]])).max() < 1e-9
+    # two equal particles alone: equal, opposite, along the axis, repulsive
+    two = _two_particles(0.3, 16.0)   # the particle alone counts 32/3: it needs the other
+    st = oracle.solve(two, mode=oracle.ROOT, root_tol=1e-14, search=0)
+    ft = oracle.pressure_force(two, st["h"], st["rho"], np.ones(2), search=0)
+    assert ft["ax"][0] < 0.0 < ft["ax"][1]
+    assert ft["ax"][0] == pytest.approx(-ft["ax"][1], rel=1e-12)
+    assert abs(ft["ay"][0]) < 1e-12 * abs(ft["ax"][0]) and abs(ft["az"][1]) < 1e-12 * abs(ft["ax"][0])
