@@ -376,6 +376,31 @@ def run_scatter(sph, torch, d, ps, steps):
                          "kernel": "k_adjoint (scatter phase)", "flop_per_launch": flop}}
 
 
+def run_force(sph, torch, d, ps, steps):
+    """The grad-h SPH pressure force (the adjoint for the cotangent m P/rho^2)
+    on the clustered 2^20 set at the h and rho of an FP32C root-mode solve,
+    P = A rho^(5/3) with A ~ U(0.5, 2) (seed 5)."""
+    p = sph.default_params(periodic=1, box=ps.box, n_target=ps.n_target, n_tol=ps.n_tol,
+                           precision=sph.FP32C, mode=sph.ROOT, root_tol=1e-6)
+    f = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p)
+    A = torch.tensor(np.random.default_rng(5).uniform(0.5, 2.0, ps.n), dtype=torch.float64,
+                     device=d["x"].device)
+    P = A * f["rho"] ** (5.0 / 3.0)
+    ws = sph.workspace(p, ps.n, 0, d["x"].device)
+    sph.pressure_force(d["x"], d["y"], d["z"], d["m"], f["h"], f["rho"], P, p, ws=ws)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        sph.pressure_force(d["x"], d["y"], d["z"], d["m"], f["h"], f["rho"], P, p, ws=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"workload": "clustered2^20 FP32C, h and rho of a root-mode solve, P = A rho^(5/3); "
+                        "sort + both walk passes + scaling per call",
+            "ms_per_call": ms, "particles_per_s": ps.n / (ms * 1e-3)}
+
+
 def cpu_baseline(ps, budget_s=15.0):
     """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
     import oracle
@@ -535,6 +560,7 @@ def main():
     ap.add_argument("--no-knn", action="store_true")
     ap.add_argument("--no-aos", action="store_true")
     ap.add_argument("--no-scatter", action="store_true")
+    ap.add_argument("--no-force", action="store_true")
     ap.add_argument("--only-knn", action="store_true",
                     help="only the exact-K leg (for a kernel trace of its stages)")
     ap.add_argument("--profile-run", action="store_true",
@@ -605,6 +631,10 @@ def main():
     if not args.no_scatter:
         scat = run_scatter(sph, torch, d, ps, max(3, args.steps // 2))
         print(f"[bench] scatter {scat}", file=sys.stderr, flush=True)
+    frc = None
+    if not args.no_force:
+        frc = run_force(sph, torch, d, ps, max(3, args.steps // 2))
+        print(f"[bench] force {frc}", file=sys.stderr, flush=True)
     aos = None
     if not args.no_aos:
         aos = run_aos(sph, torch, d, ps, max(3, args.steps // 2))
@@ -674,6 +704,8 @@ def main():
         line["aos"] = aos
     if scat is not None:
         line["scatter"] = scat
+    if frc is not None:
+        line["pressure_force"] = frc
     if adj is not None:
         line["adjoint"] = adj
     if not args.no_cpu_baseline:

@@ -238,6 +238,24 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
                          void *grad_x, void *grad_y, void *grad_z, void *grad_m,
                          void *ws, size_t ws_bytes, void *stream);
 
+/* Pressure acceleration of the variational (grad-h) SPH equations (the
+ * "other particle interaction computations" of the neighbour loop), at the
+ * converged h of sph_density_solve (h_out) and its rho (rho_out), for
+ * per-particle pressures P:
+ *   a_k = -(1/m_k) dE/dx_k,  E = sum_i m_i u_i(rho_i),  du_i/drho_i = P_i/rho_i^2,
+ * with every h_i held on its count constraint n_i(h_i, x) = n_i(achieved):
+ * the sph_density_backward gradient for grad_rho_i = m_i P_i/rho_i^2 (and
+ * grad_h = 0), divided by -m_k.  Pairwise antisymmetric: sum_k m_k a_k = 0
+ * (and no torque for isolated groups) up to rounding.  rho and pressure are
+ * inputs like x (in_stride); ax/ay/az outputs (out_stride), caller order,
+ * io_dtype, overwritten.  SPH_KNN mode: SPH_E_UNSUPPORTED. */
+int sph_pressure_force(const sph_params *params, int64_t n, int32_t n_groups,
+                       const int64_t *group_offsets,
+                       const void *x, const void *y, const void *z, const void *m,
+                       const void *h, const void *rho, const void *pressure,
+                       void *ax_out, void *ay_out, void *az_out,
+                       void *ws, size_t ws_bytes, void *stream);
+
 /* Scatter form of the density, Eq. (1) as printed (each neighbour j with its
  * own smoothing length h_j), at given h (e.g. sph_density_solve's h_out):
  *   rho_s_out[i]   = sum_{j: r_ij < h_j} m_j W(r_ij, h_j)     (i included)

@@ -17,7 +17,8 @@ import os
 
 __all__ = [
     "LIB_PATH", "Params", "SPHError", "load", "default_params", "workspace_size", "sort",
-    "density_solve", "density_backward", "density_scatter", "autotune", "density", "SPHDensity",
+    "density_solve", "density_backward", "density_scatter", "pressure_force", "autotune",
+    "density", "SPHDensity",
     "status_string",
     "FP64", "FP32C", "F64", "F32", "BAND", "ROOT", "KNN", "KERNEL_M4", "KERNEL_WENDLAND_C6",
     "ST_NOCONV", "ST_HTOOLARGE", "ST_BADINPUT", "ST_UNREACHABLE",
@@ -38,7 +39,8 @@ KERNEL_M4, KERNEL_WENDLAND_C6 = 0, 1
 
 EXPORTS = [
     "sph_default_params", "sph_workspace_size", "sph_sort", "sph_density_solve",
-    "sph_density_backward", "sph_density_scatter", "sph_autotune", "sph_status_string",
+    "sph_density_backward", "sph_density_scatter", "sph_pressure_force", "sph_autotune",
+    "sph_status_string",
     "sph_last_hip_error",
     "sph_last_hip_error_string",
 ]
@@ -107,6 +109,8 @@ def load():
     L.sph_density_backward.restype = C.c_int
     L.sph_density_scatter.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, P, SZ, P]
     L.sph_density_scatter.restype = C.c_int
+    L.sph_pressure_force.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P]
+    L.sph_pressure_force.restype = C.c_int
     L.sph_autotune.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, SZ, P, PP,
                                C.POINTER(C.c_float)]
     L.sph_autotune.restype = C.c_int
@@ -356,6 +360,35 @@ def density_scatter(x, y, z, m, h, params: Params | None = None, group_offsets=N
     if rc != OK:
         raise SPHError(rc, "sph_density_scatter")
     return dict(rho_s=rs, rho_sym=rsym, nngb_s=cnt)
+
+
+def pressure_force(x, y, z, m, h, rho, pressure, params: Params | None = None,
+                   group_offsets=None, ws=None, out=None):
+    """``sph_pressure_force``: the grad-h SPH pressure acceleration,
+    dict(ax, ay, az); strided inputs and preallocated strided ``out`` as in
+    ``density_solve``."""
+    torch = _torch()
+    params = params or default_params()
+    dev = _check_dev(x, y, z, m, h, rho, pressure, group_offsets)
+    n = x.shape[0]
+    G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    if ws is None:
+        ws = workspace(params, n, G, dev)
+    dt = _io(params)
+    if out is None:
+        ax, ay, az = (torch.empty(n, dtype=dt, device=dev) for _ in range(3))
+    else:
+        ax, ay, az = out["ax"], out["ay"], out["az"]
+        _check_dev(ax, ay, az)
+    prm = _with_strides(params, _stride_bytes(x, y, z, m, h, rho, pressure),
+                        _stride_bytes(ax, ay, az))
+    rc = load().sph_pressure_force(C.byref(prm), n, G, _ptr(group_offsets), _ptr(x), _ptr(y),
+                                   _ptr(z), _ptr(m), _ptr(h), _ptr(rho), _ptr(pressure),
+                                   _ptr(ax), _ptr(ay), _ptr(az), _ptr(ws), ws.numel(),
+                                   _stream(dev))
+    if rc != OK:
+        raise SPHError(rc, "sph_pressure_force")
+    return dict(ax=ax, ay=ay, az=az)
 
 
 def autotune(x, y, z, m, h_init=None, params: Params | None = None, group_offsets=None, ws=None):

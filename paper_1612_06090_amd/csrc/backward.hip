@@ -21,6 +21,12 @@
 // range-max table.  Every candidate is visited once and tested against both
 // radii.
 //
+// The pressure force of the variational (grad-h) SPH equations is the same
+// adjoint: with h held on its count constraint, m_k a_k = -dE/dx_k for the
+// thermal energy E = sum_i m_i u_i(rho_i), du/drho = P/rho^2, i.e. the
+// position gradient for the cotangent gr_i = m_i P_i/rho_i^2, scaled by
+// -1/m_k.
+//
 // A wave holds a tile of 16 consecutive sorted particles, each on 4 lanes
 // that split every 64-candidate chunk between them (partial sums are folded
 // across the 4 copies at the end).  The next chunk's candidates are loaded
@@ -636,10 +642,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
             if (valid) { g0 = acc0; g1 = acc1; g2 = acc2; g3 = acc3; }
             if (a.out_f32) {
                 st<float>(a.gx, oi, g0, a.ost); st<float>(a.gy, oi, g1, a.ost);
-                st<float>(a.gz, oi, g2, a.ost); st<float>(a.gm, oi, g3, a.ost);
+                st<float>(a.gz, oi, g2, a.ost);
+                if (a.gm) st<float>(a.gm, oi, g3, a.ost);
             } else {
                 st<double>(a.gx, oi, g0, a.ost); st<double>(a.gy, oi, g1, a.ost);
-                st<double>(a.gz, oi, g2, a.ost); st<double>(a.gm, oi, g3, a.ost);
+                st<double>(a.gz, oi, g2, a.ost);
+                if (a.gm) st<double>(a.gm, oi, g3, a.ost);
             }
         }
     }
@@ -758,7 +766,14 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
         hipLaunchKernelGGL(k_adj_gather<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm, grad_rho,
                            grad_h, pl.in_stride, grs, ghs);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) e = build_rmq(pl, st);
+    if (e != hipSuccess) return e;
+    return run_backward_sorted(pl, goff, gx, gy, gz, gm, st);
+}
+
+// both passes of the adjoint with the sorted-order cotangents already in place
+hipError_t run_backward_sorted(Plan &pl, const int64_t *goff, void *gx, void *gy, void *gz,
+                               void *gm, hipStream_t st) {
+    hipError_t e = build_rmq(pl, st);
     if (e != hipSuccess) return e;
     AdjArgs a;
     adj_args(pl, goff, a);
@@ -774,6 +789,55 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
     if (e != hipSuccess) return e;
     if (pl.prm.prof_events[1]) e = hipEventRecord((hipEvent_t)pl.prm.prof_events[1], st);
     return e;
+}
+
+// Pressure force cotangent m_i P_i / rho_i^2 in sorted order (caller arrays,
+// strided), grad_h = 0.
+template <typename T>
+__global__ void k_force_coef(int64_t n, const int32_t *perm, const void *m, const void *P,
+                             const void *rho, int64_t ins, double *grs, double *ghs) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    const int64_t i = perm[s];
+    const double r = ld<T>(rho, i, ins);
+    grs[s] = ld<T>(m, i, ins) * ld<T>(P, i, ins) / (r * r);
+    ghs[s] = 0.0;
+}
+
+// a_k = -dE/dx_k / m_k, in place on the adjoint's position gradient
+template <typename T>
+__global__ void k_force_scale(int64_t n, const void *m, int64_t ins, void *ax, void *ay,
+                              void *az, int64_t ost) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double w = -1.0 / ld<T>(m, i, ins);
+    st<T>(ax, i, ld<T>(ax, i, ost) * w, ost);
+    st<T>(ay, i, ld<T>(ay, i, ost) * w, ost);
+    st<T>(az, i, ld<T>(az, i, ost) * w, ost);
+}
+
+hipError_t run_force(Plan &pl, const int64_t *goff, const void *m, const void *rho,
+                     const void *P, void *ax, void *ay, void *az, hipStream_t st) {
+    const int64_t n = pl.n;
+    const unsigned nbk = (unsigned)ceil_div(n, 256);
+    double *grs = pl.adj + 3 * n, *ghs = pl.adj + 4 * n;
+    const bool f32 = pl.prm.io_dtype == SPH_F32;
+    if (f32)
+        hipLaunchKernelGGL(k_force_coef<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm, m, P,
+                           rho, pl.in_stride, grs, ghs);
+    else
+        hipLaunchKernelGGL(k_force_coef<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm, m, P,
+                           rho, pl.in_stride, grs, ghs);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = run_backward_sorted(pl, goff, ax, ay, az, nullptr, st);
+    if (e != hipSuccess) return e;
+    if (f32)
+        hipLaunchKernelGGL(k_force_scale<float>, dim3(nbk), dim3(256), 0, st, n, m,
+                           pl.in_stride, ax, ay, az, pl.out_stride);
+    else
+        hipLaunchKernelGGL(k_force_scale<double>, dim3(nbk), dim3(256), 0, st, n, m,
+                           pl.in_stride, ax, ay, az, pl.out_stride);
+    return hipGetLastError();
 }
 
 // gamma_j = m_j sigma / h_j^3 (sorted order; 0 for invalid particles), from the

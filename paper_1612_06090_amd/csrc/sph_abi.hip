@@ -328,6 +328,42 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
 }
 
 
+int sph_pressure_force(const sph_params *params, int64_t n, int32_t n_groups,
+                       const int64_t *group_offsets, const void *x, const void *y,
+                       const void *z, const void *m, const void *h, const void *rho,
+                       const void *pressure, void *ax_out, void *ay_out, void *az_out,
+                       void *ws, size_t ws_bytes, void *stream) {
+    int rc = check_params(params, n, n_groups, group_offsets);
+    if (rc != SPH_OK) return rc;
+    if (params->mode == SPH_KNN) return SPH_E_UNSUPPORTED;
+    if (n == 0) return SPH_OK;
+    if (!x || !y || !z || !m || !h || !rho || !pressure || !ax_out || !ay_out || !az_out)
+        return SPH_E_INVALID;
+    {
+        const uintptr_t es = params->io_dtype == SPH_F32 ? 4 : 8;
+        if (!aligned(x, es) || !aligned(y, es) || !aligned(z, es) || !aligned(m, es) ||
+            !aligned(h, es) || !aligned(rho, es) || !aligned(pressure, es) ||
+            !aligned(ax_out, es) || !aligned(ay_out, es) || !aligned(az_out, es))
+            return SPH_E_INVALID;
+    }
+    Plan pl;
+    rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
+    if (rc != SPH_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f32c = params->precision == SPH_FP32C;
+    pl.prm.segment = kAdjTile;
+    hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
+    if (e == hipSuccess) e = run_permute(pl, group_offsets, x, y, z, m, h, f32c, st);
+    if (e == hipSuccess) {
+        if (!pl.grouped) e = run_dense_table(pl, st);
+        else e = run_group_items(pl, group_offsets, st);
+    }
+    if (e == hipSuccess)
+        e = run_force(pl, group_offsets, m, rho, pressure, ax_out, ay_out, az_out, st);
+    if (e != hipSuccess) return hip_fail(e);
+    return SPH_OK;
+}
+
 int sph_density_scatter(const sph_params *params, int64_t n, int32_t n_groups,
                         const int64_t *group_offsets, const void *x, const void *y,
                         const void *z, const void *m, const void *h, void *rho_s_out,

@@ -161,6 +161,10 @@ hipError_t run_backward(Plan &pl, const int64_t *goff, const void *h, const void
                         hipStream_t st);
 hipError_t run_scatter(Plan &pl, const int64_t *goff, void *rho_s, void *rho_sym,
                        int32_t *nngb_s, hipStream_t st);
+hipError_t run_backward_sorted(Plan &pl, const int64_t *goff, void *gx, void *gy, void *gz,
+                               void *gm, hipStream_t st);
+hipError_t run_force(Plan &pl, const int64_t *goff, const void *m, const void *rho,
+                     const void *P, void *ax, void *ay, void *az, hipStream_t st);
 
 // ---------------------------------------------------------------- helpers
 

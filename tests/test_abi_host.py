@@ -135,6 +135,26 @@ def test_strides_accepted_and_alignment_checked():
                         ws, 1 << 30, None) == sph.E_INVALID
 
 
+def test_force_and_scatter_host_checks():
+    lib = _lib()
+    fake, ws = C.c_void_p(0x1000), C.c_void_p(0x100000)
+    p = sph.default_params()
+    # missing pressure / outputs
+    assert lib.sph_pressure_force(C.byref(p), 10, 0, None, fake, fake, fake, fake, fake, fake,
+                                  None, fake, fake, fake, ws, 1 << 30, None) == sph.E_INVALID
+    assert lib.sph_density_scatter(C.byref(p), 10, 0, None, fake, fake, fake, fake, fake, None,
+                                   None, None, ws, 1 << 30, None) == sph.E_INVALID
+    # exact-K h is not differentiable: no force from it
+    k = sph.default_params(mode=sph.KNN, n_target=32.0, n_tol=2.0)
+    assert lib.sph_pressure_force(C.byref(k), 10, 0, None, fake, fake, fake, fake, fake, fake,
+                                  fake, fake, fake, fake, ws, 1 << 30, None) == sph.E_UNSUPPORTED
+    # nothing to do
+    assert lib.sph_pressure_force(C.byref(p), 0, 0, None, None, None, None, None, None, None,
+                                  None, None, None, None, None, 0, None) == sph.OK
+    assert lib.sph_density_scatter(C.byref(p), 0, 0, None, None, None, None, None, None, None,
+                                   None, None, None, 0, None) == sph.OK
+
+
 def test_knn_backward_unsupported():
     # h of the K-th neighbour is not differentiable in the positions: refused on the host
     lib = _lib()
