@@ -125,14 +125,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_up(int64_t n, const uint
     for (int k = tid; k < 4 * 256; k += kSortThreads) (&h[0][0])[k] = 0u;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * (256 * ROUNDS) + (int64_t)w * 64 * ROUNDS;
-#pragma unroll 4
+    // all loads first, so that they are in flight together
+    uint32_t dg[ROUNDS];
+#pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const int64_t idx = base + r * 64 + l;
-        if (idx < n) {
-            const uint32_t d = (uint32_t)(keys[idx] >> shift) & 255u;
-            atomicAdd(&h[w][d], 1u);
-        }
+        dg[r] = idx < n ? (uint32_t)(keys[idx] >> shift) & 255u : 256u;
     }
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r)
+        if (dg[r] < 256u) atomicAdd(&h[w][dg[r]], 1u);
     __syncthreads();
     hist[(int64_t)tid * nb + blockIdx.x] = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
 }
@@ -176,6 +178,11 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scan(uint32_t *hist, int
     if (tid == 0) digit_tot[blockIdx.x] = tot;
 }
 
+// Scatter of one pass.  Each block ranks its 256 * ROUNDS keys stably by the
+// pass digit (waves in index order, rounds in order within a wave, lanes in
+// order within a round), places them in LDS in that order, and then writes
+// them out from LDS: consecutive threads write consecutive slots of each
+// digit's run in the output, so the stores coalesce.
 template <int ROUNDS>
 __global__ __launch_bounds__(kSortThreads) void k_radix_down(int64_t n, const uint64_t *kin,
                                                             const int32_t *vin, uint64_t *kout,
@@ -183,8 +190,12 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_down(int64_t n, const ui
                                                             const uint32_t *hist,
                                                             const uint32_t *digit_tot,
                                                             int64_t nb) {
+    constexpr int TILE = 256 * ROUNDS;
     __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t dbase[256];
+    __shared__ uint32_t dbase[256];   // output start of each digit's run of this block
+    __shared__ uint32_t lbase[256];   // LDS start of each digit's run
+    __shared__ uint64_t skey[TILE];
+    __shared__ int32_t sval[TILE];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     for (int k = tid; k < 4 * 256; k += kSortThreads) (&wcnt[0][0])[k] = 0u;
     {
@@ -193,17 +204,23 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_down(int64_t n, const ui
         dbase[tid] = pre + hist[(int64_t)tid * nb + blockIdx.x];
     }
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * (256 * ROUNDS) + (int64_t)w * 64 * ROUNDS;
+    const int64_t base = (int64_t)blockIdx.x * TILE + (int64_t)w * 64 * ROUNDS;
     uint64_t key[ROUNDS];
     int32_t val[ROUNDS];
     uint32_t rank[ROUNDS];
-    volatile uint32_t *wc = wcnt[w];
+    // all loads first, so that they are in flight together
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const int64_t idx = base + r * 64 + l;
         const bool valid = idx < n;
         key[r] = valid ? kin[idx] : ~0ull;
         val[r] = valid ? vin[idx] : 0;
+    }
+    volatile uint32_t *wc = wcnt[w];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = base + r * 64 + l;
+        const bool valid = idx < n;
         const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
         uint64_t m = __ballot(valid);
 #pragma unroll
@@ -221,6 +238,8 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_down(int64_t n, const ui
     }
     __syncthreads();
     {
+        // per digit: the waves' counts become offsets, their total the run
+        // length, and the runs are laid out in digit order in LDS
         uint32_t s = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -228,17 +247,31 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_down(int64_t n, const ui
             wcnt[k][tid] = s;
             s += t;
         }
+        const uint32_t lb = block_excl_scan_256(s, nullptr);
+        lbase[tid] = lb;
+        // output slot of LDS slot j of this digit: dbase + (j - lbase)
+        dbase[tid] = dbase[tid] - lb;
     }
     __syncthreads();
+    const int64_t blk0 = (int64_t)blockIdx.x * TILE;
+    const int cnt = n - blk0 < TILE ? (int)(n - blk0) : TILE;
 #pragma unroll
     for (int r = 0; r < ROUNDS; ++r) {
         const int64_t idx = base + r * 64 + l;
         if (idx < n) {
             const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
-            const uint32_t pos = dbase[d] + wcnt[w][d] + rank[r];
-            kout[pos] = key[r];
-            vout[pos] = val[r];
+            const uint32_t j = lbase[d] + wcnt[w][d] + rank[r];
+            skey[j] = key[r];
+            sval[j] = val[r];
         }
+    }
+    __syncthreads();
+    for (int j = tid; j < cnt; j += kSortThreads) {
+        const uint64_t k = skey[j];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t pos = dbase[d] + (uint32_t)j;
+        kout[pos] = k;
+        vout[pos] = sval[j];
     }
 }
 
