@@ -524,8 +524,8 @@ def summarize_trace(stats_csv, cmd, which="headline"):
                 "nearest particle (itself first), Wendland C6, count band [K, K + 14]. "
                 "One call = sort + three launches of the density kernel, told apart by "
                 "its last template argument: 1 the count stage (h iterated on the "
-                "integer count), 2 the selection of the K-th distance (one particle per "
-                "lane), 3 the evaluation at that h. `k_solve<1, ...>` is FP32C, "
+                "integer count), 2 the selection of the K-th distance (16-particle tiles, "
+                "4 lanes per particle, heaps merged), 3 the evaluation at that h. `k_solve<1, ...>` is FP32C, "
                 "`k_solve<0, ...>` FP64.", ""]
     else:
         path = TRACE_MD

@@ -304,6 +304,10 @@ __device__ inline void kahan(float &s, float &c, float x) {
 // copies' sums are combined before the (replicated) h update.  Smaller P
 // means a smaller tile region (fewer candidates per particle) and a shorter
 // sequential stream per wave, at the price of more tiles.
+// Particles per wave tile of the exact-K selection pass (4 lanes per particle,
+// each with its own heap; the heaps are merged at the end of the pass).
+constexpr int kSelTile = 16;
+
 // Selection heap of the exact-K mode: per lane, a min-heap of the CAP largest
 // squared distances inside h (binary64 for FP64, binary32 for FP32C: rounding
 // is monotone, so the order is kept and only the selected value is rounded),
@@ -358,16 +362,16 @@ __device__ inline void sel_pop(T *H, int l, int &hc) {
 
 // STAGE 0: the density solve of the band and root modes.  Exact K runs three
 // launches: 1 iterates h on the integer count into the band [K, K + dK]
-// (writes knn_h, knn_st); 2 selects (one lane per particle, P = 64): at the
-// count-stage h of each particle the squared distances inside h go through the
-// lane's heap, and the K-th smallest becomes the particle's h (writes sh_out,
-// knn_st); 3 evaluates at that h with the status of knn_st.  The stage is a
+// (writes knn_h, knn_st); 2 selects (16-particle tiles, 4 lanes per
+// particle): at the count-stage h of each particle the squared distances
+// inside h go through the lanes' heaps, which copy 0 merges, and the K-th
+// smallest becomes the particle's h (writes sh_out, knn_st); 3 evaluates at
+// that h with the status of knn_st.  The stage is a
 // template argument so that the band-mode kernel carries none of it.
 template <int PREC, bool GROUPED, int P, int KERNEL, int STAGE = 0, int CAP = 64>
 __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     using KT = Kern<KERNEL>;
     constexpr bool SEL = STAGE == 2;
-    static_assert(!SEL || P == 64, "the selection pass holds one particle per lane");
     using HeapT = typename std::conditional<PREC == SPH_FP64, double, float>::type;
     __shared__ HeapT selheap[SEL ? 64 * CAP : 1];
     constexpr int S = 64 / P;
@@ -660,7 +664,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                             // selection: squared distances inside h into the heap
                             if (PREC == SPH_FP64) {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
-                                for (int t = 0; t < mc; ++t) {
+                                for (int t = kk; t < mc; t += S) {
                                     const double dx = (c.x[t] - xi) + c.shx[t];
                                     const double dy = (c.y[t] - yi) + c.shy[t];
                                     const double dz = (c.z[t] - zi) + c.shz[t];
@@ -679,7 +683,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                 // holds at least K, and its order is the binary64 one
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
                                 const double hq2 = hq * hq * (1.0 + 0x1p-18);
-                                for (int t = 0; t < mc; ++t) {
+                                for (int t = kk; t < mc; t += S) {
                                     const float4 cj = c.c[t];
                                     const double dx = (double)cj.x - (double)pix;
                                     const double dy = (double)cj.y - (double)piy;
@@ -778,21 +782,39 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 cnt_cands += pass_cands;
                 cnt_passes += (uint64_t)__popcll(am);
             }
-            if (SEL && !done) {
-                // the K-th smallest of the sel_n distances inside h is the
-                // (sel_n - K + 1)-th largest: pop the heap down to that rank
-                const int rank = sel_n - (int)a.Nt + 1;
-                double hk = hs.h;
-                int32_t stt = st_in;
-                if (rank >= 1 && rank <= sel_hc) {
-                    while (sel_hc > rank) sel_pop(selheap, l, sel_hc);
-                    const double d2 = (double)selheap[l];
-                    hk = PREC == SPH_FP64 ? sqrt(d2) : sqrt(d2) / sc;
-                } else {
-                    stt |= SPH_ST_NOCONV;  // the count stage's h did not hold K
+            if (SEL) {
+                // each copy kept the CAP largest of its share of the distances
+                // inside h; copy 0 takes in the other copies' heaps (the union's
+                // CAP largest contain its rank-th largest for any rank <= CAP)
+                int seln = sel_n;
+                int hco[S > 1 ? S - 1 : 1];
+#pragma unroll
+                for (int o = P; o < 64; o <<= 1) seln += __shfl_xor(seln, o, 64);
+#pragma unroll
+                for (int k = 1; k < S; ++k) hco[k - 1] = __shfl(sel_hc, p + k * P, 64);
+                __syncthreads();
+                if (!done && kk == 0) {
+#pragma unroll
+                    for (int k = 1; k < S; ++k) {
+                        const int lo = p + k * P;
+                        for (int i = 0; i < hco[k - 1]; ++i)
+                            sel_insert<CAP>(selheap, l, sel_hc, selheap[i * 64 + lo], sel_min);
+                    }
+                    // the K-th smallest of the seln distances inside h is the
+                    // (seln - K + 1)-th largest: pop the heap down to that rank
+                    const int rank = seln - (int)a.Nt + 1;
+                    double hk = hs.h;
+                    int32_t stt = st_in;
+                    if (rank >= 1 && rank <= sel_hc) {
+                        while (sel_hc > rank) sel_pop(selheap, l, sel_hc);
+                        const double d2 = (double)selheap[l];
+                        hk = PREC == SPH_FP64 ? sqrt(d2) : sqrt(d2) / sc;
+                    } else {
+                        stt |= SPH_ST_NOCONV;  // the count stage's h did not hold K
+                    }
+                    a.sh_out[b + p] = hk;
+                    a.knn_st[b + p] = stt;
                 }
-                a.sh_out[b + p] = hk;
-                a.knn_st[b + p] = stt;
                 done = true;
             }
             if (!SEL && !done) {
@@ -870,7 +892,7 @@ static hipError_t launch_solve(const Plan &pl, SolveArgs &a, int seg, int64_t gr
         // the selection pass needs distances only: one kernel shape per
         // precision and heap size
 #define SPH_SEL(PR, GR, CP) \
-    hipLaunchKernelGGL((k_solve<PR, GR, 64, SPH_KERNEL_M4, 2, CP>), grid, block, 0, st, a)
+    hipLaunchKernelGGL((k_solve<PR, GR, kSelTile, SPH_KERNEL_M4, 2, CP>), grid, block, 0, st, a)
 #define SPH_SEL_CAP(PR, GR)                                  \
     do {                                                    \
         if (a.sel_cap == 16) SPH_SEL(PR, GR, 16);           \
@@ -947,18 +969,18 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     if (pl.prm.mode != SPH_KNN) {
         e = launch_solve(pl, a, seg, pl.grid, 0, st);
     } else {
-        // exact K: count band, selection of the K-th distance (one particle per
-        // lane), evaluation at that distance
+        // exact K: count band, selection of the K-th distance (its own tile
+        // size), evaluation at that distance
         const int64_t full = (int64_t)256 * pl.prm.waves_per_cu;
         e = launch_solve(pl, a, seg, pl.grid, 1, st);
         if (e == hipSuccess && pl.grouped) {
-            pl.prm.segment = 64;
+            pl.prm.segment = kSelTile;
             e = run_group_items(pl, goff, st);
         }
         if (e == hipSuccess) {
-            a.n_items = ceil_div(pl.n, 64);
+            a.n_items = ceil_div(pl.n, kSelTile);
             const int64_t g2 = pl.grouped ? full : (a.n_items < full ? a.n_items : full);
-            e = launch_solve(pl, a, 64, g2 > 0 ? g2 : 1, 2, st);
+            e = launch_solve(pl, a, kSelTile, g2 > 0 ? g2 : 1, 2, st);
         }
         if (e == hipSuccess && pl.grouped) {
             pl.prm.segment = seg;
