@@ -707,13 +707,16 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                     const double dz = (c.z[t] - zi) + c.shz[t];
                                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                                     if (r2 < h2) {
-                                        // scaled pair terms (factors applied to the totals)
-                                        const double q = sqrt(r2) * hinv;
-                                        double fh, gs;
-                                        KT::template terms<double>(q, q * q, fh, gs);
-                                        sm.d0 += fh;
-                                        sm.d1 += gs;
-                                        sm.dr += c.m[t] * fh;
+                                        // the exact-K count stage needs the count only
+                                        if (STAGE != 1) {
+                                            // scaled pair terms (factors applied to the totals)
+                                            const double q = sqrt(r2) * hinv;
+                                            double fh, gs;
+                                            KT::template terms<double>(q, q * q, fh, gs);
+                                            sm.d0 += fh;
+                                            sm.d1 += gs;
+                                            sm.dr += c.m[t] * fh;
+                                        }
                                         sm.n += 1;
                                     }
                                 }
@@ -729,14 +732,16 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                     const float dz = cj.z - piz;
                                     const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
                                     if (r2 < h2f) {
-                                        // scaled pair terms (factors applied to the totals)
-                                        const float q2 = r2 * ih2;
-                                        const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
-                                        float fh, gs;
-                                        KT::template terms<float>(q, q2, fh, gs);
-                                        pa0 += fh;
-                                        pa1 += gs;
-                                        par = __builtin_fmaf(cj.w, fh, par);
+                                        if (STAGE != 1) {
+                                            // scaled pair terms (factors applied to the totals)
+                                            const float q2 = r2 * ih2;
+                                            const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
+                                            float fh, gs;
+                                            KT::template terms<float>(q, q2, fh, gs);
+                                            pa0 += fh;
+                                            pa1 += gs;
+                                            par = __builtin_fmaf(cj.w, fh, par);
+                                        }
                                         sm.n += 1;
                                     }
                                 }
