@@ -205,6 +205,11 @@ def run_batched(sph, torch, steps, warmup):
             "n": n, "groups": G, "ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
             "particles_per_s": n / (ms * 1e-3), "pairs_per_step": pairs,
             "candidates_per_step": cands, "final_pairs_per_s": final_pairs / (ms * 1e-3),
+            "roofline": {"bound": "alu", "kernel": "k_solve (groups, whole replay)",
+                         "achieved": (FLOP_CAND * cands + FLOP_PAIR["fp32c"] * pairs)
+                         / (ms * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                         "frac": (FLOP_CAND * cands + FLOP_PAIR["fp32c"] * pairs)
+                         / (ms * 1e-3) / PEAK_FP32},
             "tuned": {"segment": p.segment, "waves_per_cu": p.waves_per_cu,
                       "tile_cell": p.tile_cell, "ms": tuned_ms, "tuning_s": tune_s}}
 
