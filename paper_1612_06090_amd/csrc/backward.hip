@@ -50,8 +50,8 @@ struct AdjArgs {
     const uint64_t *skeys;
     const int32_t *perm;
     const double *sx, *sy, *sz, *sm, *sh;
-    const int32_t *qx, *qy, *qz;
-    const float *fx, *fy, *fz, *fm;
+    const int4 *qp;     // FP32C: grid cell, mass bits
+    const float4 *fp;   // FP32C: fraction
     const int32_t *table;
     int32_t Ld;
     const double *frame;
@@ -171,9 +171,11 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 fyk = (float)(ty - (double)qyk);
                 fzk = (float)(tz - (double)qzk);
             } else {
-                qxk = a.qx[s]; qyk = a.qy[s]; qzk = a.qz[s];
-                fxk = a.fx[s]; fyk = a.fy[s]; fzk = a.fz[s];
-                mk = (double)a.fm[s];
+                const int4 q4 = a.qp[s];
+                const float4 f4 = a.fp[s];
+                qxk = q4.x; qyk = q4.y; qzk = q4.z;
+                fxk = f4.x; fyk = f4.y; fzk = f4.z;
+                mk = (double)__int_as_float(q4.w);
                 valid = !isnan(fxk);
             }
         }
@@ -268,9 +270,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                     } else {
                         const int32_t W = 1 << B;
                         const double hqj = hj * sc;
-                        c.p = make_float4((float)(a.qx[j] + sh0 * W - t0) + a.fx[j],
-                                          (float)(a.qy[j] + sh1 * W - t1) + a.fy[j],
-                                          (float)(a.qz[j] + sh2 * W - t2) + a.fz[j], a.fm[j]);
+                        const int4 q4 = a.qp[j];
+                        const float4 f4 = a.fp[j];
+                        c.p = make_float4((float)(q4.x + sh0 * W - t0) + f4.x,
+                                          (float)(q4.y + sh1 * W - t1) + f4.y,
+                                          (float)(q4.z + sh2 * W - t2) + f4.z,
+                                          __int_as_float(q4.w));
                         c.h = make_float4((float)hqj, (float)(1.0 / hqj), (float)aj, (float)bj);
                         c.g = (float)gj;
                     }
@@ -705,8 +710,8 @@ static void adj_args(const Plan &pl, const int64_t *goff, AdjArgs &a) {
     a.skeys = pl.skeys;
     a.perm = pl.perm;
     a.sx = pl.sx; a.sy = pl.sy; a.sz = pl.sz; a.sm = pl.sm; a.sh = pl.sh0;
-    a.qx = pl.qx; a.qy = pl.qy; a.qz = pl.qz;
-    a.fx = pl.fx; a.fy = pl.fy; a.fz = pl.fz; a.fm = pl.fm;
+    a.qp = pl.qp;
+    a.fp = pl.fp;
     a.table = pl.table;
     a.Ld = pl.Ld;
     a.frame = pl.frame;
@@ -843,13 +848,13 @@ hipError_t run_force(Plan &pl, const int64_t *goff, const void *m, const void *r
 // gamma_j = m_j sigma / h_j^3 (sorted order; 0 for invalid particles), from the
 // masses the walk itself uses (binary32 in FP32C)
 template <int KERNEL>
-__global__ void k_scatter_coef(int64_t n, const double *sm, const float *fm, const double *sh,
-                               const double *sx, const float *fx, double *gamma) {
+__global__ void k_scatter_coef(int64_t n, const double *sm, const int4 *qp, const double *sh,
+                               const double *sx, const float4 *fp, double *gamma) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double h = sh[s];
-    const bool valid = sm ? !isnan(sx[s]) : !isnan(fx[s]);
-    const double m = sm ? sm[s] : (double)fm[s];
+    const bool valid = sm ? !isnan(sx[s]) : !isnan(fp[s].x);
+    const double m = sm ? sm[s] : (double)__int_as_float(qp[s].w);
     gamma[s] = valid ? m * Kern<KERNEL>::sigma / (h * h * h) : 0.0;
 }
 
@@ -860,13 +865,12 @@ hipError_t run_scatter(Plan &pl, const int64_t *goff, void *rho_s, void *rho_sym
     const bool f32c = pl.prm.precision == SPH_FP32C;
     double *gamma = pl.adj + 2 * n;
     const double *sm = f32c ? nullptr : pl.sm;
-    const float *fm = f32c ? pl.fm : nullptr;
     if (pl.prm.kernel == SPH_KERNEL_WENDLAND_C6)
         hipLaunchKernelGGL(k_scatter_coef<SPH_KERNEL_WENDLAND_C6>, dim3(nbk), dim3(256), 0, st,
-                           n, sm, fm, pl.sh0, pl.sx, pl.fx, gamma);
+                           n, sm, pl.qp, pl.sh0, pl.sx, pl.fp, gamma);
     else
-        hipLaunchKernelGGL(k_scatter_coef<SPH_KERNEL_M4>, dim3(nbk), dim3(256), 0, st, n, sm, fm,
-                           pl.sh0, pl.sx, pl.fx, gamma);
+        hipLaunchKernelGGL(k_scatter_coef<SPH_KERNEL_M4>, dim3(nbk), dim3(256), 0, st, n, sm,
+                           pl.qp, pl.sh0, pl.sx, pl.fp, gamma);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = build_rmq(pl, st);
     if (e != hipSuccess) return e;

@@ -47,8 +47,8 @@ struct SolveArgs {
     const uint64_t *skeys;
     const int32_t *perm;
     const double *sx, *sy, *sz, *sm, *sh0;
-    const int32_t *qx, *qy, *qz;
-    const float *fx, *fy, *fz, *fm;
+    const int4 *qp;     // FP32C: grid cell, mass bits
+    const float4 *fp;   // FP32C: fraction
     const int32_t *table;
     int32_t Ld;
     const double *frame;
@@ -445,8 +445,10 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 xi = a.sx[s]; yi = a.sy[s]; zi = a.sz[s];
                 valid = !isnan(xi);
             } else {
-                qxi = a.qx[s]; qyi = a.qy[s]; qzi = a.qz[s];
-                fxi = a.fx[s]; fyi = a.fy[s]; fzi = a.fz[s];
+                const int4 q4 = a.qp[s];
+                const float4 f4 = a.fp[s];
+                qxi = q4.x; qyi = q4.y; qzi = q4.z;
+                fxi = f4.x; fyi = f4.y; fzi = f4.z;
                 valid = !isnan(fxi);
             }
         }
@@ -649,10 +651,12 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                             } else {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
                                 const int32_t W = 1 << B;
-                                c.c[l] = make_float4((float)(a.qx[j] + sh0 * W - o0) + a.fx[j],
-                                                     (float)(a.qy[j] + sh1 * W - o1) + a.fy[j],
-                                                     (float)(a.qz[j] + sh2 * W - o2) + a.fz[j],
-                                                     a.fm[j]);
+                                const int4 q4 = a.qp[j];
+                                const float4 f4 = a.fp[j];
+                                c.c[l] = make_float4((float)(q4.x + sh0 * W - o0) + f4.x,
+                                                     (float)(q4.y + sh1 * W - o1) + f4.y,
+                                                     (float)(q4.z + sh2 * W - o2) + f4.z,
+                                                     __int_as_float(q4.w));
                             }
                         }
                         __syncthreads();
@@ -932,8 +936,8 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     a.skeys = pl.skeys;
     a.perm = pl.perm;
     a.sx = pl.sx; a.sy = pl.sy; a.sz = pl.sz; a.sm = pl.sm; a.sh0 = pl.sh0;
-    a.qx = pl.qx; a.qy = pl.qy; a.qz = pl.qz;
-    a.fx = pl.fx; a.fy = pl.fy; a.fz = pl.fz; a.fm = pl.fm;
+    a.qp = pl.qp;
+    a.fp = pl.fp;
     a.table = pl.table;
     a.Ld = pl.Ld;
     a.frame = pl.frame;

@@ -379,13 +379,14 @@ __global__ void k_permute64(int64_t n, const int32_t *perm, const uint64_t *skey
 }
 
 // Positions as integer Morton-grid coordinates q (units of the grid spacing:
-// box / 2^21, or the group cube / 2^16) plus a binary32 fraction in [0, 1].
+// box / 2^21, or the group cube / 2^16) plus a binary32 fraction in [0, 1],
+// packed per particle as (q, mass bits) and (fraction, 0): a candidate is two
+// 16-byte loads.
 template <typename T>
 __global__ void k_permute32(int64_t n, const int32_t *perm, const uint64_t *skeys,
                             const void *x, const void *y, const void *z, const void *m,
                             const void *h0, int64_t ins, bool grouped, double box, const double *frame,
-                            const int64_t *goff, int32_t *qx, int32_t *qy, int32_t *qz,
-                            float *fx, float *fy, float *fz, float *fm, double *sh0) {
+                            const int64_t *goff, int4 *qp, float4 *fp, double *sh0) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = perm[s];
@@ -405,9 +406,8 @@ __global__ void k_permute32(int64_t n, const int32_t *perm, const uint64_t *skey
     const uint32_t ux = quantise(tx, nmax), uy = quantise(ty, nmax), uz = quantise(tz, nmax);
     float ax = (float)(tx - (double)ux), ay = (float)(ty - (double)uy), az = (float)(tz - (double)uz);
     if (!valid_input(!grouped, box, xv, yv, zv, mv, hv)) { ax = NAN; ay = NAN; az = NAN; }
-    qx[s] = (int32_t)ux; qy[s] = (int32_t)uy; qz[s] = (int32_t)uz;
-    fx[s] = ax; fy[s] = ay; fz[s] = az;
-    fm[s] = (float)mv;
+    qp[s] = make_int4((int32_t)ux, (int32_t)uy, (int32_t)uz, __float_as_int((float)mv));
+    fp[s] = make_float4(ax, ay, az, 0.f);
     sh0[s] = hv;
 }
 
@@ -430,11 +430,11 @@ hipError_t run_permute(Plan &pl, const int64_t *goff, const void *x, const void 
         if (f32)
             hipLaunchKernelGGL(k_permute32<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
                                pl.skeys, x, y, z, m, h0, pl.in_stride, pl.grouped, pl.prm.box, pl.frame, goff,
-                               pl.qx, pl.qy, pl.qz, pl.fx, pl.fy, pl.fz, pl.fm, pl.sh0);
+                               pl.qp, pl.fp, pl.sh0);
         else
             hipLaunchKernelGGL(k_permute32<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
                                pl.skeys, x, y, z, m, h0, pl.in_stride, pl.grouped, pl.prm.box, pl.frame, goff,
-                               pl.qx, pl.qy, pl.qz, pl.fx, pl.fy, pl.fz, pl.fm, pl.sh0);
+                               pl.qp, pl.fp, pl.sh0);
     }
     return hipGetLastError();
 }

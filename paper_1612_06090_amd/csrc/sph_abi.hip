@@ -82,13 +82,8 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
         pl.sz = (double *)take(8 * N);
         pl.sm = (double *)take(8 * N);
     } else {
-        pl.qx = (int32_t *)take(4 * N);
-        pl.qy = (int32_t *)take(4 * N);
-        pl.qz = (int32_t *)take(4 * N);
-        pl.fx = (float *)take(4 * N);
-        pl.fy = (float *)take(4 * N);
-        pl.fz = (float *)take(4 * N);
-        pl.fm = (float *)take(4 * N);
+        pl.qp = (int4 *)take(16 * N);
+        pl.fp = (float4 *)take(16 * N);
     }
     pl.sh0 = (double *)take(8 * N);
     if (pl.table_n > 0) pl.table = (int32_t *)take(4 * (size_t)pl.table_n);

@@ -108,8 +108,10 @@ struct Plan {
     uint32_t *hist = nullptr, *digit_tot = nullptr;
     // sorted structure-of-arrays
     double *sx = nullptr, *sy = nullptr, *sz = nullptr, *sm = nullptr, *sh0 = nullptr;
-    int32_t *qx = nullptr, *qy = nullptr, *qz = nullptr;
-    float *fx = nullptr, *fy = nullptr, *fz = nullptr, *fm = nullptr;
+    // FP32C: per particle (qx, qy, qz, bits of the binary32 mass) and (fx, fy,
+    // fz, 0): the integer grid cell and the binary32 fraction, 2 x 16 bytes
+    int4 *qp = nullptr;
+    float4 *fp = nullptr;
     int32_t *table = nullptr;
     int32_t *scan_a = nullptr;   // n-sized int32 scratch (cell flags / scan)
     int32_t *bsum = nullptr;     // block sums of scans
