@@ -190,3 +190,30 @@ def test_knn_clustered2p20_K295_wc6_sampled(dk):
     assert np.all((g64["status"] & FLAGS) == 0)
     assert np.array_equal(g64["h"][sub], o["h"])
     assert np.array_equal(g64["nngb"][sub], o["nngb"])
+
+
+def test_knn_out_of_updates_flags_noconv():
+    # from a tiny h_init with one count update allowed, most particles never
+    # bracket the band: they are flagged NOCONV; the others are still exact
+    ps = sphgen.uniform(4096, seed=91)
+    h0 = np.full(ps.n, 1e-3)
+    g = gpu_solve(ps, h_init=h0, mode=KNN, n_target=64.0, n_tol=8.0, max_iter=1)
+    o = oracle.knn(ps, 64)
+    noconv = (g["status"] & sph.ST_NOCONV) != 0
+    say(f"  NOCONV {noconv.sum()} / {ps.n}")
+    assert noconv.sum() > ps.n // 2
+    assert np.all((g["status"][~noconv] & FLAGS) == 0)
+    assert np.array_equal(g["h"][~noconv], o["h"][~noconv])
+
+
+def test_knn_autotune():
+    import torch
+    ps = sphgen.plummer_mixture(1 << 14, 8, seed=92)
+    p = sph.default_params(mode=KNN, n_target=64.0, n_tol=8.0)
+    d = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+         for k in ("x", "y", "z", "m", "h_init")}
+    best, ms = sph.autotune(d["x"], d["y"], d["z"], d["m"], d["h_init"], p)
+    assert best.mode == KNN and best.segment in (8, 16, 32, 64) and ms > 0.0
+    g = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], best)
+    torch.cuda.synchronize()
+    assert np.array_equal(g["h"].cpu().numpy(), oracle.knn(ps, 64)["h"])

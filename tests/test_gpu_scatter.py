@@ -165,3 +165,16 @@ def test_scatter_clustered2p20_fp32c():
     flips = int((g["nngb_s"] != o["nngb_s"]).sum())
     say(f"  max rel rho_s {d1:.2e} rho_sym {d2:.2e} count flips {flips}")
     assert d1 <= 1e-5 and d2 <= 1e-5 and flips <= ps.n // 10000
+
+
+def test_scatter_groups_f32_io():
+    # isolated groups with binary32 inputs: the oracle takes the same rounded values
+    ps = sphgen.groups(40, seed=80, lo=10, hi=2000)
+    for k in ("x", "y", "z", "m"):
+        setattr(ps, k, np.asarray(getattr(ps, k), dtype=np.float32).astype(np.float64))
+    h = np.asarray(np.random.default_rng(81).uniform(0.002, 0.04, ps.n),
+                   dtype=np.float32).astype(np.float64)
+    g = _scatter(ps, h, io="float32")
+    o = oracle.scatter(ps, h)
+    assert rel(g["rho_s"].astype(np.float64), o["rho_s"]).max() <= 2.0 ** -23
+    assert np.array_equal(g["nngb_s"], o["nngb_s"].astype(np.int32))
