@@ -49,7 +49,8 @@ struct AdjArgs {
     const int64_t *goff;
     const uint64_t *skeys;
     const int32_t *perm;
-    const double *sx, *sy, *sz, *sm, *sh;
+    const double4 *sp;  // FP64: x, y, z, m
+    const double *sh;
     const int4 *qp;     // FP32C: grid cell, mass bits
     const float4 *fp;   // FP32C: fraction
     const int32_t *table;
@@ -161,7 +162,8 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
         if (mine) {
             hk = a.sh[s];
             if constexpr (PREC == SPH_FP64) {
-                xk = a.sx[s]; yk = a.sy[s]; zk = a.sz[s]; mk = a.sm[s];
+                const double4 p4 = a.sp[s];
+                xk = p4.x; yk = p4.y; zk = p4.z; mk = p4.w;
                 valid = !isnan(xk);
                 const double tx = (xk - org0) * sc, ty = (yk - org1) * sc, tz = (zk - org2) * sc;
                 qxk = valid ? (int32_t)floor(tx) : 0;
@@ -262,7 +264,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                     const double bj = a.phase == 2 ? a.beta[j] : 0.0;
                     const double gj = a.phase >= 2 ? a.gamma[j] : 0.0;
                     if constexpr (PREC == SPH_FP64) {
-                        c.p = make_double4(a.sx[j], a.sy[j], a.sz[j], a.sm[j]);
+                        c.p = a.sp[j];
                         c.s = make_double4((double)sh0 * a.box, (double)sh1 * a.box,
                                            (double)sh2 * a.box, 0.0);
                         c.h = make_double4(hj, 1.0 / hj, aj, bj);
@@ -709,7 +711,7 @@ static void adj_args(const Plan &pl, const int64_t *goff, AdjArgs &a) {
     a.goff = goff;
     a.skeys = pl.skeys;
     a.perm = pl.perm;
-    a.sx = pl.sx; a.sy = pl.sy; a.sz = pl.sz; a.sm = pl.sm; a.sh = pl.sh0;
+    a.sp = pl.sp; a.sh = pl.sh0;
     a.qp = pl.qp;
     a.fp = pl.fp;
     a.table = pl.table;
@@ -848,13 +850,13 @@ hipError_t run_force(Plan &pl, const int64_t *goff, const void *m, const void *r
 // gamma_j = m_j sigma / h_j^3 (sorted order; 0 for invalid particles), from the
 // masses the walk itself uses (binary32 in FP32C)
 template <int KERNEL>
-__global__ void k_scatter_coef(int64_t n, const double *sm, const int4 *qp, const double *sh,
-                               const double *sx, const float4 *fp, double *gamma) {
+__global__ void k_scatter_coef(int64_t n, const double4 *sp, const int4 *qp, const double *sh,
+                               const float4 *fp, double *gamma) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const double h = sh[s];
-    const bool valid = sm ? !isnan(sx[s]) : !isnan(fp[s].x);
-    const double m = sm ? sm[s] : (double)__int_as_float(qp[s].w);
+    const bool valid = sp ? !isnan(sp[s].x) : !isnan(fp[s].x);
+    const double m = sp ? sp[s].w : (double)__int_as_float(qp[s].w);
     gamma[s] = valid ? m * Kern<KERNEL>::sigma / (h * h * h) : 0.0;
 }
 
@@ -864,13 +866,13 @@ hipError_t run_scatter(Plan &pl, const int64_t *goff, void *rho_s, void *rho_sym
     const unsigned nbk = (unsigned)ceil_div(n, 256);
     const bool f32c = pl.prm.precision == SPH_FP32C;
     double *gamma = pl.adj + 2 * n;
-    const double *sm = f32c ? nullptr : pl.sm;
+    const double4 *sp = f32c ? nullptr : pl.sp;
     if (pl.prm.kernel == SPH_KERNEL_WENDLAND_C6)
         hipLaunchKernelGGL(k_scatter_coef<SPH_KERNEL_WENDLAND_C6>, dim3(nbk), dim3(256), 0, st,
-                           n, sm, pl.qp, pl.sh0, pl.sx, pl.fp, gamma);
+                           n, sp, pl.qp, pl.sh0, pl.fp, gamma);
     else
-        hipLaunchKernelGGL(k_scatter_coef<SPH_KERNEL_M4>, dim3(nbk), dim3(256), 0, st, n, sm,
-                           pl.qp, pl.sh0, pl.sx, pl.fp, gamma);
+        hipLaunchKernelGGL(k_scatter_coef<SPH_KERNEL_M4>, dim3(nbk), dim3(256), 0, st, n, sp,
+                           pl.qp, pl.sh0, pl.fp, gamma);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = build_rmq(pl, st);
     if (e != hipSuccess) return e;

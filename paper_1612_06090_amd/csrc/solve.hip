@@ -46,7 +46,8 @@ struct SolveArgs {
     const int64_t *goff;
     const uint64_t *skeys;
     const int32_t *perm;
-    const double *sx, *sy, *sz, *sm, *sh0;
+    const double4 *sp;  // FP64: x, y, z, m
+    const double *sh0;
     const int4 *qp;     // FP32C: grid cell, mass bits
     const float4 *fp;   // FP32C: fraction
     const int32_t *table;
@@ -442,7 +443,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         bool valid = false;
         if (mine) {
             if (PREC == SPH_FP64) {
-                xi = a.sx[s]; yi = a.sy[s]; zi = a.sz[s];
+                const double4 p4 = a.sp[s];
+                xi = p4.x; yi = p4.y; zi = p4.z;
                 valid = !isnan(xi);
             } else {
                 const int4 q4 = a.qp[s];
@@ -641,10 +643,11 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                       sh2 = ((cc >> 4) & 3) - 1;
                             if (PREC == SPH_FP64) {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
-                                c.x[l] = a.sx[j];
-                                c.y[l] = a.sy[j];
-                                c.z[l] = a.sz[j];
-                                c.m[l] = a.sm[j];
+                                const double4 p4 = a.sp[j];
+                                c.x[l] = p4.x;
+                                c.y[l] = p4.y;
+                                c.z[l] = p4.z;
+                                c.m[l] = p4.w;
                                 c.shx[l] = (double)sh0 * a.box;
                                 c.shy[l] = (double)sh1 * a.box;
                                 c.shz[l] = (double)sh2 * a.box;
@@ -935,7 +938,7 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     a.goff = goff;
     a.skeys = pl.skeys;
     a.perm = pl.perm;
-    a.sx = pl.sx; a.sy = pl.sy; a.sz = pl.sz; a.sm = pl.sm; a.sh0 = pl.sh0;
+    a.sp = pl.sp; a.sh0 = pl.sh0;
     a.qp = pl.qp;
     a.fp = pl.fp;
     a.table = pl.table;

@@ -365,8 +365,7 @@ template <typename T>
 __global__ void k_permute64(int64_t n, const int32_t *perm, const uint64_t *skeys,
                             const void *x, const void *y, const void *z, const void *m,
                             const void *h0, int64_t ins, bool grouped, double box, const double *frame,
-                            const int64_t *goff, double *sx, double *sy, double *sz, double *sm,
-                            double *sh0) {
+                            const int64_t *goff, double4 *sp, double *sh0) {
     const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (s >= n) return;
     const int64_t i = perm[s];
@@ -375,7 +374,8 @@ __global__ void k_permute64(int64_t n, const int32_t *perm, const uint64_t *skey
     if (!valid_input(!grouped, box, xv, yv, zv, mv, hv)) {
         xv = NAN; yv = NAN; zv = NAN;
     }
-    sx[s] = xv; sy[s] = yv; sz[s] = zv; sm[s] = mv; sh0[s] = hv;
+    sp[s] = make_double4(xv, yv, zv, mv);
+    sh0[s] = hv;
 }
 
 // Positions as integer Morton-grid coordinates q (units of the grid spacing:
@@ -421,11 +421,11 @@ hipError_t run_permute(Plan &pl, const int64_t *goff, const void *x, const void 
         if (f32)
             hipLaunchKernelGGL(k_permute64<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
                                pl.skeys, x, y, z, m, h0, pl.in_stride, pl.grouped, pl.prm.box, pl.frame, goff,
-                               pl.sx, pl.sy, pl.sz, pl.sm, pl.sh0);
+                               pl.sp, pl.sh0);
         else
             hipLaunchKernelGGL(k_permute64<double>, dim3(nbk), dim3(256), 0, st, n, pl.perm,
                                pl.skeys, x, y, z, m, h0, pl.in_stride, pl.grouped, pl.prm.box, pl.frame, goff,
-                               pl.sx, pl.sy, pl.sz, pl.sm, pl.sh0);
+                               pl.sp, pl.sh0);
     } else {
         if (f32)
             hipLaunchKernelGGL(k_permute32<float>, dim3(nbk), dim3(256), 0, st, n, pl.perm,

@@ -77,10 +77,7 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
     pl.hist = (uint32_t *)take(4 * 256 * (size_t)pl.nb_sort);
     pl.digit_tot = (uint32_t *)take(4 * 256);
     if (!f32c) {
-        pl.sx = (double *)take(8 * N);
-        pl.sy = (double *)take(8 * N);
-        pl.sz = (double *)take(8 * N);
-        pl.sm = (double *)take(8 * N);
+        pl.sp = (double4 *)take(32 * N);
     } else {
         pl.qp = (int4 *)take(16 * N);
         pl.fp = (float4 *)take(16 * N);

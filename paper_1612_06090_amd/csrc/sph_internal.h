@@ -107,7 +107,8 @@ struct Plan {
     int32_t *valsA = nullptr, *valsB = nullptr;
     uint32_t *hist = nullptr, *digit_tot = nullptr;
     // sorted structure-of-arrays
-    double *sx = nullptr, *sy = nullptr, *sz = nullptr, *sm = nullptr, *sh0 = nullptr;
+    double4 *sp = nullptr;       // FP64: x, y, z, m per particle (one 32-byte record)
+    double *sh0 = nullptr;
     // FP32C: per particle (qx, qy, qz, bits of the binary32 mass) and (fx, fy,
     // fz, 0): the integer grid cell and the binary32 fraction, 2 x 16 bytes
     int4 *qp = nullptr;
