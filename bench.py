@@ -524,7 +524,7 @@ def summarize_trace(stats_csv, cmd, which="headline"):
         path = TRACE_KNN_MD
         head = ["# Exact-K stages on clustered2^20 (K = 295, Wendland C6) — rocprofv3 "
                 "kernel trace", "",
-                "Command (GPU box, repo root):", "", "    " + cmd, "",
+                "Command (on the GPU host, from the repository root):", "", "    " + cmd, "",
                 "Workload: the 2^20-particle clustered set, h = distance of the 295th "
                 "nearest particle (itself first), Wendland C6, count band [K, K + 14]. "
                 "One call = sort + three launches of the density kernel, told apart by "
@@ -535,7 +535,7 @@ def summarize_trace(stats_csv, cmd, which="headline"):
     else:
         path = TRACE_MD
         head = ["# k_solve on clustered2^20 — rocprofv3 kernel trace", "",
-                "Command (GPU box, repo root):", "", "    " + cmd, "",
+                "Command (on the GPU host, from the repository root):", "", "    " + cmd, "",
                 "Workload: the 2^20-particle clustered set (200 Plummer spheres + 30% "
                 "background), N_t = 64 +- 2; one call = keys + radix sort + permute + dense "
                 "cell table + density/h solve. `k_solve<1, ...>` is the FP32C solve, "
@@ -589,7 +589,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is "
-              "single-GPU in this build.", file=sys.stderr)
+              "single-GPU: one process drives one MI355X.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -15,7 +15,7 @@ def pytest_configure(config):
 
 def pytest_collection_modifyitems(config, items):
     # GPU tests are skipped (not failed) where no GPU is visible, so that a
-    # plain `pytest` on a CPU-only host stays green; `-m gpu` on a GPU machine runs them.
+    # plain `pytest` on a CPU-only host stays green; `-m gpu` on a GPU host runs them.
     try:
         import torch
         have_gpu = torch.cuda.is_available()
