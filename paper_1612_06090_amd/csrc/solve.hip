@@ -16,7 +16,7 @@
 //    by broadcast and tests it against its own h.  Tiles that straddle a
 //    large jump of the Morton curve are split in halves until the region is
 //    small.
-//  * The in-support test (Listing 1, line 3) is an exact r^2 < h^2 compare;
+//  * The in-support test of Listing 1 is an exact r^2 < h^2 compare;
 //    the kernel sums run only on in-range pairs.
 //  * h iteration: after each pass every lane updates its own h (safeguarded
 //    Newton on the weighted count, FP64); a ballot gives the lanes still
