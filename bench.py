@@ -270,6 +270,21 @@ def run_wendland(sph, torch, d, ps, steps):
     return out
 
 
+def kernel_ms(ev, p, call, steps):
+    """Mean time of the library's kernels over `steps` calls, from the hipEvent
+    pair each call records on its stream (params.prof_events)."""
+    pairs = [(ev.create(), ev.create()) for _ in range(steps)]
+    for a, b in pairs:
+        p.prof_events[0], p.prof_events[1] = a, b
+        call()
+    p.prof_events[0] = p.prof_events[1] = None
+    ms = float(np.mean([ev.elapsed_ms(a, b) for a, b in pairs]))
+    for a, b in pairs:
+        ev.hip.hipEventDestroy(a)
+        ev.hip.hipEventDestroy(b)
+    return ms
+
+
 def run_knn(sph, torch, d, ps, steps, dk=14.0):
     """The paper's own criterion at its scale: h = distance of the 295th
     nearest particle (itself first), Wendland C6, on the clustered 2^20 set
@@ -291,8 +306,26 @@ def run_knn(sph, torch, d, ps, steps, dk=14.0):
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
+        st = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws,
+                               stats=True)
+        torch.cuda.synchronize()
+        cands = int(st["stats"][1].item())
+        final_pairs = int(st["nngb"].to(torch.int64).sum().item())
+        kms = kernel_ms(HipEvents(), p, lambda: sph.density_solve(
+            d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws), steps)
+        # algorithmic work, a lower bound: every candidate test of the three
+        # stages, and the kernel terms of the evaluation stage only
+        form = "fp32c" if prec == sph.FP32C else "fp64"
+        flop = FLOP_CAND * cands + FLOP_PAIR[form] * final_pairs
+        peak = PEAK_FP32 if prec == sph.FP32C else PEAK_FP64
         out[name] = {"ms_per_step": ms, "particles_per_s": ps.n / (ms * 1e-3),
-                     "flagged": flagged, "max_count_updates": iters}
+                     "flagged": flagged, "max_count_updates": iters, "kernel_ms": kms,
+                     "candidates_per_step": cands, "final_pairs": final_pairs,
+                     "roofline": {"bound": "alu", "kernel": "k_solve (three exact-K stages)",
+                                  "achieved": flop / (kms * 1e-3) / 1e12,
+                                  "peak": peak / 1e12, "unit": "TFLOP/s",
+                                  "frac": flop / (kms * 1e-3) / peak,
+                                  "flop_per_launch": flop}}
     out["fp32c_speedup_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32c"]["ms_per_step"]
     return out
 
@@ -401,9 +434,18 @@ def run_force(sph, torch, d, ps, steps):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
+    kms = kernel_ms(HipEvents(), p, lambda: sph.pressure_force(
+        d["x"], d["y"], d["z"], d["m"], f["h"], f["rho"], P, p, ws=ws), steps)
+    pairs = int(f["nngb"].to(torch.int64).sum().item())
+    flop = FLOP_ADJ_PAIR * pairs
     return {"workload": "clustered2^20 FP32C, h and rho of a root-mode solve, P = A rho^(5/3); "
                         "sort + both walk passes + scaling per call",
-            "ms_per_call": ms, "particles_per_s": ps.n / (ms * 1e-3)}
+            "ms_per_call": ms, "particles_per_s": ps.n / (ms * 1e-3), "kernel_ms": kms,
+            "pairs": pairs,
+            "roofline": {"bound": "alu", "kernel": "k_adjoint (both passes)",
+                         "achieved": flop / (kms * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12,
+                         "unit": "TFLOP/s", "frac": flop / (kms * 1e-3) / PEAK_FP32,
+                         "flop_per_launch": flop}}
 
 
 def cpu_baseline(ps, budget_s=15.0):
