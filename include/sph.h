@@ -84,7 +84,11 @@ extern "C" {
                           N = #(r < h) into [K, K + n_tol] (n_tol an integer in
                           [0, 48]) and selecting the K-th smallest distance among
                           those N.  FP32C selects from binary32 coordinates with
-                          binary64 differences.  The selection keeps the 16, 32 or
+                          binary64 differences.  On a periodic set the count stage
+                          starts from h_init moved to within a factor 1.25 of a local
+                          estimate from the occupancy of the particle's Morton cell
+                          (the result does not depend on the start); isolated groups
+                          start from h_init.  The selection keeps the 16, 32 or
                           64 largest distances inside the count-stage h (for n_tol
                           up to 14, 30, 48); where ties make the count jump over the
                           band, the count stage hands over a bracket end holding up

@@ -930,6 +930,37 @@ static hipError_t launch_solve(const Plan &pl, SolveArgs &a, int seg, int64_t gr
     return hipGetLastError();
 }
 
+// Exact K, periodic set: the count stage's starting h.  The K-th distance does
+// not depend on where the iteration starts, so the caller's h_init is moved to
+// within a factor 1.25 of a local estimate: the occupancy of the particle's
+// Morton cell, from the dense-table level upwards until the cell holds at
+// least K/8 particles, taken as a number density, gives h = (3K/(4 pi n))^(1/3).
+// A uniform h_init is far too large inside clusters; this saves the count
+// stage its largest passes.
+__global__ void k_knn_start(int64_t n, const uint64_t *skeys, const int32_t *table, int Ld,
+                            int bits, double box, double K, const double4 *sp,
+                            const float4 *fp, double *sh0) {
+    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    // invalid particles (NaN position after the permute) keep their h_init
+    if (sp ? isnan(sp[s].x) : isnan(fp[s].x)) return;
+    const double h = sh0[s];
+    const uint64_t c = skeys[s] >> (3 * (bits - Ld));
+    int L = Ld;
+    int32_t cnt = 0;
+    for (;;) {
+        const int sh = 3 * (Ld - L);
+        const uint64_t a0 = (c >> sh) << sh;
+        cnt = table[a0 + ((uint64_t)1 << sh)] - table[a0];
+        if ((double)cnt >= 0.125 * K || L == 1) break;
+        --L;
+    }
+    const double side = ldexp(box, -L);
+    const double dens = (double)(cnt > 0 ? cnt : 1) / (side * side * side);
+    const double he = cbrt(3.0 * K / (4.0 * kPi * dens));
+    sh0[s] = fmin(fmax(h, 0.8 * he), 1.25 * he);
+}
+
 hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw,
                      int32_t *nngb, int32_t *status, uint64_t *stats, hipStream_t st) {
     SolveArgs a;
@@ -984,7 +1015,15 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
         // exact K: count band, selection of the K-th distance (its own tile
         // size), evaluation at that distance
         const int64_t full = (int64_t)256 * pl.prm.waves_per_cu;
-        e = launch_solve(pl, a, seg, pl.grid, 1, st);
+        if (!pl.grouped) {
+            hipLaunchKernelGGL(k_knn_start, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st,
+                               pl.n, pl.skeys, pl.table, pl.Ld, pl.bits, pl.prm.box,
+                               pl.prm.n_target,
+                               pl.prm.precision == SPH_FP32C ? nullptr : pl.sp,
+                               pl.prm.precision == SPH_FP32C ? pl.fp : nullptr, pl.sh0);
+            e = hipGetLastError();
+        }
+        if (e == hipSuccess) e = launch_solve(pl, a, seg, pl.grid, 1, st);
         if (e == hipSuccess && pl.grouped) {
             pl.prm.segment = kSelTile;
             e = run_group_items(pl, goff, st);

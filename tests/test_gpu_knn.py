@@ -193,10 +193,11 @@ def test_knn_clustered2p20_K295_wc6_sampled(dk):
 
 
 def test_knn_out_of_updates_flags_noconv():
-    # from a tiny h_init with one count update allowed, most particles never
-    # bracket the band: they are flagged NOCONV; the others are still exact
-    ps = sphgen.uniform(4096, seed=91)
-    h0 = np.full(ps.n, 1e-3)
+    # isolated groups (which start from the caller's h_init as given) from a
+    # tiny h_init with one count update allowed: most particles never bracket
+    # the band and are flagged NOCONV; the others are still exact
+    ps = sphgen.groups(20, seed=91, lo=200, hi=3000)
+    h0 = np.full(ps.n, 1e-6)
     g = gpu_solve(ps, h_init=h0, mode=KNN, n_target=64.0, n_tol=8.0, max_iter=1)
     o = oracle.knn(ps, 64)
     noconv = (g["status"] & sph.ST_NOCONV) != 0
