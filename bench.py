@@ -91,7 +91,8 @@ def run_form(sph, torch, d, ps, precision, steps, warmup, ev):
     return dict(ms_per_step=1e3 * wall / steps, kernel_ms=float(np.mean(kern_ms)),
                 pairs=int(st[0]), cands=int(st[1]), passes=int(st[2]),
                 final_pairs=int(nngb.astype(np.int64).sum()),
-                flagged=int(((status >> 16) != 0).sum()))
+                flagged=int(((status >> 16) != 0).sum()),
+                _rho=outs["rho"].cpu().numpy(), _h=outs["h"].cpu().numpy())
 
 
 # adjoint: per in-range pair, 20 FLOP in the coefficient pass (sqrt, q, f, f',
@@ -652,11 +653,13 @@ def main():
               flush=True)
         return
     f32 = run_form(sph, torch, d, ps, sph.FP32C, args.steps, args.warmup, ev)
-    print(f"[bench] fp32c {f32}", file=sys.stderr, flush=True)
+    print(f"[bench] fp32c { {k: v for k, v in f32.items() if k[0] != '_'} }", file=sys.stderr,
+          flush=True)
     f64 = None
     if not args.no_fp64:
         f64 = run_form(sph, torch, d, ps, sph.FP64, max(3, args.steps // 2), 1, ev)
-        print(f"[bench] fp64 {f64}", file=sys.stderr, flush=True)
+        print(f"[bench] fp64 { {k: v for k, v in f64.items() if k[0] != '_'} }",
+              file=sys.stderr, flush=True)
 
     srt = run_sort(sph, torch, d, ps, max(3, args.steps))
     print(f"[bench] sort {srt}", file=sys.stderr, flush=True)
@@ -738,6 +741,15 @@ def main():
             "roofline": roof(f64, "fp64"),
         }
         line["fp32c_speedup_over_fp64"] = f64["ms_per_step"] / f32["ms_per_step"]
+        # per-particle error of the FP32C form; the FP64 path is the oracle's to 1e-12
+        drho = np.abs(f32["_rho"] - f64["_rho"]) / f64["_rho"]
+        dh = np.abs(f32["_h"] - f64["_h"]) / f64["_h"]
+        line["fp32c_error_vs_fp64"] = {
+            "rho_rel_max": float(drho.max()), "rho_rel_p99": float(np.quantile(drho, 0.99)),
+            "h_rel_max": float(dh.max()), "h_rel_p99": float(np.quantile(dh, 0.99)),
+            "frac_h_rel_le_1e-5": float((dh <= 1e-5).mean()),
+            # particles whose iteration stopped at another h inside the band
+            "band_flips": int((dh > 1e-5).sum())}
     line["sort"] = srt
     if bat is not None:
         line["batched"] = bat
