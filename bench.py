@@ -469,8 +469,9 @@ def cpu_baseline(ps, budget_s=15.0):
     dt = time.perf_counter() - t0
     pairs = int(r["pairs"].sum())
     return {"value": pairs / dt, "unit": "interactions/s", "cores": cores, "kind": "oracle",
-            "sample": f"{k} particles drawn uniformly from the {ps.n}-particle clustered set, "
-                      f"each solved to convergence against the full set (FP64 k-d tree, "
+            "sample": (f"all {k} particles of the clustered set" if k == ps.n else
+                       f"{k} particles drawn uniformly from the {ps.n}-particle clustered set")
+                      + f", each solved to convergence against the full set (FP64 k-d tree, "
                       f"{dt:.1f} s incl. tree build); particles/s = {k / dt:.4g}",
             "particles_per_s": k / dt}
 
