@@ -31,8 +31,12 @@ sys.path.insert(0, ROOT)
 METRIC = "particle-neighbour interactions/s and particles/s for density+h solve, FP32 vs FP64"
 PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed) FLOP/s
 PEAK_FP64 = 78.6e12    # MI355X vector FP64 FLOP/s
-FLOP_CAND = 8.0        # 3 differences + r^2 (two FMA) + compare
-FLOP_PAIR = {"fp32c": 31.0, "fp64": 22.0}
+FLOP_CAND = 8.0        # 3 differences + r^2 (one multiply, two FMA; FMA = 2)
+# per in-range pair, M4, the same in both forms: q^2 (or q = sqrt(r^2) / h) 2,
+# the branch-free spline's f and q f' 11, three sums 4 (one FMA).  The binary32
+# form sums up to 64 terms per lane plainly and folds them into Kahan-compensated
+# totals once per chunk round, so its compensation costs no FLOP per pair.
+FLOP_PAIR = {"fp32c": 17.0, "fp64": 17.0}
 
 
 class HipEvents:
@@ -555,6 +559,62 @@ def summarize_traffic(fetch_csv, write_csv, cmd):
                                           "copy_calibration")}))
 
 
+VALU_JSON = os.path.join(ROOT, "profiles", "k_solve_clustered2p20_valu.txt")
+# wave-instruction counters -> operations on all 64 lanes (FMA = 2), masked lanes included
+VALU_WEIGHTS = {"f32": {"SQ_INSTS_VALU_ADD_F32": 1, "SQ_INSTS_VALU_MUL_F32": 1,
+                        "SQ_INSTS_VALU_FMA_F32": 2, "SQ_INSTS_VALU_TRANS_F32": 1},
+                "f64": {"SQ_INSTS_VALU_ADD_F64": 1, "SQ_INSTS_VALU_MUL_F64": 1,
+                        "SQ_INSTS_VALU_FMA_F64": 2, "SQ_INSTS_VALU_TRANS_F64": 1}}
+
+
+def summarize_valu(cmd, *csvs):
+    """Executed VALU work per k_solve launch from SQ instruction counters taken
+    over several --pmc passes of the same profile run: per-dispatch sums over
+    the counter's instances, averaged over the solve dispatches."""
+    import csv
+    per = {}
+    for path in csvs:
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if "k_solve" not in r["Kernel_Name"]:
+                continue
+            key = (r["Counter_Name"], r["Dispatch_Id"])
+            acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+        for (name, _), v in acc.items():
+            per.setdefault(name, []).append(v)
+    mean = {k: float(np.mean(v)) for k, v in sorted(per.items())}
+    flop = {t: 64.0 * sum(w * mean.get(c, 0.0) for c, w in ws.items())
+            for t, ws in VALU_WEIGHTS.items()}
+    out = {"kernel": "k_solve (FP32C, 16-particle tiles)", "workload": "clustered2^20",
+           "solve_hip_sha256": solve_source_sha(),
+           "executed_f32_flop_per_launch": flop["f32"],
+           "executed_f64_flop_per_launch": flop["f64"],
+           "counters_per_launch": mean,
+           "dispatches": {k: len(v) for k, v in sorted(per.items())},
+           "note": "SQ_INSTS_VALU_* count wave instructions; FLOP = 64 lanes x (ADD + MUL + "
+                   "TRANS + 2 FMA), lanes masked off included",
+           "command": cmd}
+    if mean.get("SQ_ACTIVE_INST_VALU"):
+        out["thread_cycles_per_valu_cycle_raw"] = (mean.get("SQ_THREAD_CYCLES_VALU", 0.0) /
+                                                   mean["SQ_ACTIVE_INST_VALU"])
+    os.makedirs(os.path.dirname(VALU_JSON), exist_ok=True)
+    json.dump(out, open(VALU_JSON, "w"), indent=1)
+    print(json.dumps({k: out[k] for k in ("executed_f32_flop_per_launch",
+                                          "executed_f64_flop_per_launch", "dispatches")}))
+
+
+def measured_valu():
+    """Executed binary32 VALU FLOP per k_solve launch from the committed counter
+    summary, or None when the kernel source changed since it was taken."""
+    try:
+        d = json.load(open(VALU_JSON))
+    except (OSError, ValueError):
+        return None
+    if d.get("solve_hip_sha256") != solve_source_sha():
+        return None
+    return d.get("executed_f32_flop_per_launch")
+
+
 TRACE_MD = os.path.join(ROOT, "profiles", "k_solve_clustered2p20_kernel_trace.md")
 TRACE_KNN_MD = os.path.join(ROOT, "profiles", "k_solve_exactK295_clustered2p20_kernel_trace.md")
 
@@ -619,6 +679,9 @@ def main():
                          "from rocprofv3 --stats output")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
                     help="write the k_solve traffic summary from two --pmc runs")
+    ap.add_argument("--summarize-valu", nargs="+", metavar="ARG",
+                    help="CMD CSV [CSV ...]: write the k_solve executed-VALU summary from "
+                         "--pmc runs of SQ instruction counters")
     args = ap.parse_args()
     if args.summarize_trace:
         if len(args.summarize_trace) not in (2, 3):
@@ -627,6 +690,11 @@ def main():
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic)
+        return
+    if args.summarize_valu:
+        if len(args.summarize_valu) < 2:
+            ap.error("--summarize-valu takes CMD CSV [CSV ...]")
+        summarize_valu(*args.summarize_valu)
         return
     if args.profile_run:
         profile_run(args.steps)
@@ -704,9 +772,18 @@ def main():
         ach = flop / (r["kernel_ms"] * 1e-3)
         peak = PEAK_FP32 if form == "fp32c" else PEAK_FP64
         tr = measured_traffic() if form == "fp32c" else None
-        return {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                "frac": ach / peak, "traffic": tr, "kernel": "k_solve",
-                "kernel_ms": r["kernel_ms"], "flop_per_launch": flop}
+        out = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+               "frac": ach / peak, "traffic": tr, "kernel": "k_solve",
+               "kernel_ms": r["kernel_ms"], "flop_per_launch": flop}
+        if form == "fp32c":
+            # counter-measured binary32 VALU work of the same launch (all 64 lanes of
+            # every issued instruction, masked lanes included), at this run's kernel time
+            ex = measured_valu()
+            out["executed"] = None if ex is None else {
+                "flop_per_launch": ex, "achieved": ex / (r["kernel_ms"] * 1e-3) / 1e12,
+                "frac": ex / (r["kernel_ms"] * 1e-3) / peak,
+                "algorithmic_over_executed": flop / ex}
+        return out
 
     value = f32["pairs"] / (f32["ms_per_step"] * 1e-3)
     line = {
