@@ -242,6 +242,11 @@ def run_large(sph, torch, steps):
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
     srt = run_sort(sph, torch, d, ps, steps)
+    tr = measured_sort_traffic()
+    srt["traffic"] = tr
+    if tr is not None:
+        # HBM bytes the counters saw per call, over the same call time
+        srt["traffic_GBps"] = tr / (srt["ms_per_call"] * 1e-3) / 1e9
     return {"workload": "clustered2^24: 2^24 particles, 2000 Plummer spheres (contrast <= 1e5) "
                         "+ 30% background, N_t = 64 +- 1, FP32C, full sort every call",
             "n": n, "ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
@@ -615,6 +620,91 @@ def measured_valu():
     return d.get("executed_f32_flop_per_launch")
 
 
+SORT_SRC = os.path.join(ROOT, "paper_1612_06090_amd", "csrc", "sort.hip")
+SORT_TRAFFIC_JSON = os.path.join(ROOT, "profiles", "sph_sort_clustered2p24_traffic.txt")
+
+
+def sort_source_sha():
+    import hashlib
+    return hashlib.sha256(open(SORT_SRC, "rb").read()).hexdigest()
+
+
+def profile_sort_run(steps):
+    """sph_sort calls on the clustered 2^24 set (as the large leg times them)
+    plus one plain copy of COPY_MIB MiB (the counter calibration)."""
+    import torch
+    import paper_1612_06090_amd as sph
+    import sphgen
+    ps = sphgen.config("clustered2^24")
+    d = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+         for k in ("x", "y", "z")}
+    p = sph.default_params(periodic=1, box=ps.box)
+    for _ in range(steps):
+        sph.sort(d["x"], d["y"], d["z"], p)
+    src = torch.ones(COPY_MIB << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"[bench] sort profile run: {steps} sorts of {ps.n} + one {COPY_MIB} MiB copy",
+          flush=True)
+
+
+def summarize_sort_traffic(fetch_csv, write_csv, cmd, steps="2"):
+    """HBM bytes per sph_sort call at 2^24 from FETCH_SIZE / WRITE_SIZE (KiB
+    per dispatch) over the library's dispatches, each counter scaled by its
+    reading on the calibration copy; per kernel and in total."""
+    import csv
+    steps = int(steps)
+
+    def read(path, counter):
+        lib, other = {}, []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"]) * 1024.0
+            name = r["Kernel_Name"]
+            if "sph::" in name:
+                short = name.split("sph::", 1)[1].split("(", 1)[0]
+                lib[short] = lib.get(short, 0.0) + v
+            else:
+                other.append(v)
+        return lib, max(other)
+
+    lf, cf = read(fetch_csv, "FETCH_SIZE")
+    lw, cw = read(write_csv, "WRITE_SIZE")
+    nbytes = float(COPY_MIB << 20)
+    kf, kw = cf / nbytes, cw / nbytes
+    n = 1 << 24
+    per_kernel = {k: {"fetch": lf.get(k, 0.0) / kf / steps, "write": lw.get(k, 0.0) / kw / steps}
+                  for k in sorted(set(lf) | set(lw))}
+    fetch = sum(v["fetch"] for v in per_kernel.values())
+    write = sum(v["write"] for v in per_kernel.values())
+    out = {"call": "sph_sort (keys, radix passes, permutation, cell table)",
+           "workload": "clustered2^24", "n": n, "sort_hip_sha256": sort_source_sha(),
+           "fetch_bytes_per_call": fetch, "write_bytes_per_call": write,
+           "bytes_per_call": fetch + write, "bytes_per_particle": (fetch + write) / n,
+           "algorithmic_bytes_per_particle": SORT_BYTES_PER_PARTICLE,
+           "per_kernel_bytes_per_call": per_kernel,
+           "copy_calibration": {"bytes": nbytes, "fetch_factor": kf, "write_factor": kw},
+           "calls": steps, "command": cmd}
+    os.makedirs(os.path.dirname(SORT_TRAFFIC_JSON), exist_ok=True)
+    json.dump(out, open(SORT_TRAFFIC_JSON, "w"), indent=1)
+    print(json.dumps({k: out[k] for k in ("bytes_per_call", "bytes_per_particle",
+                                          "copy_calibration")}))
+
+
+def measured_sort_traffic():
+    """HBM bytes per sph_sort call at 2^24 from the committed counter summary,
+    or None when the sort source changed since the counters were taken."""
+    try:
+        d = json.load(open(SORT_TRAFFIC_JSON))
+    except (OSError, ValueError):
+        return None
+    if d.get("sort_hip_sha256") != sort_source_sha():
+        return None
+    return d.get("bytes_per_call")
+
+
 TRACE_MD = os.path.join(ROOT, "profiles", "k_solve_clustered2p20_kernel_trace.md")
 TRACE_KNN_MD = os.path.join(ROOT, "profiles", "k_solve_exactK295_clustered2p20_kernel_trace.md")
 
@@ -674,6 +764,10 @@ def main():
                     help="only the exact-K leg (for a kernel trace of its stages)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--profile-sort", action="store_true",
+                    help="only sph_sort calls at 2^24 + a calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--summarize-sort-traffic", nargs="+", metavar="ARG",
+                    help="FETCH_CSV WRITE_CSV CMD [CALLS]: write the sph_sort traffic summary")
     ap.add_argument("--summarize-trace", nargs="+", metavar="ARG",
                     help="STATS_CSV CMD [headline|knn]: write the kernel-trace summary "
                          "from rocprofv3 --stats output")
@@ -696,8 +790,16 @@ def main():
             ap.error("--summarize-valu takes CMD CSV [CSV ...]")
         summarize_valu(*args.summarize_valu)
         return
+    if args.summarize_sort_traffic:
+        if len(args.summarize_sort_traffic) not in (3, 4):
+            ap.error("--summarize-sort-traffic takes FETCH_CSV WRITE_CSV CMD [CALLS]")
+        summarize_sort_traffic(*args.summarize_sort_traffic)
+        return
     if args.profile_run:
         profile_run(args.steps)
+        return
+    if args.profile_sort:
+        profile_sort_run(args.steps)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is "
