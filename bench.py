@@ -477,7 +477,16 @@ def cpu_baseline(ps, budget_s=15.0):
     r = oracle.solve(ps, subset=sub)
     dt = time.perf_counter() - t0
     pairs = int(r["pairs"].sum())
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": pairs / dt, "unit": "interactions/s", "cores": cores, "kind": "oracle",
+            "cpu_model": model, "host_cpus": os.cpu_count(),
             "sample": (f"all {k} particles of the clustered set" if k == ps.n else
                        f"{k} particles drawn uniformly from the {ps.n}-particle clustered set")
                       + f", each solved to convergence against the full set (FP64 k-d tree, "
