@@ -37,6 +37,9 @@ FLOP_CAND = 8.0        # 3 differences + r^2 (one multiply, two FMA; FMA = 2)
 # form sums up to 64 terms per lane plainly and folds them into Kahan-compensated
 # totals once per chunk round, so its compensation costs no FLOP per pair.
 FLOP_PAIR = {"fp32c": 17.0, "fp64": 17.0}
+# Wendland C6: q^2 and q 2 (FP32C) or 3 (FP64: sqrt, 1/h, q^2), the two
+# polynomials and powers of (1 - q) 19, three sums 4
+FLOP_PAIR_WC6 = {"fp32c": 25.0, "fp64": 26.0}
 
 
 class HipEvents:
@@ -254,9 +257,10 @@ def run_large(sph, torch, steps):
             "sort": srt}
 
 
-def run_wendland(sph, torch, d, ps, steps):
+def run_wendland(sph, torch, d, ps, steps, ev):
     """The paper's kernel at the paper's scale: Wendland C6 with N_t = 295 +- 2
-    on the clustered 2^20 set (FP32C and FP64), sort + solve per step."""
+    on the clustered 2^20 set (FP32C and FP64), sort + solve per step; the
+    roofline of its k_solve launch from the kernel's own counts."""
     out = {"workload": "clustered2^20, Wendland C6 kernel, N_t = 295 +- 2, h_init = 2 N^-1/3"}
     for prec, name in ((sph.FP32C, "fp32c"), (sph.FP64, "fp64")):
         p = sph.default_params(periodic=1, box=ps.box, n_target=295.0, n_tol=2.0,
@@ -273,9 +277,18 @@ def run_wendland(sph, torch, d, ps, steps):
         b.record()
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
+        cands = int(o["stats"][1].item())
+        kms = kernel_ms(ev, p, lambda: sph.density_solve(d["x"], d["y"], d["z"], d["m"],
+                                                         d["h_init"], p, ws=ws), steps)
+        flop = FLOP_CAND * cands + FLOP_PAIR_WC6[name] * pairs
+        peak = PEAK_FP32 if name == "fp32c" else PEAK_FP64
         out[name] = {"ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
                      "particles_per_s": ps.n / (ms * 1e-3), "pairs_per_step": pairs,
-                     "flagged": flagged}
+                     "candidates_per_step": cands, "flagged": flagged, "kernel_ms": kms,
+                     "roofline": {"bound": "alu", "kernel": "k_solve",
+                                  "achieved": flop / (kms * 1e-3) / 1e12,
+                                  "peak": peak / 1e12, "unit": "TFLOP/s",
+                                  "frac": flop / (kms * 1e-3) / peak, "flop_per_launch": flop}}
     out["fp32c_speedup_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32c"]["ms_per_step"]
     return out
 
@@ -324,9 +337,9 @@ def run_knn(sph, torch, d, ps, steps, dk=14.0):
         kms = kernel_ms(HipEvents(), p, lambda: sph.density_solve(
             d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws), steps)
         # algorithmic work, a lower bound: every candidate test of the three
-        # stages, and the kernel terms of the evaluation stage only
+        # stages, and the Wendland C6 pair terms of the evaluation stage only
         form = "fp32c" if prec == sph.FP32C else "fp64"
-        flop = FLOP_CAND * cands + FLOP_PAIR[form] * final_pairs
+        flop = FLOP_CAND * cands + FLOP_PAIR_WC6[form] * final_pairs
         peak = PEAK_FP32 if prec == sph.FP32C else PEAK_FP64
         out[name] = {"ms_per_step": ms, "particles_per_s": ps.n / (ms * 1e-3),
                      "flagged": flagged, "max_count_updates": iters, "kernel_ms": kms,
@@ -855,7 +868,7 @@ def main():
 
     wc6 = None
     if not args.no_wendland:
-        wc6 = run_wendland(sph, torch, d, ps, max(3, args.steps // 2))
+        wc6 = run_wendland(sph, torch, d, ps, max(3, args.steps // 2), ev)
         print(f"[bench] wendland {wc6}", file=sys.stderr, flush=True)
     scat = None
     if not args.no_scatter:
