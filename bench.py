@@ -109,6 +109,16 @@ FLOP_ADJ_PAIR = 60.0
 SORT_BYTES_PER_PARTICLE = 300.0   # keys 36, 8 radix passes 192, histograms 8, permute 64
 
 
+def _executed(ex, flop, kms):
+    """Counter-measured binary32 VALU work of a unit (all 64 lanes of every
+    issued instruction) at this run's kernel time, beside the algorithmic
+    count; None without a summary for the current source."""
+    if ex is None:
+        return None
+    return {"flop_per_launch": ex, "achieved": ex / (kms * 1e-3) / 1e12,
+            "frac": ex / (kms * 1e-3) / PEAK_FP32, "algorithmic_over_executed": flop / ex}
+
+
 def run_adjoint(sph, torch, d, ps, steps, warmup, ev):
     """FP32C root-mode solve, then the adjoint under a Gaussian cotangent on rho."""
     p = sph.default_params(periodic=1, box=ps.box, n_target=ps.n_target, n_tol=ps.n_tol,
@@ -148,7 +158,8 @@ def run_adjoint(sph, torch, d, ps, steps, warmup, ev):
             "pairs": pairs, "forward_flagged": flagged,
             "roofline": {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_FP32 / 1e12,
                          "unit": "TFLOP/s", "frac": ach / PEAK_FP32,
-                         "kernel": "k_adjoint (both passes)", "flop_per_launch": flop}}
+                         "kernel": "k_adjoint (both passes)", "flop_per_launch": flop,
+                         "executed": _executed(measured_valu("k_adjoint"), flop, kern)}}
 
 
 def run_sort(sph, torch, d, ps, steps):
@@ -547,6 +558,25 @@ def profile_run(steps):
     print(f"[bench] profile run: {steps} solves + one {COPY_MIB} MiB copy", flush=True)
 
 
+def profile_adjoint_run(steps):
+    """A root-mode FP32C solve of the clustered 2^20 set, then `steps` adjoint
+    calls with the benchmark's cotangent (for rocprofv3 --pmc)."""
+    import torch
+    import paper_1612_06090_amd as sph
+    import sphgen
+    ps = sphgen.config("clustered2^20")
+    d = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
+         for k in ("x", "y", "z", "m", "h_init")}
+    p = sph.default_params(periodic=1, box=ps.box, n_target=ps.n_target, n_tol=ps.n_tol,
+                           precision=sph.FP32C, mode=sph.ROOT, root_tol=1e-6)
+    fw = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p)
+    gr = torch.tensor(sphgen.cotangent(ps.n, 5), dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        sph.density_backward(d["x"], d["y"], d["z"], d["m"], fw["h"], gr, None, p)
+    torch.cuda.synchronize()
+    print(f"[bench] adjoint profile run: one solve + {steps} adjoint calls", flush=True)
+
+
 def summarize_traffic(fetch_csv, write_csv, cmd):
     """Per-launch k_solve HBM traffic from FETCH_SIZE / WRITE_SIZE (KiB per
     dispatch), each scaled by the same counter on the calibration copy."""
@@ -594,26 +624,46 @@ VALU_WEIGHTS = {"f32": {"SQ_INSTS_VALU_ADD_F32": 1, "SQ_INSTS_VALU_MUL_F32": 1,
                         "SQ_INSTS_VALU_FMA_F64": 2, "SQ_INSTS_VALU_TRANS_F64": 1}}
 
 
-def summarize_valu(cmd, *csvs):
-    """Executed VALU work per k_solve launch from SQ instruction counters taken
-    over several --pmc passes of the same profile run: per-dispatch sums over
-    the counter's instances, averaged over the solve dispatches."""
+VALU_TARGETS = {
+    # kernel -> (summary file, source it is tied to, what one unit is)
+    "k_solve": (VALU_JSON, SOLVE_SRC, "launch"),
+    "k_adjoint": (os.path.join(ROOT, "profiles", "k_adjoint_clustered2p20_valu.txt"),
+                  os.path.join(ROOT, "paper_1612_06090_amd", "csrc", "backward.hip"),
+                  "backward call (both passes)"),
+}
+
+
+def summarize_valu(cmd, *csvs, kernel="k_solve", calls=None):
+    """Executed VALU work of one kernel from SQ instruction counters taken over
+    several --pmc passes of the same profile run: per-dispatch sums over the
+    counter's instances, then the mean per dispatch (or, given `calls`, the
+    total over all dispatches divided by the number of calls)."""
     import csv
+    import hashlib
+    out_path, src, unit = VALU_TARGETS[kernel]
+    if kernel == "k_solve":
+        out_path = VALU_JSON
     per = {}
     for path in csvs:
         acc = {}
         for r in csv.DictReader(open(path)):
-            if "k_solve" not in r["Kernel_Name"]:
+            if kernel not in r["Kernel_Name"]:
                 continue
             key = (r["Counter_Name"], r["Dispatch_Id"])
             acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
         for (name, _), v in acc.items():
             per.setdefault(name, []).append(v)
-    mean = {k: float(np.mean(v)) for k, v in sorted(per.items())}
+    if calls is None:
+        mean = {k: float(np.mean(v)) for k, v in sorted(per.items())}
+    else:
+        mean = {k: float(np.sum(v)) / int(calls) for k, v in sorted(per.items())}
     flop = {t: 64.0 * sum(w * mean.get(c, 0.0) for c, w in ws.items())
             for t, ws in VALU_WEIGHTS.items()}
-    out = {"kernel": "k_solve (FP32C, 16-particle tiles)", "workload": "clustered2^20",
-           "solve_hip_sha256": solve_source_sha(),
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    out = {"kernel": ("k_solve (FP32C, 16-particle tiles)" if kernel == "k_solve"
+                      else f"{kernel} (FP32C)"),
+           "workload": "clustered2^20", "unit": unit,
+           ("solve_hip_sha256" if kernel == "k_solve" else "source_sha256"): sha,
            "executed_f32_flop_per_launch": flop["f32"],
            "executed_f64_flop_per_launch": flop["f64"],
            "counters_per_launch": mean,
@@ -624,20 +674,27 @@ def summarize_valu(cmd, *csvs):
     if mean.get("SQ_ACTIVE_INST_VALU"):
         out["thread_cycles_per_valu_cycle_raw"] = (mean.get("SQ_THREAD_CYCLES_VALU", 0.0) /
                                                    mean["SQ_ACTIVE_INST_VALU"])
-    os.makedirs(os.path.dirname(VALU_JSON), exist_ok=True)
-    json.dump(out, open(VALU_JSON, "w"), indent=1)
+    os.makedirs(os.path.dirname(out_path), exist_ok=True)
+    json.dump(out, open(out_path, "w"), indent=1)
     print(json.dumps({k: out[k] for k in ("executed_f32_flop_per_launch",
                                           "executed_f64_flop_per_launch", "dispatches")}))
 
 
-def measured_valu():
-    """Executed binary32 VALU FLOP per k_solve launch from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+def measured_valu(kernel="k_solve"):
+    """Executed binary32 VALU FLOP per unit (a k_solve launch, a backward call)
+    from the committed counter summary, or None when the kernel source changed
+    since it was taken."""
+    import hashlib
+    path, src, _ = VALU_TARGETS[kernel]
+    if kernel == "k_solve":
+        path, key = VALU_JSON, "solve_hip_sha256"
+    else:
+        key = "source_sha256"
     try:
-        d = json.load(open(VALU_JSON))
+        d = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if d.get("solve_hip_sha256") != solve_source_sha():
+    if d.get(key) != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
     return d.get("executed_f32_flop_per_launch")
 
@@ -796,8 +853,13 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
                     help="write the k_solve traffic summary from two --pmc runs")
     ap.add_argument("--summarize-valu", nargs="+", metavar="ARG",
-                    help="CMD CSV [CSV ...]: write the k_solve executed-VALU summary from "
-                         "--pmc runs of SQ instruction counters")
+                    help="CMD CSV [CSV ...]: write the executed-VALU summary of --valu-kernel "
+                         "from --pmc runs of SQ instruction counters")
+    ap.add_argument("--valu-kernel", default="k_solve", choices=sorted(VALU_TARGETS))
+    ap.add_argument("--valu-calls", type=int, default=None,
+                    help="report totals per call over this many calls (default: per dispatch)")
+    ap.add_argument("--profile-adjoint", action="store_true",
+                    help="only one solve + adjoint calls (for rocprofv3 --pmc)")
     args = ap.parse_args()
     if args.summarize_trace:
         if len(args.summarize_trace) not in (2, 3):
@@ -810,7 +872,7 @@ def main():
     if args.summarize_valu:
         if len(args.summarize_valu) < 2:
             ap.error("--summarize-valu takes CMD CSV [CSV ...]")
-        summarize_valu(*args.summarize_valu)
+        summarize_valu(*args.summarize_valu, kernel=args.valu_kernel, calls=args.valu_calls)
         return
     if args.summarize_sort_traffic:
         if len(args.summarize_sort_traffic) not in (3, 4):
@@ -822,6 +884,9 @@ def main():
         return
     if args.profile_sort:
         profile_sort_run(args.steps)
+        return
+    if args.profile_adjoint:
+        profile_adjoint_run(args.steps)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path is "
@@ -902,11 +967,7 @@ def main():
         if form == "fp32c":
             # counter-measured binary32 VALU work of the same launch (all 64 lanes of
             # every issued instruction, masked lanes included), at this run's kernel time
-            ex = measured_valu()
-            out["executed"] = None if ex is None else {
-                "flop_per_launch": ex, "achieved": ex / (r["kernel_ms"] * 1e-3) / 1e12,
-                "frac": ex / (r["kernel_ms"] * 1e-3) / peak,
-                "algorithmic_over_executed": flop / ex}
+            out["executed"] = _executed(measured_valu(), flop, r["kernel_ms"])
         return out
 
     value = f32["pairs"] / (f32["ms_per_step"] * 1e-3)

@@ -102,3 +102,19 @@ def test_solve_traffic_summary(tmp_path, monkeypatch):
                                   (3, "__amd_rocclr_copyBuffer", "WRITE_SIZE", nbytes / 1024)])
     bench.summarize_traffic(f, w, "cmd")
     assert bench.measured_traffic() == pytest.approx(5e8 + 1e8)
+
+
+def test_valu_summary_per_call(tmp_path, monkeypatch):
+    # the adjoint: two dispatches per call, totals reported per call
+    path = str(tmp_path / "adj.txt")
+    _, src, unit = bench.VALU_TARGETS["k_adjoint"]
+    monkeypatch.setitem(bench.VALU_TARGETS, "k_adjoint", (path, src, unit))
+    adj = "void sph::k_adjoint<1, false, 0>(sph::AdjArgs)"
+    rows = [(d, adj, "SQ_INSTS_VALU_FMA_F32", 10.0 * d) for d in (1, 2, 3, 4)]
+    a = _csv(tmp_path / "a.csv", rows + [(5, SOLVE, "SQ_INSTS_VALU_FMA_F32", 1e6)])
+    bench.summarize_valu("cmd", a, kernel="k_adjoint", calls=2)
+    d = json.load(open(path))
+    assert d["executed_f32_flop_per_launch"] == pytest.approx(64 * 2 * 100.0 / 2)
+    assert bench.measured_valu("k_adjoint") == d["executed_f32_flop_per_launch"]
+    ex = bench._executed(d["executed_f32_flop_per_launch"], 1600.0, 2.0)
+    assert ex["algorithmic_over_executed"] == pytest.approx(0.25)
