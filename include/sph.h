@@ -166,7 +166,10 @@ void sph_default_params(sph_params *p);
 
 /* Host only.  Bytes of workspace needed by sph_sort, sph_density_solve and
  * sph_density_backward for n particles in n_groups groups (0 = one periodic
- * set).  The size is monotone in n.  Returns SPH_OK or SPH_E_INVALID. */
+ * set).  The size is monotone in n.  Every entry point accepts 0 <= n <
+ * 2^31 - 1 (sorted indices are 32-bit) and 1 <= n_groups <= 65535 for
+ * isolated groups (n_groups = 0 for a periodic set); other sizes give
+ * SPH_E_INVALID.  Returns SPH_OK or SPH_E_INVALID. */
 int sph_workspace_size(const sph_params *params, int64_t n, int32_t n_groups, size_t *bytes);
 
 /* The spatial sort that precedes the density loop (no counterpart in the

@@ -238,3 +238,19 @@ def test_autotune_host_checks():
     assert (best.segment, best.waves_per_cu, best.tile_cell) == (p.segment, p.waves_per_cu,
                                                                   p.tile_cell)
     assert ms.value == 0.0
+
+
+def test_size_limits():
+    # particle counts below 2^31 - 1 (32-bit sorted indices), group counts in
+    # [1, 65535] for isolated groups and none for a periodic set
+    lib = _lib()
+    out = C.c_size_t(0)
+    p = sph.default_params()
+    for n, ok in ((0, True), ((1 << 31) - 2, True), ((1 << 31) - 1, False), (-1, False)):
+        rc = lib.sph_workspace_size(C.byref(p), n, 0, C.byref(out))
+        assert rc == (sph.OK if ok else sph.E_INVALID), n
+    assert lib.sph_workspace_size(C.byref(p), 100, 3, C.byref(out)) == sph.E_INVALID
+    g = sph.default_params(periodic=0, n_target=32.0, n_tol=1.0)
+    for G, ok in ((1, True), (65535, True), (0, False), (65536, False)):
+        rc = lib.sph_workspace_size(C.byref(g), 1000, G, C.byref(out))
+        assert rc == (sph.OK if ok else sph.E_INVALID), G
