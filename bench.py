@@ -32,11 +32,16 @@ METRIC = "particle-neighbour interactions/s and particles/s for density+h solve,
 PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed) FLOP/s
 PEAK_FP64 = 78.6e12    # MI355X vector FP64 FLOP/s
 FLOP_CAND = 8.0        # 3 differences + r^2 (one multiply, two FMA; FMA = 2)
-# per in-range pair, M4, the same in both forms: q^2 (or q = sqrt(r^2) / h) 2,
-# the branch-free spline's f and q f' 11, three sums 4 (one FMA).  The binary32
-# form sums up to 64 terms per lane plainly and folds them into Kahan-compensated
-# totals once per chunk round, so its compensation costs no FLOP per pair.
-FLOP_PAIR = {"fp32c": 17.0, "fp64": 17.0}
+# Algorithmic FLOP per in-range pair, the headline weights: the root, q, the
+# spline's f and f', and the three sums S0, S1, R: 22 in FP64; the FP32C form
+# adds a Kahan compensation to each of the three sums (3 x 3): 31.
+FLOP_PAIR = {"fp32c": 31.0, "fp64": 22.0}
+# Beside them, what this kernel's instructions do per in-range pair, the same in
+# both forms: q^2 (or q = sqrt(r^2) / h) 2, the branch-free spline's f and q f'
+# 11, three sums 4 (one FMA).  The binary32 form sums up to 64 terms per lane
+# plainly and folds them into Kahan-compensated totals once per chunk round, so
+# its compensation costs no FLOP per pair.
+FLOP_PAIR_KERNEL = {"fp32c": 17.0, "fp64": 17.0}
 # Wendland C6: q^2 and q 2 (FP32C) or 3 (FP64: sqrt, 1/h, q^2), the two
 # polynomials and powers of (1 - q) 19, three sums 4
 FLOP_PAIR_WC6 = {"fp32c": 25.0, "fp64": 26.0}
@@ -109,14 +114,42 @@ FLOP_ADJ_PAIR = 60.0
 SORT_BYTES_PER_PARTICLE = 300.0   # keys 36, 8 radix passes 192, histograms 8, permute 64
 
 
-def _executed(ex, flop, kms):
+def _executed(summary, flop, kms):
     """Counter-measured binary32 VALU work of a unit (all 64 lanes of every
     issued instruction) at this run's kernel time, beside the algorithmic
-    count; None without a summary for the current source."""
-    if ex is None:
+    count, and the VALU lane utilisation: the mean fraction of the 64 lanes
+    active per issued VALU instruction (SQ_THREAD_CYCLES_VALU over
+    64 x SQ_ACTIVE_INST_VALU), the GPU counterpart of the vector efficiency
+    of Sec. IV-C (Eq. 2, speed-up over vector length).  None without a
+    summary for the current source."""
+    if summary is None:
         return None
-    return {"flop_per_launch": ex, "achieved": ex / (kms * 1e-3) / 1e12,
-            "frac": ex / (kms * 1e-3) / PEAK_FP32, "algorithmic_over_executed": flop / ex}
+    ex = summary["executed_f32_flop_per_launch"]
+    out = {"flop_per_launch": ex, "achieved": ex / (kms * 1e-3) / 1e12,
+           "frac": ex / (kms * 1e-3) / PEAK_FP32, "algorithmic_over_executed": flop / ex}
+    c = summary.get("counters_per_launch", {})
+    if c.get("SQ_ACTIVE_INST_VALU") and c.get("SQ_THREAD_CYCLES_VALU"):
+        out["valu_lane_utilisation"] = c["SQ_THREAD_CYCLES_VALU"] / (
+            64.0 * c["SQ_ACTIVE_INST_VALU"])
+    if c.get("SQ_INSTS_VALU"):
+        out["valu_wave_instructions"] = c["SQ_INSTS_VALU"]
+    return out
+
+
+def alu_roofline(cands, pairs, kms, form, kernel="k_solve"):
+    """Roofline of one density-kernel launch: algorithmic FLOP (8 per candidate
+    test, FLOP_PAIR per in-range pair) over the launch's HIP-event time, and
+    the same with this kernel's own per-pair count beside it."""
+    peak = PEAK_FP32 if form == "fp32c" else PEAK_FP64
+    flop = FLOP_CAND * cands + FLOP_PAIR[form] * pairs
+    flop_k = FLOP_CAND * cands + FLOP_PAIR_KERNEL[form] * pairs
+    sec = kms * 1e-3
+    return {"bound": "alu", "achieved": flop / sec / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": flop / sec / peak, "kernel": kernel, "kernel_ms": kms,
+            "flop_per_launch": flop,
+            "flop_weights": {"candidate": FLOP_CAND, "pair": FLOP_PAIR[form]},
+            "kernel_counted": {"flop_per_launch": flop_k, "pair": FLOP_PAIR_KERNEL[form],
+                               "achieved": flop_k / sec / 1e12, "frac": flop_k / sec / peak}}
 
 
 def run_adjoint(sph, torch, d, ps, steps, warmup, ev):
@@ -177,12 +210,21 @@ def run_sort(sph, torch, d, ps, steps):
             "achieved_GBps": gbs, "peak_GBps": 8000.0, "frac": gbs / 8000.0}
 
 
-def run_batched(sph, torch, steps, warmup):
-    """groups10k (10,000 isolated Plummer groups, sizes ~ n^-2 on [32, 131072],
-    N_t = 32 +- 1), FP32C, autotuned launch parameters, sort + solve replayed
-    from a captured HIP graph."""
+BATCHED = {
+    "groups10k": "groups10k: 10000 isolated Plummer groups (sizes ~ n^-2 on [32, 131072], "
+                 "scale radii log-uniform 0.005-0.05)",
+    "groups10k_a1554": "groups10k_a1554: 10000 isolated Plummer groups (sizes ~ n^-1.554 on "
+                       "[32, 131072], the slope whose expected total is ~1.6e7; scale radii "
+                       "log-uniform 0.005-0.05)",
+}
+
+
+def run_batched(sph, torch, steps, warmup, ev, name="groups10k"):
+    """Many isolated groups (sizes power-law on [32, 131072], N_t = 32 +- 1),
+    FP32C, autotuned launch parameters, sort + solve replayed from a captured
+    HIP graph; the solve kernel's own time from HIP events on eager calls."""
     import sphgen
-    ps = sphgen.config("groups10k")
+    ps = sphgen.config(name)
     n, G = ps.n, len(ps.offsets) - 1
     d = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
          for k in ("x", "y", "z", "m", "h_init")}
@@ -199,6 +241,7 @@ def run_batched(sph, torch, steps, warmup):
     pairs = int(st["stats"][0].item())
     cands = int(st["stats"][1].item())
     final_pairs = int(st["nngb"].to(torch.int64).sum().item())
+    flagged = int(((st["status"] >> 16) != 0).sum().item())
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -218,22 +261,23 @@ def run_batched(sph, torch, steps, warmup):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
-    return {"workload": f"groups10k: {G} isolated Plummer groups (sizes ~ n^-2 on [32, 131072], "
-                        f"scale radii log-uniform 0.005-0.05), {n} particles, N_t = 32 +- 1, "
-                        "FP32C, autotuned, sort + solve replayed from one HIP graph",
-            "n": n, "groups": G, "ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
+    del graph
+    kms = kernel_ms(ev, p, lambda: sph.density_solve(d["x"], d["y"], d["z"], d["m"],
+                                                     d["h_init"], p, goff, ws=ws), steps)
+    roof = alu_roofline(cands, pairs, kms, "fp32c")
+    roof["replay_frac"] = roof["frac"] * kms / ms   # the same work over the whole replay
+    return {"workload": f"{BATCHED[name]}, {n} particles, N_t = 32 +- 1, FP32C, autotuned, "
+                        "sort + solve replayed from one HIP graph",
+            "n": n, "groups": G, "ms_per_step": ms, "kernel_ms": kms,
+            "interactions_per_s": pairs / (ms * 1e-3),
             "particles_per_s": n / (ms * 1e-3), "pairs_per_step": pairs,
             "candidates_per_step": cands, "final_pairs_per_s": final_pairs / (ms * 1e-3),
-            "roofline": {"bound": "alu", "kernel": "k_solve (groups, whole replay)",
-                         "achieved": (FLOP_CAND * cands + FLOP_PAIR["fp32c"] * pairs)
-                         / (ms * 1e-3) / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                         "frac": (FLOP_CAND * cands + FLOP_PAIR["fp32c"] * pairs)
-                         / (ms * 1e-3) / PEAK_FP32},
+            "flagged": flagged, "roofline": roof,
             "tuned": {"segment": p.segment, "waves_per_cu": p.waves_per_cu,
                       "tile_cell": p.tile_cell, "ms": tuned_ms, "tuning_s": tune_s}}
 
 
-def run_large(sph, torch, steps):
+def run_large(sph, torch, steps, ev):
     """clustered2^24: 2^24 particles, 2000 Plummer spheres (central contrast
     <= 1e5), N_t = 64 +- 1, FP32C, full sort in every call."""
     import sphgen
@@ -255,6 +299,10 @@ def run_large(sph, torch, steps):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
+    cands = int(o["stats"][1].item())
+    kms = kernel_ms(ev, p, lambda: sph.density_solve(d["x"], d["y"], d["z"], d["m"],
+                                                     d["h_init"], p, ws=ws), steps)
+    del o
     srt = run_sort(sph, torch, d, ps, steps)
     tr = measured_sort_traffic()
     srt["traffic"] = tr
@@ -264,8 +312,9 @@ def run_large(sph, torch, steps):
     return {"workload": "clustered2^24: 2^24 particles, 2000 Plummer spheres (contrast <= 1e5) "
                         "+ 30% background, N_t = 64 +- 1, FP32C, full sort every call",
             "n": n, "ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
-            "particles_per_s": n / (ms * 1e-3), "pairs_per_step": pairs, "flagged": flagged,
-            "sort": srt}
+            "particles_per_s": n / (ms * 1e-3), "pairs_per_step": pairs,
+            "candidates_per_step": cands, "flagged": flagged, "kernel_ms": kms,
+            "roofline": alu_roofline(cands, pairs, kms, "fp32c"), "sort": srt}
 
 
 def run_wendland(sph, torch, d, ps, steps, ev):
@@ -482,9 +531,42 @@ def run_force(sph, torch, d, ps, steps):
                          "flop_per_launch": flop}}
 
 
-def cpu_baseline(ps, budget_s=15.0):
-    """The oracle (k-d tree, OpenMP dynamic schedule, FP64) on a random sample."""
+def _cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo), with its family
+    and model numbers where the name alone is generic."""
+    import subprocess
+    name, fam, mod = None, None, None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() == "Model name" and name is None:
+                name = v.strip()
+            elif k.strip() == "CPU family":
+                fam = v.strip()
+            elif k.strip() == "Model":
+                mod = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if name is None:
+        try:
+            for ln in open("/proc/cpuinfo"):
+                if ln.startswith("model name"):
+                    name = ln.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    if name is not None and fam is not None:
+        name = f"{name} (family {fam}, model {mod})"
+    return name
+
+
+def cpu_baseline_child(budget_s):
+    """Runs in its own process with the OpenMP placement fixed before the
+    oracle's runtime starts: OMP_PROC_BIND=close, OMP_PLACES=cores."""
     import oracle
+    import sphgen
+    ps = sphgen.config("clustered2^20")
     rng = np.random.default_rng(12345)
     cores = oracle.max_threads()
     # two probes separate the fixed cost (tree build) from the per-particle cost
@@ -497,25 +579,49 @@ def cpu_baseline(ps, budget_s=15.0):
     fixed = max(t[0] - 2000 * per, 0.0)
     k = int(min(ps.n, max(2000, (budget_s - fixed) / per)))
     sub = rng.choice(ps.n, k, replace=False)
-    t0 = time.perf_counter()
-    r = oracle.solve(ps, subset=sub)
-    dt = time.perf_counter() - t0
-    pairs = int(r["pairs"].sum())
-    model = None
-    try:
-        for ln in open("/proc/cpuinfo"):
-            if ln.startswith("model name"):
-                model = ln.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
+    runs = []
+    pairs = 0
+    for _ in range(3):
+        t0 = time.perf_counter()
+        r = oracle.solve(ps, subset=sub)
+        runs.append(time.perf_counter() - t0)
+        pairs = int(r["pairs"].sum())
+    dt = float(np.median(runs))
+    # the small configuration by brute force (O(N^2) neighbour search), the same
+    # dynamic schedule: 4096 uniform particles, h_init = 0.125, N_t = 64 +- 2
+    c1 = sphgen.config("uniform4096")
+    bf = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        rb = oracle.solve(c1, search=0)
+        bf.append(time.perf_counter() - t0)
+    bdt = float(np.median(bf))
+    bpairs = int(rb["pairs"].sum())
     return {"value": pairs / dt, "unit": "interactions/s", "cores": cores, "kind": "oracle",
-            "cpu_model": model, "host_cpus": os.cpu_count(),
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "omp": {k: os.environ.get(k) for k in ("OMP_PROC_BIND", "OMP_PLACES",
+                                                   "OMP_NUM_THREADS")},
             "sample": (f"all {k} particles of the clustered set" if k == ps.n else
                        f"{k} particles drawn uniformly from the {ps.n}-particle clustered set")
                       + f", each solved to convergence against the full set (FP64 k-d tree, "
-                      f"{dt:.1f} s incl. tree build); particles/s = {k / dt:.4g}",
-            "particles_per_s": k / dt}
+                      f"OpenMP dynamic schedule; median of 3 runs {dt:.2f} s incl. tree "
+                      f"build); particles/s = {k / dt:.4g}",
+            "runs_s": runs, "particles_per_s": k / dt,
+            "brute_force_uniform4096": {"ms": 1e3 * bdt, "runs_ms": [1e3 * v for v in bf],
+                                        "interactions_per_s": bpairs / bdt,
+                                        "particles_per_s": c1.n / bdt}}
+
+
+def cpu_baseline(budget_s=6.0):
+    """The oracle on the host's cores, in a child process (it uses no GPU) so
+    that its OpenMP threads are pinned as asked before they start."""
+    import subprocess
+    env = dict(os.environ, OMP_PROC_BIND="close", OMP_PLACES="cores")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-child",
+                        str(budget_s)], env=env, capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        raise RuntimeError("cpu baseline failed:\n" + r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 SOLVE_SRC = os.path.join(ROOT, "paper_1612_06090_amd", "csrc", "solve.hip")
@@ -681,8 +787,8 @@ def summarize_valu(cmd, *csvs, kernel="k_solve", calls=None):
 
 
 def measured_valu(kernel="k_solve"):
-    """Executed binary32 VALU FLOP per unit (a k_solve launch, a backward call)
-    from the committed counter summary, or None when the kernel source changed
+    """The committed counter summary of a kernel's executed VALU work (per
+    k_solve launch, per backward call), or None when the kernel source changed
     since it was taken."""
     import hashlib
     path, src, _ = VALU_TARGETS[kernel]
@@ -696,7 +802,7 @@ def measured_valu(kernel="k_solve"):
         return None
     if d.get(key) != hashlib.sha256(open(src, "rb").read()).hexdigest():
         return None
-    return d.get("executed_f32_flop_per_launch")
+    return d
 
 
 SORT_SRC = os.path.join(ROOT, "paper_1612_06090_amd", "csrc", "sort.hip")
@@ -860,7 +966,12 @@ def main():
                     help="report totals per call over this many calls (default: per dispatch)")
     ap.add_argument("--profile-adjoint", action="store_true",
                     help="only one solve + adjoint calls (for rocprofv3 --pmc)")
+    ap.add_argument("--cpu-baseline-child", type=float, default=None, metavar="BUDGET_S",
+                    help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_baseline_child is not None:
+        print(json.dumps(cpu_baseline_child(args.cpu_baseline_child)), flush=True)
+        return
     if args.summarize_trace:
         if len(args.summarize_trace) not in (2, 3):
             ap.error("--summarize-trace takes STATS_CSV CMD [headline|knn]")
@@ -926,10 +1037,12 @@ def main():
         adj = run_adjoint(sph, torch, d, ps, max(3, args.steps // 2), 1, ev)
         print(f"[bench] adjoint {adj}", file=sys.stderr, flush=True)
 
-    bat = None
+    bat = bat2 = None
     if not args.no_batched:
-        bat = run_batched(sph, torch, max(3, args.steps), args.warmup)
+        bat = run_batched(sph, torch, max(3, args.steps), args.warmup, ev)
         print(f"[bench] batched {bat}", file=sys.stderr, flush=True)
+        bat2 = run_batched(sph, torch, 3, 1, ev, "groups10k_a1554")
+        print(f"[bench] batched_a1554 {bat2}", file=sys.stderr, flush=True)
 
     wc6 = None
     if not args.no_wendland:
@@ -953,22 +1066,18 @@ def main():
         print(f"[bench] knn {knn}", file=sys.stderr, flush=True)
     big = None
     if not args.no_large:
-        big = run_large(sph, torch, 3)
+        big = run_large(sph, torch, 3, ev)
         print(f"[bench] large {big}", file=sys.stderr, flush=True)
 
     def roof(r, form):
-        flop = FLOP_CAND * r["cands"] + FLOP_PAIR[form] * r["pairs"]
-        ach = flop / (r["kernel_ms"] * 1e-3)
-        peak = PEAK_FP32 if form == "fp32c" else PEAK_FP64
-        tr = measured_traffic() if form == "fp32c" else None
-        out = {"bound": "alu", "achieved": ach / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-               "frac": ach / peak, "traffic": tr, "kernel": "k_solve",
-               "kernel_ms": r["kernel_ms"], "kernel_ms_median": r["kernel_ms_median"],
-               "flop_per_launch": flop}
+        out = alu_roofline(r["cands"], r["pairs"], r["kernel_ms"], form)
+        out["traffic"] = measured_traffic() if form == "fp32c" else None
+        out["kernel_ms_median"] = r["kernel_ms_median"]
         if form == "fp32c":
-            # counter-measured binary32 VALU work of the same launch (all 64 lanes of
-            # every issued instruction, masked lanes included), at this run's kernel time
-            out["executed"] = _executed(measured_valu(), flop, r["kernel_ms"])
+            # counter-measured VALU work of the same launch (all 64 lanes of every
+            # issued instruction, masked lanes included), at this run's kernel time
+            out["executed"] = _executed(measured_valu(), out["flop_per_launch"],
+                                        r["kernel_ms"])
         return out
 
     value = f32["pairs"] / (f32["ms_per_step"] * 1e-3)
@@ -1017,6 +1126,8 @@ def main():
     line["sort"] = srt
     if bat is not None:
         line["batched"] = bat
+    if bat2 is not None:
+        line["batched_a1554"] = bat2
     if big is not None:
         line["large"] = big
     if wc6 is not None:
@@ -1032,7 +1143,7 @@ def main():
     if adj is not None:
         line["adjoint"] = adj
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(ps)
+        line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
 
 

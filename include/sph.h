@@ -64,7 +64,7 @@ extern "C" {
 #define SPH_KERNEL_M4          0  /* M4 cubic spline (Gadget-2 convention), sigma = 8/pi:
                                      f = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (q <= 1) */
 #define SPH_KERNEL_WENDLAND_C6 1  /* Wendland C6, the kernel of the paper's runs
-                                     (Sec. II-C), sigma = 1365/(64 pi):
+                                     (Sec. II-B), sigma = 1365/(64 pi):
                                      f = (1-q)^8 (1 + 8q + 25q^2 + 32q^3) */
 
 /* io_dtype: element type of caller arrays x, y, z, m, h_init, rho, h, nw, grads */
@@ -188,6 +188,13 @@ int sph_workspace_size(const sph_params *params, int64_t n, int32_t n_groups, si
  *   *n_cells_out (device int32) = number of occupied cells.
  * group_offsets: device int64[n_groups + 1], non-decreasing, offsets[0] = 0,
  * offsets[n_groups] = n; NULL iff n_groups == 0.  Requires n_groups < 65536.
+ * The offsets stay on the device and are not checked synchronously: every
+ * entry point first copies them into its workspace as offsets[0] = 0,
+ * offsets[n_groups] = n and, in between, the running maximum of the given
+ * values clamped to [0, n], which leaves well-formed offsets unchanged.
+ * Malformed offsets therefore never make a kernel read outside the caller's
+ * arrays; the results are those of the corrected groups (the Python binding
+ * rejects malformed offsets on the host instead).
  * Any output pointer except keys_out and perm_out may be NULL. */
 int sph_sort(const sph_params *params, int64_t n, int32_t n_groups,
              const int64_t *group_offsets,

@@ -73,7 +73,9 @@ class _Cfg(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        path = build()
+        # SPH_ORACLE_LIB names another build of the same source (the tests load
+        # an AddressSanitizer / UBSan build this way)
+        path = os.environ.get("SPH_ORACLE_LIB") or build()
         L = C.CDLL(path)
         P = C.c_void_p
         L.oracle_kernel_f.restype = C.c_double

@@ -28,7 +28,7 @@
  * Kernels (cfg.kernel), both with compact support h, W(r,h) = sigma/h^3 f(r/h):
  *   0  M4 cubic spline (the Gadget-2 convention), sigma = 8/pi:
  *      f = 1 - 6q^2 + 6q^3 (q <= 1/2), 2(1-q)^3 (1/2 < q <= 1);
- *   1  Wendland C6, the kernel of the paper's runs (Sec. II-C), in its 3D
+ *   1  Wendland C6, the kernel of the paper's runs (Sec. II-B), in its 3D
  *      normalisation, sigma = 1365/(64 pi):  f = (1-q)^8 (1 + 8q + 25q^2 + 32q^3).
  * The weighted neighbour count is n = (4 pi/3) h^3 sum_j W = C sum_j f with
  * C = (4 pi/3) sigma (32/3 and 1365/48).

@@ -194,6 +194,27 @@ def _check_dev(*ts):
     return dev
 
 
+def _check_offsets(goff, n):
+    """Host check of group offsets: non-decreasing from 0 to n.
+
+    The library itself replaces malformed offsets by the nearest well-formed
+    ones on the device (so no kernel reads out of range); this check turns
+    them into an error instead.  It reads the offsets back (a synchronising
+    copy), so it is skipped while a HIP graph is being captured.
+    """
+    if goff is None:
+        return
+    torch = _torch()
+    if goff.dtype != torch.int64 or goff.dim() != 1 or goff.shape[0] < 2:
+        raise ValueError("group offsets must be a 1-D int64 tensor of n_groups + 1 entries")
+    if torch.cuda.is_current_stream_capturing():
+        return
+    o = goff.cpu()
+    if int(o[0]) != 0 or int(o[-1]) != n or bool((o[1:] < o[:-1]).any()):
+        raise ValueError("group offsets must be non-decreasing with offsets[0] = 0 and "
+                         "offsets[n_groups] = n")
+
+
 def _stride_bytes(*ts):
     """Common byte stride of 1-D per-particle tensors (0: all packed).
 
@@ -237,6 +258,7 @@ def sort(x, y, z, params: Params | None = None, group_offsets=None, cells=True):
     dev = _check_dev(x, y, z, group_offsets)
     n = x.shape[0]
     G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    _check_offsets(group_offsets, n)
     ws = workspace(params, n, G, dev)
     keys = torch.empty(n, dtype=torch.int64, device=dev)
     perm = torch.empty(n, dtype=torch.int32, device=dev)
@@ -271,6 +293,7 @@ def density_solve(x, y, z, m, h_init=None, params: Params | None = None, group_o
     dev = _check_dev(x, y, z, m, h_init, group_offsets)
     n = x.shape[0]
     G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    _check_offsets(group_offsets, n)
     if ws is None:
         ws = workspace(params, n, G, dev)
     dt = _io(params)
@@ -311,6 +334,7 @@ def density_backward(x, y, z, m, h, grad_rho, grad_h=None, params: Params | None
     dev = _check_dev(x, y, z, m, h, grad_rho, grad_h, group_offsets)
     n = x.shape[0]
     G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    _check_offsets(group_offsets, n)
     if ws is None:
         ws = workspace(params, n, G, dev)
     dt = _io(params)
@@ -343,6 +367,7 @@ def density_scatter(x, y, z, m, h, params: Params | None = None, group_offsets=N
     dev = _check_dev(x, y, z, m, h, group_offsets)
     n = x.shape[0]
     G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    _check_offsets(group_offsets, n)
     if ws is None:
         ws = workspace(params, n, G, dev)
     dt = _io(params)
@@ -372,6 +397,7 @@ def pressure_force(x, y, z, m, h, rho, pressure, params: Params | None = None,
     dev = _check_dev(x, y, z, m, h, rho, pressure, group_offsets)
     n = x.shape[0]
     G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    _check_offsets(group_offsets, n)
     if ws is None:
         ws = workspace(params, n, G, dev)
     dt = _io(params)
@@ -398,6 +424,7 @@ def autotune(x, y, z, m, h_init=None, params: Params | None = None, group_offset
     dev = _check_dev(x, y, z, m, h_init, group_offsets)
     n = x.shape[0]
     G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    _check_offsets(group_offsets, n)
     if ws is None:
         ws = workspace(params, n, G, dev)
     dt = _io(params)

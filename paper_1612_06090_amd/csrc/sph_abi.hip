@@ -99,6 +99,7 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
         pl.gvalsA = (int32_t *)take(4 * (size_t)G);
         pl.gvalsB = (int32_t *)take(4 * (size_t)G);
         pl.ghist = (uint32_t *)take(4 * 256 * (size_t)pl.nb_gsort);
+        pl.goff = (int64_t *)take(8 * ((size_t)G + 1));
     }
     pl.ctrl = (int32_t *)take(64);
     pl.stats = (uint64_t *)take(64);
@@ -172,6 +173,55 @@ static int check_ws(const sph_params *p, int64_t n, int32_t G, void *ws, size_t 
 
 __global__ void k_store_i32(int32_t *p, int32_t v) { *p = v; }
 
+// Group offsets as every kernel assumes them: out[0] = 0, out[G] = n and
+// out[g] = the running maximum of the caller's offsets clamped to [0, n]
+// in between.  Well-formed offsets are copied unchanged; malformed ones
+// (decreasing, outside [0, n], wrong ends) are replaced by the nearest
+// well-formed sequence, so that no kernel reads outside the particle arrays.
+// One block of 1024 threads, each owning a contiguous run of entries.
+constexpr int kCleanThreads = 1024;
+
+__global__ __launch_bounds__(kCleanThreads) void k_clean_offsets(int32_t G, int64_t n,
+                                                                 const int64_t *in,
+                                                                 int64_t *out) {
+    __shared__ int64_t run_max[kCleanThreads];
+    const int t = threadIdx.x;
+    const int64_t cnt = (int64_t)G + 1;
+    const int64_t per = (cnt + kCleanThreads - 1) / kCleanThreads;
+    const int64_t b = (int64_t)t * per;
+    const int64_t e = b + per < cnt ? b + per : cnt;
+    auto clampv = [&](int64_t g) -> int64_t {
+        if (g == 0) return 0;
+        if (g == G) return n;
+        const int64_t v = in[g];
+        return v < 0 ? 0 : (v > n ? n : v);
+    };
+    int64_t m = 0;
+    for (int64_t g = b; g < e; ++g) m = clampv(g) > m ? clampv(g) : m;
+    run_max[t] = m;
+    __syncthreads();
+    // inclusive max-scan over the threads' maxima (Hillis-Steele)
+    for (int o = 1; o < kCleanThreads; o <<= 1) {
+        const int64_t w = t >= o ? run_max[t - o] : 0;
+        __syncthreads();
+        if (w > run_max[t]) run_max[t] = w;
+        __syncthreads();
+    }
+    int64_t acc = t > 0 ? run_max[t - 1] : 0;
+    for (int64_t g = b; g < e; ++g) {
+        const int64_t v = clampv(g);
+        acc = v > acc ? v : acc;
+        out[g] = acc;
+    }
+}
+
+hipError_t run_clean_offsets(const Plan &pl, const int64_t *goff, hipStream_t st) {
+    if (!pl.grouped) return hipSuccess;
+    hipLaunchKernelGGL(k_clean_offsets, dim3(1), dim3(kCleanThreads), 0, st, pl.G, pl.n, goff,
+                       pl.goff);
+    return hipGetLastError();
+}
+
 }  // namespace sph
 
 using namespace sph;
@@ -232,7 +282,9 @@ int sph_sort(const sph_params *params, int64_t n, int32_t n_groups, const int64_
     Plan pl;
     rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
     if (rc != SPH_OK) return rc;
-    hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
+    hipError_t e = run_clean_offsets(pl, group_offsets, st);
+    const int64_t *goff = pl.goff;
+    if (e == hipSuccess) e = run_keys_and_sort(pl, goff, x, y, z, st);
     if (e == hipSuccess) e = run_copy_sorted(pl, keys_out, perm_out, st);
     if (e == hipSuccess && (cell_id_out || cell_start_out || cell_count_out || n_cells_out))
         e = run_contract_cells(pl, cell_id_out, cell_start_out, cell_count_out, n_cells_out, st);
@@ -267,15 +319,16 @@ int sph_density_solve(const sph_params *params, int64_t n, int32_t n_groups,
     rc = check_ws(params, n, n_groups, ws, ws_bytes, &pl);
     if (rc != SPH_OK) return rc;
     const bool f32c = params->precision == SPH_FP32C;
-    hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
-    if (e == hipSuccess) e = run_permute(pl, group_offsets, x, y, z, m, h_init, f32c, st);
+    hipError_t e = run_clean_offsets(pl, group_offsets, st);
+    const int64_t *goff = pl.goff;
+    if (e == hipSuccess) e = run_keys_and_sort(pl, goff, x, y, z, st);
+    if (e == hipSuccess) e = run_permute(pl, goff, x, y, z, m, h_init, f32c, st);
     if (e == hipSuccess) {
         if (!pl.grouped) e = run_dense_table(pl, st);
-        else e = run_group_items(pl, group_offsets, st);
+        else e = run_group_items(pl, goff, st);
     }
     if (e == hipSuccess)
-        e = run_solve(pl, group_offsets, rho_out, h_out, nw_out, nngb_out, status_out, stats_out,
-                      st);
+        e = run_solve(pl, goff, rho_out, h_out, nw_out, nngb_out, status_out, stats_out, st);
     if (e != hipSuccess) return hip_fail(e);
     return SPH_OK;
 }
@@ -306,15 +359,16 @@ int sph_density_backward(const sph_params *params, int64_t n, int32_t n_groups,
     const bool f32c = params->precision == SPH_FP32C;
     // group work items of the adjoint are its tiles
     pl.prm.segment = kAdjTile;
-    hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
-    if (e == hipSuccess) e = run_permute(pl, group_offsets, x, y, z, m, h, f32c, st);
+    hipError_t e = run_clean_offsets(pl, group_offsets, st);
+    const int64_t *goff = pl.goff;
+    if (e == hipSuccess) e = run_keys_and_sort(pl, goff, x, y, z, st);
+    if (e == hipSuccess) e = run_permute(pl, goff, x, y, z, m, h, f32c, st);
     if (e == hipSuccess) {
         if (!pl.grouped) e = run_dense_table(pl, st);
-        else e = run_group_items(pl, group_offsets, st);
+        else e = run_group_items(pl, goff, st);
     }
     if (e == hipSuccess)
-        e = run_backward(pl, group_offsets, h, grad_rho, grad_h, grad_x, grad_y, grad_z, grad_m,
-                         st);
+        e = run_backward(pl, goff, h, grad_rho, grad_h, grad_x, grad_y, grad_z, grad_m, st);
     if (e != hipSuccess) return hip_fail(e);
     return SPH_OK;
 }
@@ -344,14 +398,16 @@ int sph_pressure_force(const sph_params *params, int64_t n, int32_t n_groups,
     hipStream_t st = (hipStream_t)stream;
     const bool f32c = params->precision == SPH_FP32C;
     pl.prm.segment = kAdjTile;
-    hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
-    if (e == hipSuccess) e = run_permute(pl, group_offsets, x, y, z, m, h, f32c, st);
+    hipError_t e = run_clean_offsets(pl, group_offsets, st);
+    const int64_t *goff = pl.goff;
+    if (e == hipSuccess) e = run_keys_and_sort(pl, goff, x, y, z, st);
+    if (e == hipSuccess) e = run_permute(pl, goff, x, y, z, m, h, f32c, st);
     if (e == hipSuccess) {
         if (!pl.grouped) e = run_dense_table(pl, st);
-        else e = run_group_items(pl, group_offsets, st);
+        else e = run_group_items(pl, goff, st);
     }
     if (e == hipSuccess)
-        e = run_force(pl, group_offsets, m, rho, pressure, ax_out, ay_out, az_out, st);
+        e = run_force(pl, goff, m, rho, pressure, ax_out, ay_out, az_out, st);
     if (e != hipSuccess) return hip_fail(e);
     return SPH_OK;
 }
@@ -379,13 +435,15 @@ int sph_density_scatter(const sph_params *params, int64_t n, int32_t n_groups,
     const bool f32c = params->precision == SPH_FP32C;
     // the walk's group work items are its tiles
     pl.prm.segment = kAdjTile;
-    hipError_t e = run_keys_and_sort(pl, group_offsets, x, y, z, st);
-    if (e == hipSuccess) e = run_permute(pl, group_offsets, x, y, z, m, h, f32c, st);
+    hipError_t e = run_clean_offsets(pl, group_offsets, st);
+    const int64_t *goff = pl.goff;
+    if (e == hipSuccess) e = run_keys_and_sort(pl, goff, x, y, z, st);
+    if (e == hipSuccess) e = run_permute(pl, goff, x, y, z, m, h, f32c, st);
     if (e == hipSuccess) {
         if (!pl.grouped) e = run_dense_table(pl, st);
-        else e = run_group_items(pl, group_offsets, st);
+        else e = run_group_items(pl, goff, st);
     }
-    if (e == hipSuccess) e = run_scatter(pl, group_offsets, rho_s_out, rho_sym_out, nngb_s_out, st);
+    if (e == hipSuccess) e = run_scatter(pl, goff, rho_s_out, rho_sym_out, nngb_s_out, st);
     if (e != hipSuccess) return hip_fail(e);
     return SPH_OK;
 }

@@ -123,6 +123,7 @@ struct Plan {
     int32_t *gvalsA = nullptr, *gvalsB = nullptr;
     uint32_t *ghist = nullptr;
     int64_t nb_gsort = 0;        // radix blocks of the group-order sort
+    int64_t *goff = nullptr;     // groups: the caller's offsets made well formed (G+1)
     int32_t *ctrl = nullptr;     // [0] work queue head, [1..] reserved
     uint64_t *stats = nullptr;   // 4 x uint64 device counters
     double *adj = nullptr;       // adjoint, sorted order: alpha, beta, gamma, grad_rho, grad_h (5 x n)
@@ -153,6 +154,7 @@ hipError_t run_group_items(Plan &pl, const int64_t *goff, hipStream_t st);
 hipError_t run_copy_sorted(Plan &pl, uint64_t *keys_out, int32_t *perm_out, hipStream_t st);
 hipError_t run_zero_u64(uint64_t *p, int64_t cnt, hipStream_t st);
 hipError_t run_zero_i32(int32_t *p, int64_t cnt, hipStream_t st);
+hipError_t run_clean_offsets(const Plan &pl, const int64_t *goff, hipStream_t st);
 
 // solve.hip
 hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw,

@@ -49,7 +49,11 @@ def test_valu_summary(tmp_path, monkeypatch):
     assert d["executed_f64_flop_per_launch"] == pytest.approx(64 * 2 * 7 * 2.0)
     assert d["thread_cycles_per_valu_cycle_raw"] == pytest.approx(32.0)
     assert d["dispatches"]["SQ_INSTS_VALU_FMA_F32"] == 2
-    assert bench.measured_valu() == d["executed_f32_flop_per_launch"]
+    assert bench.measured_valu()["executed_f32_flop_per_launch"] == \
+        d["executed_f32_flop_per_launch"]
+    # lane utilisation: 3200 thread-cycles per 100 active VALU cycles = 32 of 64 lanes
+    ex = bench._executed(bench.measured_valu(), 1.0, 1.0)
+    assert ex["valu_lane_utilisation"] == pytest.approx(0.5)
     d["solve_hip_sha256"] = "0" * 64
     json.dump(d, open(bench.VALU_JSON, "w"))
     assert bench.measured_valu() is None
@@ -115,6 +119,20 @@ def test_valu_summary_per_call(tmp_path, monkeypatch):
     bench.summarize_valu("cmd", a, kernel="k_adjoint", calls=2)
     d = json.load(open(path))
     assert d["executed_f32_flop_per_launch"] == pytest.approx(64 * 2 * 100.0 / 2)
-    assert bench.measured_valu("k_adjoint") == d["executed_f32_flop_per_launch"]
-    ex = bench._executed(d["executed_f32_flop_per_launch"], 1600.0, 2.0)
+    assert bench.measured_valu("k_adjoint")["executed_f32_flop_per_launch"] == \
+        d["executed_f32_flop_per_launch"]
+    ex = bench._executed(d, 1600.0, 2.0)
     assert ex["algorithmic_over_executed"] == pytest.approx(0.25)
+    assert "valu_lane_utilisation" not in ex    # no thread-cycle counters in this summary
+
+
+def test_alu_roofline_weights():
+    # headline: 8 FLOP per candidate test, 31 (FP32C) / 22 (FP64) per in-range
+    # pair; the kernel's own count (17 per pair) beside it
+    r = bench.alu_roofline(1e10, 4e9, 10.0, "fp32c")
+    assert r["flop_per_launch"] == pytest.approx(8e10 + 31 * 4e9)
+    assert r["frac"] == pytest.approx((8e10 + 31 * 4e9) / 1e-2 / 157.3e12)
+    assert r["kernel_counted"]["flop_per_launch"] == pytest.approx(8e10 + 17 * 4e9)
+    r = bench.alu_roofline(1e10, 4e9, 10.0, "fp64")
+    assert r["flop_per_launch"] == pytest.approx(8e10 + 22 * 4e9)
+    assert r["peak"] == pytest.approx(78.6)

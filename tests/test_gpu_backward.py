@@ -154,8 +154,9 @@ def test_backward_lattice_symmetry(precision):
 
 def test_backward_clustered2p20_central_differences():
     # full-size set, FP64 root-mode solves: the directional derivative of
-    # L = sum gr rho along 8 random unit directions over all (x, m), and 16
-    # single-coordinate probes, against the adjoint (FP64 and FP32C)
+    # L = sum gr rho along 8 random unit directions over all (x, m), and 64
+    # single-coordinate probes (x, y, z and m of 16 particles), against the
+    # adjoint (FP64 and FP32C)
     import torch
     ps = sphgen.config("clustered2^20")
     n = ps.n
@@ -198,20 +199,33 @@ def test_backward_clustered2p20_central_differences():
         say(f"  direction {t}: fd {fd:.10e}")
     say(f"  worst relative error: {worst}")
     assert worst["fp64"] <= 1e-5 and worst["fp32c"] <= 1e-4
-    # single coordinates of particles in the densest regions (largest rho)
+    # 64 single-coordinate probes: the three position coordinates and the mass
+    # of 16 particles, 8 in the densest regions (largest rho) and 8 at random
     top = np.argsort(-o0["rho"].cpu().numpy())[:8]
     probes = list(top) + list(rng.choice(n, 8, replace=False))
     scale = np.abs(g64["gx"]).max()
+    scale_m = np.abs(g64["gm"]).max()
+    done = 0
     for k in probes:
         for a, key in enumerate(("gx", "gy", "gz")):
-            if a != k % 3:
-                continue
             dx = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
             dx[k, a] = 1.0
             step = 1e-6 * h[k]
             fd = (L(dx, None, step)[0] - L(dx, None, -step)[0]) / (2 * step)
             err = abs(fd - g64[key][k])
             assert err <= 1e-5 * max(abs(fd), 1e-3 * scale), (k, a, fd, g64[key][k])
+            done += 1
+        dm = torch.zeros(n, dtype=torch.float64, device="cuda")
+        dm[k] = 1.0
+        # rho is linear in each mass (h does not depend on masses), so a large
+        # step keeps the difference far above the rounding of the full sum
+        step = 0.5 * ps.m[k]
+        fd = (L(None, dm, step)[0] - L(None, dm, -step)[0]) / (2 * step)
+        err = abs(fd - g64["gm"][k])
+        assert err <= 1e-5 * max(abs(fd), 1e-3 * scale_m), (k, "m", fd, g64["gm"][k])
+        done += 1
+    say(f"  {done} single-coordinate probes within 1e-5")
+    assert done == 64
 
 
 def test_backward_deterministic():

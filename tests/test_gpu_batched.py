@@ -67,6 +67,39 @@ def test_groups10k_full_sampled():
     _fp32c_at_h(ps, g, sub)
 
 
+def test_groups10k_a1554_full_sampled():
+    # the group-size reading whose expected total is ~1.6e7 (slope -1.554):
+    # 14.8e6 particles, groups up to 131072, FP32C, autotuned launch as in
+    # the benchmark; 3000 particles against the oracle's solve, the same
+    # particles at the GPU's h
+    import torch
+    ps = sphgen.config("groups10k_a1554")
+    say(f"[batched] groups10k_a1554 n={ps.n} G={len(ps.offsets) - 1}")
+    p0 = params_for(ps, precision=sph.FP32C)
+    d = dev_arrays(ps)
+    p, ms = sph.autotune(d["x"], d["y"], d["z"], d["m"], d["h_init"], p0, d["goff"])
+    say(f"  tuned: segment {p.segment} waves/CU {p.waves_per_cu} tile_cell {p.tile_cell}: "
+        f"{ms:.3f} ms")
+    o = sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, d["goff"])
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in o.items()}
+    for k in ("rho", "h", "nw"):
+        g[k] = g[k].astype(np.float64)
+    del d, o
+    assert np.all((g["status"] & (sph.ST_NOCONV | sph.ST_BADINPUT)) == 0)
+    rng = np.random.default_rng(62)
+    sub = rng.choice(ps.n, 3000, replace=False)
+    # the largest groups hold most particles: take 300 more from the largest
+    big = int(np.argmax(np.diff(ps.offsets)))
+    sub = np.unique(np.concatenate([sub, rng.integers(ps.offsets[big], ps.offsets[big + 1],
+                                                      300)]))
+    o = oracle.solve(ps, subset=sub)
+    dh = rel(g["h"][sub], o["h"])
+    say(f"  sampled frac |dh|/h <= 1e-5: {(dh <= 1e-5).mean():.5f}")
+    assert (dh <= 1e-5).mean() >= 0.999
+    _fp32c_at_h(ps, g, sub)
+
+
 def test_autotune_and_cache():
     import time
     import torch
@@ -190,3 +223,57 @@ def test_maximum_group_count():
     torch.cuda.synchronize()
     ok = oracle.sort(ps)
     assert np.array_equal(s["perm"].cpu().numpy(), ok["perm"].astype(np.int32))
+
+
+def test_malformed_offsets():
+    # the binding rejects malformed offsets on the host; through the C ABI the
+    # library replaces them by the nearest well-formed ones (running maximum
+    # clamped to [0, n], ends 0 and n) before any kernel reads them
+    import ctypes as C
+    import torch
+    ps = sphgen.groups(5, seed=66, sizes=np.array([300, 500, 200, 400, 100]), n_target=16.0,
+                       n_tol=1.0)
+    d = dev_arrays(ps)
+    n = ps.n
+    p = params_for(ps)
+    bad = torch.tensor([5, 300, 200, 900, n + 1000, n - 7], dtype=torch.int64, device="cuda")
+    with pytest.raises(ValueError):
+        sph.sort(d["x"], d["y"], d["z"], p, bad)
+    with pytest.raises(ValueError):
+        sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p, bad)
+    good = torch.tensor([0, 300, 300, 900, n, n], dtype=torch.int64, device="cuda")
+
+    def raw_sort(goff):
+        ws = sph.workspace(p, n, 5, d["x"].device)
+        keys = torch.empty(n, dtype=torch.int64, device="cuda")
+        perm = torch.empty(n, dtype=torch.int32, device="cuda")
+        rc = sph.load().sph_sort(C.byref(p), n, 5, C.c_void_p(goff.data_ptr()),
+                                 C.c_void_p(d["x"].data_ptr()), C.c_void_p(d["y"].data_ptr()),
+                                 C.c_void_p(d["z"].data_ptr()), C.c_void_p(keys.data_ptr()),
+                                 C.c_void_p(perm.data_ptr()), None, None, None, None,
+                                 C.c_void_p(ws.data_ptr()), ws.numel(),
+                                 C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        assert rc == sph.OK
+        return keys.cpu().numpy(), perm.cpu().numpy()
+
+    kb, pb = raw_sort(bad)
+    kg, pg = raw_sort(good)
+    assert np.array_equal(kb, kg) and np.array_equal(pb, pg)
+    # the solve through the C ABI: the same as with the corrected offsets
+    ws = sph.workspace(p, n, 5, d["x"].device)
+    outs = []
+    for goff in (bad, good):
+        o = {k: torch.empty(n, dtype=torch.float64, device="cuda") for k in ("rho", "h")}
+        rc = sph.load().sph_density_solve(
+            C.byref(p), n, 5, C.c_void_p(goff.data_ptr()), C.c_void_p(d["x"].data_ptr()),
+            C.c_void_p(d["y"].data_ptr()), C.c_void_p(d["z"].data_ptr()),
+            C.c_void_p(d["m"].data_ptr()), C.c_void_p(d["h_init"].data_ptr()),
+            C.c_void_p(o["rho"].data_ptr()), C.c_void_p(o["h"].data_ptr()), None, None, None,
+            None, C.c_void_p(ws.data_ptr()), ws.numel(),
+            C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        assert rc == sph.OK
+        outs.append({k: v.cpu().numpy() for k, v in o.items()})
+    assert np.array_equal(outs[0]["h"], outs[1]["h"])
+    assert np.array_equal(outs[0]["rho"], outs[1]["rho"])

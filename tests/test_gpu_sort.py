@@ -1,5 +1,12 @@
 """GPU parity of the spatial sort (Morton keys, stable radix sort, cell
-table): bit-exact against the CPU oracle."""
+table): bit-exact against the CPU oracle.
+
+Sets of up to 2^21 particles sort with 4 ranking rounds per wave; larger ones
+with 16 (a 4096-key block tile): the cases above 2^21 (the threshold plus
+one, many duplicated keys, the clustered 2^24 set and both group-size
+readings of the 10,000-group workload) cover that second instantiation,
+where a stability error among equal keys would leave h and rho untouched
+and only the permutation would show it."""
 import numpy as np
 import pytest
 
@@ -12,7 +19,8 @@ pytestmark = pytest.mark.gpu
 
 def _cases():
     return ["uniform4096", "uniform_ragged", "clustered", "duplicates", "f32io", "groups",
-            "one", "clustered2^20"]
+            "one", "clustered2^20", "threshold+1", "duplicates2^22", "clustered2^24",
+            "groups10k", "groups10k_a1554"]
 
 
 def _make(case):
@@ -40,6 +48,19 @@ def _make(case):
         return sphgen.uniform(1, seed=36), "float64"
     if case == "clustered2^20":
         return sphgen.config("clustered2^20"), "float64"
+    if case == "threshold+1":
+        # one key past the 4-round limit: the last 4096-key tile holds one key
+        return sphgen.uniform((1 << 21) + 1, seed=38), "float64"
+    if case == "duplicates2^22":
+        # 4.2e6 particles on 3000 distinct positions (and a ragged last tile):
+        # every key is shared by ~1400 particles spread over many blocks
+        ps = sphgen.uniform((1 << 22) + 12345, seed=39)
+        rng = np.random.default_rng(39)
+        src = rng.integers(0, 3000, ps.n)
+        ps.x, ps.y, ps.z = ps.x[src].copy(), ps.y[src].copy(), ps.z[src].copy()
+        return ps, "float64"
+    if case in ("clustered2^24", "groups10k", "groups10k_a1554"):
+        return sphgen.config(case), "float64"
     raise KeyError(case)
 
 

@@ -35,9 +35,11 @@ def test_wendland_fp64(name):
     o = oracle.solve(ps, kernel=oracle.WENDLAND_C6)
     same = rel(g["h"], o["h"]) <= 1e-12
     say(f"  flips {(~same).sum()} / {ps.n}")
-    assert same.mean() >= 0.999
-    assert rel(g["rho"][same], o["rho"][same]).max() < 1e-12
-    assert np.array_equal(g["status"][same], o["status"][same])
+    # binary64 sums agree to ~1e-15, so a band-edge flip needs a count within
+    # that of N_t +- dN: none is expected on these sets, and none is allowed
+    assert same.all()
+    assert rel(g["rho"], o["rho"]).max() < 1e-12
+    assert np.array_equal(g["status"], o["status"])
 
 
 def _fp32c_check(ps, g, sub=None):
