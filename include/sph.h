@@ -312,6 +312,29 @@ int sph_autotune(const sph_params *params, int64_t n, int32_t n_groups,
                  void *ws, size_t ws_bytes, void *stream,
                  sph_params *best_out, float *best_ms_out);
 
+/* sph_density_solve without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Arguments, outputs and results are those
+ * of sph_density_solve; the workspace is a fixed scratch array of
+ * SPH_NOALLOC_SCRATCH_BYTES held in the library's device memory (one per
+ * device, kept until the process ends; its address is looked up once per
+ * device, on the first call with that device current).  The call allocates
+ * nothing.  A problem whose sph_workspace_size exceeds the scratch (about
+ * 3e5 particles) returns SPH_E_WORKSPACE before anything is enqueued; use
+ * sph_density_solve with a caller workspace for larger sets.  Every call on
+ * one device shares that device's scratch, which keeps the last call's
+ * contents (no call relies on them): calls that may overlap on one device
+ * (different streams, or host threads without ordering) race and must not be
+ * issued. */
+#define SPH_NOALLOC_SCRATCH_BYTES (64u << 20)
+int sph_density_solve_noalloc(const sph_params *params, int64_t n, int32_t n_groups,
+                              const int64_t *group_offsets,
+                              const void *x, const void *y, const void *z, const void *m,
+                              const void *h_init,
+                              void *rho_out, void *h_out, void *nw_out,
+                              int32_t *nngb_out, int32_t *status_out, uint64_t *stats_out,
+                              void *stream);
+
 /* Static text for a return code. */
 const char *sph_status_string(int code);
 

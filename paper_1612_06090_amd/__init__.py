@@ -17,7 +17,7 @@ import os
 
 __all__ = [
     "LIB_PATH", "Params", "SPHError", "load", "default_params", "workspace_size", "sort",
-    "density_solve", "density_backward", "density_scatter", "pressure_force", "autotune",
+    "density_solve", "density_solve_noalloc", "density_backward", "density_scatter", "pressure_force", "autotune",
     "density", "SPHDensity",
     "status_string",
     "FP64", "FP32C", "F64", "F32", "BAND", "ROOT", "KNN", "KERNEL_M4", "KERNEL_WENDLAND_C6",
@@ -31,6 +31,7 @@ F64, F32 = 0, 1
 BAND, ROOT, KNN = 0, 1, 2
 ABI_VERSION = 1
 OK, E_INVALID, E_WORKSPACE, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4
+NOALLOC_SCRATCH_BYTES = 64 << 20
 ST_NOCONV = 1 << 16
 ST_HTOOLARGE = 1 << 17
 ST_BADINPUT = 1 << 18
@@ -43,6 +44,7 @@ EXPORTS = [
     "sph_status_string",
     "sph_last_hip_error",
     "sph_last_hip_error_string",
+    "sph_density_solve_noalloc",
 ]
 
 
@@ -105,6 +107,8 @@ def load():
     L.sph_sort.restype = C.c_int
     L.sph_density_solve.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P]
     L.sph_density_solve.restype = C.c_int
+    L.sph_density_solve_noalloc.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    L.sph_density_solve_noalloc.restype = C.c_int
     L.sph_density_backward.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, P, P, P, P, SZ, P]
     L.sph_density_backward.restype = C.c_int
     L.sph_density_scatter.argtypes = [PP, I64, I32, P, P, P, P, P, P, P, P, P, P, SZ, P]
@@ -316,6 +320,45 @@ def density_solve(x, y, z, m, h_init=None, params: Params | None = None, group_o
                                   _stream(dev))
     if rc != OK:
         raise SPHError(rc, "sph_density_solve")
+    res = dict(rho=rho, h=h, nw=nw, nngb=nngb, status=status)
+    if stats:
+        res["stats"] = st
+    return res
+
+
+def density_solve_noalloc(x, y, z, m, h_init=None, params: Params | None = None,
+                          group_offsets=None, stats=False, out=None):
+    """``sph_density_solve_noalloc``: as ``density_solve``, with the library's
+    fixed device scratch instead of a caller workspace (the C call allocates
+    nothing; this wrapper allocates the outputs unless ``out`` gives them).
+    Raises SPHError(E_WORKSPACE) when the set needs more than
+    NOALLOC_SCRATCH_BYTES of workspace.
+    """
+    torch = _torch()
+    params = params or default_params()
+    dev = _check_dev(x, y, z, m, h_init, group_offsets)
+    n = x.shape[0]
+    G = 0 if group_offsets is None else group_offsets.shape[0] - 1
+    _check_offsets(group_offsets, n)
+    dt = _io(params)
+    if out is None:
+        out = dict(rho=torch.empty(n, dtype=dt, device=dev),
+                   h=torch.empty(n, dtype=dt, device=dev),
+                   nw=torch.empty(n, dtype=dt, device=dev),
+                   nngb=torch.empty(n, dtype=torch.int32, device=dev),
+                   status=torch.empty(n, dtype=torch.int32, device=dev))
+    rho, h = out["rho"], out["h"]
+    nw, nngb, status = out.get("nw"), out.get("nngb"), out.get("status")
+    _check_dev(rho, h, nw, nngb, status)
+    prm = _with_strides(params, _stride_bytes(x, y, z, m, h_init),
+                        _stride_bytes(rho, h, nw, nngb, status))
+    st = torch.zeros(4, dtype=torch.int64, device=dev) if stats else None
+    rc = load().sph_density_solve_noalloc(C.byref(prm), n, G, _ptr(group_offsets), _ptr(x),
+                                          _ptr(y), _ptr(z), _ptr(m), _ptr(h_init), _ptr(rho),
+                                          _ptr(h), _ptr(nw), _ptr(nngb), _ptr(status),
+                                          _ptr(st), _stream(dev))
+    if rc != OK:
+        raise SPHError(rc, "sph_density_solve_noalloc")
     res = dict(rho=rho, h=h, nw=nw, nngb=nngb, status=status)
     if stats:
         res["stats"] = st

@@ -5,6 +5,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 namespace sph {
 
 static thread_local int g_last_hip = 0;
@@ -220,6 +222,37 @@ hipError_t run_clean_offsets(const Plan &pl, const int64_t *goff, hipStream_t st
     hipLaunchKernelGGL(k_clean_offsets, dim3(1), dim3(kCleanThreads), 0, st, pl.G, pl.n, goff,
                        pl.goff);
     return hipGetLastError();
+}
+
+// Scratch of sph_density_solve_noalloc: the workspace of a solve, held in the
+// library's own device memory.  Each device that the library runs on keeps
+// its copy until the process ends.  On the host `scratch` names a stand-in,
+// never the device memory: host code uses only the address that
+// hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocScratchBytes = (size_t)SPH_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of this device's scratch, looked up once per device with that
+// device current.  Returns hipSuccess and sets *out, or the failing error.
+static hipError_t scratch_ptr(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace sph
@@ -446,6 +479,24 @@ int sph_density_scatter(const sph_params *params, int64_t n, int32_t n_groups,
     if (e == hipSuccess) e = run_scatter(pl, goff, rho_s_out, rho_sym_out, nngb_s_out, st);
     if (e != hipSuccess) return hip_fail(e);
     return SPH_OK;
+}
+
+int sph_density_solve_noalloc(const sph_params *params, int64_t n, int32_t n_groups,
+                              const int64_t *group_offsets, const void *x, const void *y,
+                              const void *z, const void *m, const void *h_init, void *rho_out,
+                              void *h_out, void *nw_out, int32_t *nngb_out, int32_t *status_out,
+                              uint64_t *stats_out, void *stream) {
+    int rc = check_params(params, n, n_groups, group_offsets);
+    if (rc != SPH_OK) return rc;
+    Plan probe;
+    make_plan(params, n, n_groups, nullptr, &probe);
+    if (probe.total > kNoAllocScratchBytes) return SPH_E_WORKSPACE;
+    void *ws = nullptr;
+    const hipError_t e = scratch_ptr(&ws);
+    if (e != hipSuccess) return hip_fail(e);
+    return sph_density_solve(params, n, n_groups, group_offsets, x, y, z, m, h_init, rho_out,
+                             h_out, nw_out, nngb_out, status_out, stats_out, ws,
+                             kNoAllocScratchBytes, stream);
 }
 
 const char *sph_status_string(int code) {

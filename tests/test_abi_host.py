@@ -254,3 +254,18 @@ def test_size_limits():
     for G, ok in ((1, True), (65535, True), (0, False), (65536, False)):
         rc = lib.sph_workspace_size(C.byref(g), 1000, G, C.byref(out))
         assert rc == (sph.OK if ok else sph.E_INVALID), G
+
+
+def test_noalloc_host_checks():
+    # the no-workspace solve validates like sph_density_solve and rejects a set
+    # whose workspace would exceed its fixed scratch before touching a device
+    lib = _lib()
+    p = sph.default_params()
+    dummy = C.c_void_p(256)
+    args = [dummy] * 5 + [dummy, dummy, None, None, None, None, None]
+    big = 1 << 20
+    assert sph.workspace_size(p, big) > sph.NOALLOC_SCRATCH_BYTES
+    assert lib.sph_density_solve_noalloc(C.byref(p), big, 0, None, *args) == sph.E_WORKSPACE
+    bad = sph.default_params(n_target=-1.0)
+    assert lib.sph_density_solve_noalloc(C.byref(bad), 1000, 0, None, *args) == sph.E_INVALID
+    assert lib.sph_density_solve_noalloc(C.byref(p), -5, 0, None, *args) == sph.E_INVALID
