@@ -32,6 +32,10 @@ METRIC = "particle-neighbour interactions/s and particles/s for density+h solve,
 PEAK_FP32 = 157.3e12   # MI355X vector FP32 (packed) FLOP/s
 PEAK_FP64 = 78.6e12    # MI355X vector FP64 FLOP/s
 FLOP_CAND = 8.0        # 3 differences + r^2 (one multiply, two FMA; FMA = 2)
+# A candidate streamed from a neighbour cell is first tested once against the
+# tile's region (its distance from the particles' bounding box, the same 3
+# differences and r^2) before the per-particle tests: 8 FLOP per region test.
+FLOP_REGION = 8.0
 # Algorithmic FLOP per in-range pair, the headline weights: the root, q, the
 # spline's f and f', and the three sums S0, S1, R: 22 in FP64; the FP32C form
 # adds a Kahan compensation to each of the three sums (3 x 3): 31.
@@ -101,7 +105,7 @@ def run_form(sph, torch, d, ps, precision, steps, warmup, ev):
         ev.hip.hipEventDestroy(a)
         ev.hip.hipEventDestroy(b)
     return dict(ms_per_step=1e3 * wall / steps, kernel_ms=float(np.mean(kern_ms)),
-                kernel_ms_median=float(np.median(kern_ms)), pairs=int(st[0]), cands=int(st[1]), passes=int(st[2]),
+                kernel_ms_median=float(np.median(kern_ms)), pairs=int(st[0]), cands=int(st[1]), passes=int(st[2]), region=int(st[3]),
                 final_pairs=int(nngb.astype(np.int64).sum()),
                 flagged=int(((status >> 16) != 0).sum()),
                 _rho=outs["rho"].cpu().numpy(), _h=outs["h"].cpu().numpy())
@@ -136,18 +140,20 @@ def _executed(summary, flop, kms):
     return out
 
 
-def alu_roofline(cands, pairs, kms, form, kernel="k_solve"):
+def alu_roofline(cands, pairs, kms, form, kernel="k_solve", region=0):
     """Roofline of one density-kernel launch: algorithmic FLOP (8 per candidate
     test, FLOP_PAIR per in-range pair) over the launch's HIP-event time, and
     the same with this kernel's own per-pair count beside it."""
     peak = PEAK_FP32 if form == "fp32c" else PEAK_FP64
-    flop = FLOP_CAND * cands + FLOP_PAIR[form] * pairs
-    flop_k = FLOP_CAND * cands + FLOP_PAIR_KERNEL[form] * pairs
+    flop = FLOP_REGION * region + FLOP_CAND * cands + FLOP_PAIR[form] * pairs
+    flop_k = FLOP_REGION * region + FLOP_CAND * cands + FLOP_PAIR_KERNEL[form] * pairs
     sec = kms * 1e-3
     return {"bound": "alu", "achieved": flop / sec / 1e12, "peak": peak / 1e12,
             "unit": "TFLOP/s", "frac": flop / sec / peak, "kernel": kernel, "kernel_ms": kms,
             "flop_per_launch": flop,
-            "flop_weights": {"candidate": FLOP_CAND, "pair": FLOP_PAIR[form]},
+            "flop_weights": {"region_test": FLOP_REGION, "candidate": FLOP_CAND,
+                             "pair": FLOP_PAIR[form]},
+            "region_tests": region,
             "kernel_counted": {"flop_per_launch": flop_k, "pair": FLOP_PAIR_KERNEL[form],
                                "achieved": flop_k / sec / 1e12, "frac": flop_k / sec / peak}}
 
@@ -240,6 +246,7 @@ def run_batched(sph, torch, steps, warmup, ev, name="groups10k"):
     torch.cuda.synchronize()
     pairs = int(st["stats"][0].item())
     cands = int(st["stats"][1].item())
+    region = int(st["stats"][3].item())
     final_pairs = int(st["nngb"].to(torch.int64).sum().item())
     flagged = int(((st["status"] >> 16) != 0).sum().item())
     side = torch.cuda.Stream()
@@ -264,7 +271,7 @@ def run_batched(sph, torch, steps, warmup, ev, name="groups10k"):
     del graph
     kms = kernel_ms(ev, p, lambda: sph.density_solve(d["x"], d["y"], d["z"], d["m"],
                                                      d["h_init"], p, goff, ws=ws), steps)
-    roof = alu_roofline(cands, pairs, kms, "fp32c")
+    roof = alu_roofline(cands, pairs, kms, "fp32c", region=region)
     roof["replay_frac"] = roof["frac"] * kms / ms   # the same work over the whole replay
     return {"workload": f"{BATCHED[name]}, {n} particles, N_t = 32 +- 1, FP32C, autotuned, "
                         "sort + solve replayed from one HIP graph",
@@ -300,6 +307,7 @@ def run_large(sph, torch, steps, ev):
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
     cands = int(o["stats"][1].item())
+    region = int(o["stats"][3].item())
     kms = kernel_ms(ev, p, lambda: sph.density_solve(d["x"], d["y"], d["z"], d["m"],
                                                      d["h_init"], p, ws=ws), steps)
     del o
@@ -314,7 +322,7 @@ def run_large(sph, torch, steps, ev):
             "n": n, "ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
             "particles_per_s": n / (ms * 1e-3), "pairs_per_step": pairs,
             "candidates_per_step": cands, "flagged": flagged, "kernel_ms": kms,
-            "roofline": alu_roofline(cands, pairs, kms, "fp32c"), "sort": srt}
+            "roofline": alu_roofline(cands, pairs, kms, "fp32c", region=region), "sort": srt}
 
 
 def run_wendland(sph, torch, d, ps, steps, ev):
@@ -338,9 +346,10 @@ def run_wendland(sph, torch, d, ps, steps, ev):
         torch.cuda.synchronize()
         ms = a.elapsed_time(b) / steps
         cands = int(o["stats"][1].item())
+        region = int(o["stats"][3].item())
         kms = kernel_ms(ev, p, lambda: sph.density_solve(d["x"], d["y"], d["z"], d["m"],
                                                          d["h_init"], p, ws=ws), steps)
-        flop = FLOP_CAND * cands + FLOP_PAIR_WC6[name] * pairs
+        flop = FLOP_REGION * region + FLOP_CAND * cands + FLOP_PAIR_WC6[name] * pairs
         peak = PEAK_FP32 if name == "fp32c" else PEAK_FP64
         out[name] = {"ms_per_step": ms, "interactions_per_s": pairs / (ms * 1e-3),
                      "particles_per_s": ps.n / (ms * 1e-3), "pairs_per_step": pairs,
@@ -393,13 +402,14 @@ def run_knn(sph, torch, d, ps, steps, dk=14.0):
                                stats=True)
         torch.cuda.synchronize()
         cands = int(st["stats"][1].item())
+        region = int(st["stats"][3].item())
         final_pairs = int(st["nngb"].to(torch.int64).sum().item())
         kms = kernel_ms(HipEvents(), p, lambda: sph.density_solve(
             d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws), steps)
         # algorithmic work, a lower bound: every candidate test of the three
         # stages, and the Wendland C6 pair terms of the evaluation stage only
         form = "fp32c" if prec == sph.FP32C else "fp64"
-        flop = FLOP_CAND * cands + FLOP_PAIR_WC6[form] * final_pairs
+        flop = FLOP_REGION * region + FLOP_CAND * cands + FLOP_PAIR_WC6[form] * final_pairs
         peak = PEAK_FP32 if prec == sph.FP32C else PEAK_FP64
         out[name] = {"ms_per_step": ms, "particles_per_s": ps.n / (ms * 1e-3),
                      "flagged": flagged, "max_count_updates": iters, "kernel_ms": kms,
@@ -1070,7 +1080,7 @@ def main():
         print(f"[bench] large {big}", file=sys.stderr, flush=True)
 
     def roof(r, form):
-        out = alu_roofline(r["cands"], r["pairs"], r["kernel_ms"], form)
+        out = alu_roofline(r["cands"], r["pairs"], r["kernel_ms"], form, region=r["region"])
         out["traffic"] = measured_traffic() if form == "fp32c" else None
         out["kernel_ms_median"] = r["kernel_ms_median"]
         if form == "fp32c":

@@ -222,8 +222,11 @@ int sph_sort(const sph_params *params, int64_t n, int32_t n_groups,
  * of j with r_ij^2 < h^2, i included), status_out (int32, bits above).
  * Any output may be NULL except rho_out and h_out.
  * stats_out: NULL or device uint64[4], overwritten: [0] in-range pairs
- * evaluated over all trial h, [1] candidate pairs tested, [2] density
- * passes made (sum over particles of updates + 1), [3] reserved (0). */
+ * evaluated over all trial h, [1] candidate pairs tested (particle against
+ * candidate), [2] density passes made (sum over particles of updates + 1),
+ * [3] candidates streamed from neighbour cells and tested once against the
+ * region of the particles being solved together (the bounding box of their
+ * positions widened by their largest h), before the pair tests. */
 int sph_density_solve(const sph_params *params, int64_t n, int32_t n_groups,
                       const int64_t *group_offsets,
                       const void *x, const void *y, const void *z, const void *m,

@@ -11,9 +11,12 @@
 //    tile's active particles define a region; the Morton cells covering it at
 //    a level whose cell side is at least the tile's largest h are culled
 //    against every active particle's sphere, and the surviving cells'
-//    contiguous runs of the sorted arrays are streamed through LDS in
-//    coalesced chunks of 64 candidates.  Every lane then reads each candidate
-//    by broadcast and tests it against its own h.  Tiles that straddle a
+//    contiguous runs of the sorted arrays are streamed in coalesced load
+//    rounds of 64 candidates.  Each candidate is tested once against the
+//    region of the (sub-)tile -- its particles' bounding box widened by their
+//    largest h -- and the ones inside are appended (ballot slots) to a staging
+//    buffer in LDS; whenever 64 are staged, every lane reads them by broadcast
+//    and tests them against its own particle and h.  Tiles that straddle a
 //    large jump of the Morton curve are split in halves until the region is
 //    small.
 //  * The in-support test of Listing 1 is an exact r^2 < h^2 compare;
@@ -276,14 +279,19 @@ __device__ inline void cell_range_group(const SolveArgs &a, int32_t g, uint64_t 
 template <int PREC>
 struct CandLDS;
 
+// Staging buffer of the candidate stream: the candidates that passed the
+// sub-tile's region test and wait to be tested by its particles.  Up to 63
+// wait between test rounds and a load round adds up to 64, so 127 entries.
+constexpr int kStage = 128;
+
 template <>
 struct CandLDS<SPH_FP64> {
-    double x[64], y[64], z[64], m[64], shx[64], shy[64], shz[64];
+    double x[kStage], y[kStage], z[kStage], m[kStage], shx[kStage], shy[kStage], shz[kStage];
 };
 
 template <>
 struct CandLDS<SPH_FP32C> {
-    float4 c[64];  // x, y, z relative to the tile origin (grid units), m
+    float4 c[kStage];  // x, y, z relative to the tile origin (grid units), m
 };
 
 struct Sums {
@@ -380,13 +388,19 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     __shared__ double act_H[64];
     __shared__ int32_t rg_start[64], rg_excl[64], rg_code[64];
     __shared__ CandLDS<PREC> cd;
+    __shared__ float4 regbox[2];  // FP32C region of the current sub-tile
+    // FP32C: the h iteration's bracket and counters wait in LDS during a pass
+    // (only h is needed there), which keeps the kernel within 128 VGPRs
+    constexpr bool kPark = PREC == SPH_FP32C;
+    __shared__ double park_d[kPark ? 3 : 1][64];
+    __shared__ int32_t park_i[kPark ? 4 : 1][64];
 
     const int l = threadIdx.x;
     const int p = l & (P - 1);   // particle slot in the tile
     const int kk = l / P;        // copy index of this lane
     const int B = a.bits;
     constexpr uint64_t kTileMask = P == 64 ? ~0ull : ((1ull << P) - 1ull);
-    uint64_t cnt_pairs = 0, cnt_cands = 0, cnt_passes = 0;  // wave totals
+    uint64_t cnt_pairs = 0, cnt_cands = 0, cnt_passes = 0, cnt_region = 0;  // wave totals
 
     for (;;) {
         int item = 0;
@@ -507,7 +521,13 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             sm.n = 0;
             float pa0 = 0.f, pa1 = 0.f, par = 0.f;  // FP32C plain partial sums
             int pchunks = 0;                        // chunks since the last fold
-            uint64_t pass_cands = 0;  // wave total: candidates streamed x particles
+            uint64_t pass_cands = 0;   // wave total: candidates tested x particles
+            uint64_t pass_region = 0;  // wave total: candidates tested against a region
+            if (kPark) {
+                park_d[0][l] = hs.lo; park_d[1][l] = hs.hi; park_d[2][l] = hs.wprev;
+                park_i[0][l] = hs.it; park_i[1][l] = hs.flags;
+                park_i[2][l] = hs.nlo; park_i[3][l] = hs.nhi;
+            }
             __syncthreads();
 
             // sub-tiles: lane ranges [la, lb) of the active set, split in halves
@@ -570,6 +590,150 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 const float piy = (float)(qyi - o1) + fyi;
                 const float piz = (float)(qzi - o2) + fzi;
 
+                // region of the sub-tile: its particles' bounding box (exactly
+                // the coordinates its pair tests use) widened by Hm.  A
+                // candidate farther than that from the box is out of every
+                // sphere: the margin 2^-16 of Hm^2 on top of Hm's own covers
+                // the rounding of both tests
+                const int nsub = __popcll(sub);
+                double bx0 = 0.0, bx1 = 0.0, by0 = 0.0, by1 = 0.0, bz0 = 0.0, bz1 = 0.0, Hc2 = 0.0;
+                if (PREC == SPH_FP64) {
+                    bx0 = uniform_d(wave_min(in_sub ? xi : INFINITY));
+                    by0 = uniform_d(wave_min(in_sub ? yi : INFINITY));
+                    bz0 = uniform_d(wave_min(in_sub ? zi : INFINITY));
+                    bx1 = uniform_d(wave_max(in_sub ? xi : -INFINITY));
+                    by1 = uniform_d(wave_max(in_sub ? yi : -INFINITY));
+                    bz1 = uniform_d(wave_max(in_sub ? zi : -INFINITY));
+                    const double Ha = Hm / sc;
+                    Hc2 = Ha * Ha * (1.0 + 0x1p-16);
+                } else {
+                    // kept in LDS: the scalar registers are taken by the cell
+                    // enumeration, and these are read once per load round
+                    const float a0 = wave_min(in_sub ? pix : INFINITY);
+                    const float a1 = wave_min(in_sub ? piy : INFINITY);
+                    const float a2 = wave_min(in_sub ? piz : INFINITY);
+                    const float b0 = wave_max(in_sub ? pix : -INFINITY);
+                    const float b1 = wave_max(in_sub ? piy : -INFINITY);
+                    const float b2 = wave_max(in_sub ? piz : -INFINITY);
+                    if (l == 0) {
+                        regbox[0] = make_float4(a0, a1, a2, (float)(Hm * Hm * (1.0 + 0x1p-16)));
+                        regbox[1] = make_float4(b0, b1, b2, 0.f);
+                    }
+                }
+                int staged = 0;  // candidates in the staging buffer (wave-uniform)
+
+                // one test round: every particle of the sub-tile against the
+                // first mc staged candidates (mc <= 64; slots mc..63 padded)
+                auto test_round = [&](const int mc) {
+                        // candidates per copy, rounded up to the unroll of 4: the slots
+                        // past mc hold padding, and 4 * ceil(mc / 4S) * S <= 64
+                        const int nu = (((mc + S - 1) / S) + 3) & ~3;
+                        if (SEL && in_sub) {
+                            // selection: squared distances inside h into the heap
+                            if (PREC == SPH_FP64) {
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
+                                for (int t = kk; t < mc; t += S) {
+                                    const double dx = (c.x[t] - xi) + c.shx[t];
+                                    const double dy = (c.y[t] - yi) + c.shy[t];
+                                    const double dz = (c.z[t] - zi) + c.shz[t];
+                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                                    if (r2 < h2) {
+                                        ++sel_n;
+                                        sel_insert<CAP>(selheap, l, sel_hc, (HeapT)r2, sel_min);
+                                    }
+                                }
+                            } else {
+                                // binary32 coordinates, differences and squares in
+                                // binary64 (grid units).  The sphere is widened by a
+                                // relative 2^-19 so that it holds every particle the
+                                // count stage's binary32 test counted inside h (its
+                                // rounding stays below 2^-21 of r^2): the list then
+                                // holds at least K, and its order is the binary64 one
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
+                                const double hq2 = hq * hq * (1.0 + 0x1p-18);
+                                for (int t = kk; t < mc; t += S) {
+                                    const float4 cj = c.c[t];
+                                    const double dx = (double)cj.x - (double)pix;
+                                    const double dy = (double)cj.y - (double)piy;
+                                    const double dz = (double)cj.z - (double)piz;
+                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                                    if (r2 < hq2) {
+                                        ++sel_n;
+                                        sel_insert<CAP>(selheap, l, sel_hc, (HeapT)r2, sel_min);
+                                    }
+                                }
+                            }
+                        } else if (in_sub) {
+                            // binary32: branch free.  With one particle-candidate
+                            // pair per lane a wave almost always holds an in-range
+                            // pair, so a branch would not skip the pair terms, only
+                            // keep the compiler from issuing the unrolled LDS reads
+                            // together.  An out-of-range pair is evaluated at q = 1,
+                            // where every term is exactly zero; staged candidates
+                            // have finite masses (invalid particles never pass the
+                            // region test), so it adds exact zeros
+                            if (PREC == SPH_FP64) {
+                                // binary64 keeps the branch: its pair terms (a
+                                // binary64 square root among them) need more
+                                // registers than a branch-free unrolled loop leaves
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
+                                const double hinv = 1.0 / hs.h;
+#pragma unroll 4
+                                for (int u = 0; u < nu; ++u) {
+                                    const int t = u * S + kk;
+                                    const double dx = (c.x[t] - xi) + c.shx[t];
+                                    const double dy = (c.y[t] - yi) + c.shy[t];
+                                    const double dz = (c.z[t] - zi) + c.shz[t];
+                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
+                                    if (r2 < h2) {
+                                        // the exact-K count stage needs the count only
+                                        if (STAGE != 1) {
+                                            // scaled pair terms (factors applied to the totals)
+                                            const double q = sqrt(r2) * hinv;
+                                            double fh, gs;
+                                            KT::template terms<double>(q, q * q, fh, gs);
+                                            sm.d0 += fh;
+                                            sm.d1 += gs;
+                                            sm.dr += c.m[t] * fh;
+                                        }
+                                        sm.n += 1;
+                                    }
+                                }
+                            } else {
+                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
+                                // cascade summation: up to 64 terms per lane in plain
+                                // binary32 (S chunks), then Kahan-compensated into the totals
+#pragma unroll 4
+                                for (int u = 0; u < nu; ++u) {
+                                    const float4 cj = c.c[u * S + kk];
+                                    const float dx = cj.x - pix;
+                                    const float dy = cj.y - piy;
+                                    const float dz = cj.z - piz;
+                                    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                                    const bool in = r2 < h2f;
+                                    if (STAGE != 1) {
+                                        // scaled pair terms (factors applied to the totals)
+                                        const float q2 = in ? r2 * ih2 : 1.0f;
+                                        const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
+                                        float fh, gs;
+                                        KT::template terms<float>(q, q2, fh, gs);
+                                        pa0 += fh;
+                                        pa1 += gs;
+                                        par = __builtin_fmaf(cj.w, fh, par);
+                                    }
+                                    sm.n += in ? 1 : 0;
+                                }
+                            }
+                        }
+                        if (PREC == SPH_FP32C && ++pchunks == S) {
+                            kahan(sm.f0, sm.c0, pa0);
+                            kahan(sm.f1, sm.c1, pa1);
+                            kahan(sm.fr, sm.cr, par);
+                            pa0 = pa1 = par = 0.f;
+                            pchunks = 0;
+                        }
+                };
+
                 for (int64_t kb = 0; kb < K; kb += 64) {
                     const int64_t k = kb + l;
                     bool pass = false;
@@ -621,148 +785,107 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                         rg_code[slot] = code;
                     }
                     __syncthreads();
-                    pass_cands += (uint64_t)total * (uint64_t)__popcll(sub);
                     for (int cbase = 0; cbase < total; cbase += 64) {
+                        // load round: each lane takes one candidate of the
+                        // region's cells and keeps it if it lies within Hm of
+                        // the sub-tile's bounding box; the kept ones are
+                        // appended to the staging buffer (ballot slots)
                         const int gidx = cbase + l;
-                        if (gidx >= total) {
-                            // padding: a candidate at infinite distance is never in range
-                            if (PREC == SPH_FP64) {
-                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
-                                c.x[l] = INFINITY; c.y[l] = INFINITY; c.z[l] = INFINITY;
-                                c.m[l] = 0.0;
-                                c.shx[l] = 0.0; c.shy[l] = 0.0; c.shz[l] = 0.0;
-                            } else {
-                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
-                                c.c[l] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
-                            }
-                        } else {
+                        bool keep = false;
+                        float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
+                        double4 cdv = make_double4(0.0, 0.0, 0.0, 0.0);
+                        double csx = 0.0, csy = 0.0, csz = 0.0;
+                        if (gidx < total) {
                             const int lo = range_of(rg_excl, nr, gidx);
                             const int64_t j = (int64_t)rg_start[lo] + (gidx - rg_excl[lo]);
                             const int cc = rg_code[lo];
                             const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1,
                                       sh2 = ((cc >> 4) & 3) - 1;
                             if (PREC == SPH_FP64) {
-                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
-                                const double4 p4 = a.sp[j];
-                                c.x[l] = p4.x;
-                                c.y[l] = p4.y;
-                                c.z[l] = p4.z;
-                                c.m[l] = p4.w;
-                                c.shx[l] = (double)sh0 * a.box;
-                                c.shy[l] = (double)sh1 * a.box;
-                                c.shz[l] = (double)sh2 * a.box;
+                                cdv = a.sp[j];
+                                csx = (double)sh0 * a.box;
+                                csy = (double)sh1 * a.box;
+                                csz = (double)sh2 * a.box;
+                                const double px = cdv.x + csx, py = cdv.y + csy, pz = cdv.z + csz;
+                                const double ex = px - fmin(fmax(px, bx0), bx1);
+                                const double ey = py - fmin(fmax(py, by0), by1);
+                                const double ez = pz - fmin(fmax(pz, bz0), bz1);
+                                keep = (ex * ex + ey * ey) + ez * ez <= Hc2;
                             } else {
-                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
                                 const int32_t W = 1 << B;
                                 const int4 q4 = a.qp[j];
                                 const float4 f4 = a.fp[j];
-                                c.c[l] = make_float4((float)(q4.x + sh0 * W - o0) + f4.x,
-                                                     (float)(q4.y + sh1 * W - o1) + f4.y,
-                                                     (float)(q4.z + sh2 * W - o2) + f4.z,
-                                                     __int_as_float(q4.w));
+                                cf = make_float4((float)(q4.x + sh0 * W - o0) + f4.x,
+                                                 (float)(q4.y + sh1 * W - o1) + f4.y,
+                                                 (float)(q4.z + sh2 * W - o2) + f4.z,
+                                                 __int_as_float(q4.w));
+                                const float4 rl = regbox[0], rh = regbox[1];
+                                const float ex = cf.x - fminf(fmaxf(cf.x, rl.x), rh.x);
+                                const float ey = cf.y - fminf(fmaxf(cf.y, rl.y), rh.y);
+                                const float ez = cf.z - fminf(fmaxf(cf.z, rl.z), rh.z);
+                                keep = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)) <= rl.w;
                             }
                         }
-                        __syncthreads();
-                        const int mc = total - cbase < 64 ? total - cbase : 64;  // wave-uniform
-                        // candidates per copy, rounded up to the unroll of 4: the slots
-                        // past mc hold padding, and 4 * ceil(mc / 4S) * S <= 64
-                        const int nu = (((mc + S - 1) / S) + 3) & ~3;
-                        if (SEL && in_sub) {
-                            // selection: squared distances inside h into the heap
+                        const uint64_t km = __ballot(keep);
+                        const int nk = __popcll(km);
+                        if (keep) {
+                            const int slot = staged + (int)mbcnt(km);
                             if (PREC == SPH_FP64) {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
-                                for (int t = kk; t < mc; t += S) {
-                                    const double dx = (c.x[t] - xi) + c.shx[t];
-                                    const double dy = (c.y[t] - yi) + c.shy[t];
-                                    const double dz = (c.z[t] - zi) + c.shz[t];
-                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                                    if (r2 < h2) {
-                                        ++sel_n;
-                                        sel_insert<CAP>(selheap, l, sel_hc, (HeapT)r2, sel_min);
-                                    }
-                                }
-                            } else {
-                                // binary32 coordinates, differences and squares in
-                                // binary64 (grid units).  The sphere is widened by a
-                                // relative 2^-19 so that it holds every particle the
-                                // count stage's binary32 test counted inside h (its
-                                // rounding stays below 2^-21 of r^2): the list then
-                                // holds at least K, and its order is the binary64 one
-                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
-                                const double hq2 = hq * hq * (1.0 + 0x1p-18);
-                                for (int t = kk; t < mc; t += S) {
-                                    const float4 cj = c.c[t];
-                                    const double dx = (double)cj.x - (double)pix;
-                                    const double dy = (double)cj.y - (double)piy;
-                                    const double dz = (double)cj.z - (double)piz;
-                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                                    if (r2 < hq2) {
-                                        ++sel_n;
-                                        sel_insert<CAP>(selheap, l, sel_hc, (HeapT)r2, sel_min);
-                                    }
-                                }
-                            }
-                        } else if (in_sub) {
-                            if (PREC == SPH_FP64) {
-                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
-                                const double hinv = 1.0 / hs.h;
-#pragma unroll 4
-                                for (int u = 0; u < nu; ++u) {
-                                    const int t = u * S + kk;
-                                    const double dx = (c.x[t] - xi) + c.shx[t];
-                                    const double dy = (c.y[t] - yi) + c.shy[t];
-                                    const double dz = (c.z[t] - zi) + c.shz[t];
-                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                                    if (r2 < h2) {
-                                        // the exact-K count stage needs the count only
-                                        if (STAGE != 1) {
-                                            // scaled pair terms (factors applied to the totals)
-                                            const double q = sqrt(r2) * hinv;
-                                            double fh, gs;
-                                            KT::template terms<double>(q, q * q, fh, gs);
-                                            sm.d0 += fh;
-                                            sm.d1 += gs;
-                                            sm.dr += c.m[t] * fh;
-                                        }
-                                        sm.n += 1;
-                                    }
-                                }
+                                c.x[slot] = cdv.x; c.y[slot] = cdv.y; c.z[slot] = cdv.z;
+                                c.m[slot] = cdv.w;
+                                c.shx[slot] = csx; c.shy[slot] = csy; c.shz[slot] = csz;
                             } else {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
-                                // cascade summation: up to 64 terms per lane in plain
-                                // binary32 (S chunks), then Kahan-compensated into the totals
-#pragma unroll 4
-                                for (int u = 0; u < nu; ++u) {
-                                    const float4 cj = c.c[u * S + kk];
-                                    const float dx = cj.x - pix;
-                                    const float dy = cj.y - piy;
-                                    const float dz = cj.z - piz;
-                                    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                                    if (r2 < h2f) {
-                                        if (STAGE != 1) {
-                                            // scaled pair terms (factors applied to the totals)
-                                            const float q2 = r2 * ih2;
-                                            const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
-                                            float fh, gs;
-                                            KT::template terms<float>(q, q2, fh, gs);
-                                            pa0 += fh;
-                                            pa1 += gs;
-                                            par = __builtin_fmaf(cj.w, fh, par);
-                                        }
-                                        sm.n += 1;
-                                    }
-                                }
+                                c.c[slot] = cf;
                             }
                         }
-                        if (PREC == SPH_FP32C && ++pchunks == S) {
-                            kahan(sm.f0, sm.c0, pa0);
-                            kahan(sm.f1, sm.c1, pa1);
-                            kahan(sm.fr, sm.cr, par);
-                            pa0 = pa1 = par = 0.f;
-                            pchunks = 0;
+                        staged += nk;
+                        pass_cands += (uint64_t)nk * (uint64_t)nsub;
+                        pass_region += (uint64_t)(total - cbase < 64 ? total - cbase : 64);
+                        if (staged >= 64) {
+                            __syncthreads();
+                            test_round(64);
+                            __syncthreads();
+                            // the entries past the round move to the front
+                            if (l < staged - 64) {
+                                if (PREC == SPH_FP64) {
+                                    auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
+                                    const double t0 = c.x[64 + l], t1 = c.y[64 + l], t2 = c.z[64 + l];
+                                    const double t3 = c.m[64 + l], t4 = c.shx[64 + l];
+                                    const double t5 = c.shy[64 + l], t6 = c.shz[64 + l];
+                                    c.x[l] = t0; c.y[l] = t1; c.z[l] = t2; c.m[l] = t3;
+                                    c.shx[l] = t4; c.shy[l] = t5; c.shz[l] = t6;
+                                } else {
+                                    auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
+                                    const float4 t = c.c[64 + l];
+                                    c.c[l] = t;
+                                }
+                            }
+                            staged -= 64;
+                            __syncthreads();
                         }
-                        __syncthreads();
                     }
+                }
+                // the sub-tile's last, partial round (its origin and lanes are
+                // its own): slots past the staged candidates hold padding, a
+                // candidate at infinite distance that is never in range
+                if (staged > 0) {
+                    if (l >= staged) {
+                        if (PREC == SPH_FP64) {
+                            auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
+                            c.x[l] = INFINITY; c.y[l] = INFINITY; c.z[l] = INFINITY;
+                            c.m[l] = 0.0;
+                            c.shx[l] = 0.0; c.shy[l] = 0.0; c.shz[l] = 0.0;
+                        } else {
+                            auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
+                            c.c[l] = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+                        }
+                    }
+                    __syncthreads();
+                    test_round(staged);
+                    __syncthreads();
+                    staged = 0;
                 }
             }
 
@@ -792,6 +915,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             if (a.stats) {
                 cnt_pairs += uniform_u64(wave_sum<uint64_t>(!done && kk == 0 ? (uint64_t)npair : 0));
                 cnt_cands += pass_cands;
+                cnt_region += pass_region;
                 cnt_passes += (uint64_t)__popcll(am);
             }
             if (SEL) {
@@ -829,6 +953,11 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 }
                 done = true;
             }
+            if (kPark) {
+                hs.lo = park_d[0][l]; hs.hi = park_d[1][l]; hs.wprev = park_d[2][l];
+                hs.it = park_i[0][l]; hs.flags = park_i[1][l];
+                hs.nlo = park_i[2][l]; hs.nhi = park_i[3][l];
+            }
             if (!SEL && !done) {
                 const double nwv = KT::count * S0;
                 const double dndh = -KT::count * S1 / hs.h;
@@ -854,6 +983,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         atomicAdd((unsigned long long *)&a.stats[0], (unsigned long long)cnt_pairs);
         atomicAdd((unsigned long long *)&a.stats[1], (unsigned long long)cnt_cands);
         atomicAdd((unsigned long long *)&a.stats[2], (unsigned long long)cnt_passes);
+        atomicAdd((unsigned long long *)&a.stats[3], (unsigned long long)cnt_region);
     }
 }
 
