@@ -386,12 +386,20 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     constexpr int S = 64 / P;
     __shared__ double act_t[3][64];
     __shared__ double act_H[64];
-    __shared__ int32_t rg_start[64], rg_excl[64], rg_code[64];
+    // candidate ranges of the current cell batch: (sorted slot minus the
+    // range's first stream position, image code) and the stream positions at
+    // which ranges start; rg_mark maps a load round's slots to range starts
+    __shared__ int2 rg_so[64];
+    __shared__ int32_t rg_excl[64], rg_mark[64];
     __shared__ CandLDS<PREC> cd;
     __shared__ float4 regbox[2];  // FP32C region of the current sub-tile
     // FP32C: the h iteration's bracket and counters wait in LDS during a pass
-    // (only h is needed there), which keeps the kernel within 128 VGPRs
+    // (only h is needed there), and each lane's own particle (grid cell,
+    // fraction) is read from LDS where needed, which keeps the kernel within
+    // 128 VGPRs
     constexpr bool kPark = PREC == SPH_FP32C;
+    __shared__ int4 own_q[kPark ? 64 : 1];
+    __shared__ float4 own_f[kPark ? 64 : 1];
     __shared__ double park_d[kPark ? 3 : 1][64];
     __shared__ int32_t park_i[kPark ? 4 : 1][64];
 
@@ -435,8 +443,6 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         const bool mine = s < e;
         // this lane's particle
         double xi = 0.0, yi = 0.0, zi = 0.0;  // FP64 absolute position
-        int32_t qxi = 0, qyi = 0, qzi = 0;    // FP32C grid coordinates
-        float fxi = 0.f, fyi = 0.f, fzi = 0.f;
         HState hs;
         hs.h = mine ? (SEL ? a.knn_h[s] : a.sh0[s]) : 1.0;
         hs.lo = 0.0;
@@ -463,9 +469,9 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             } else {
                 const int4 q4 = a.qp[s];
                 const float4 f4 = a.fp[s];
-                qxi = q4.x; qyi = q4.y; qzi = q4.z;
-                fxi = f4.x; fyi = f4.y; fzi = f4.z;
-                valid = !isnan(fxi);
+                own_q[l] = q4;
+                own_f[l] = f4;
+                valid = !isnan(f4.x);
             }
         }
         // grid-unit position (culling), recomputed where needed
@@ -473,9 +479,11 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             if (PREC == SPH_FP64) {
                 tx = (xi - org0) * sc; ty = (yi - org1) * sc; tz = (zi - org2) * sc;
             } else {
-                tx = (double)qxi + (double)fxi;
-                ty = (double)qyi + (double)fyi;
-                tz = (double)qzi + (double)fzi;
+                const int4 q4 = own_q[l];
+                const float4 f4 = own_f[l];
+                tx = (double)q4.x + (double)f4.x;
+                ty = (double)q4.y + (double)f4.y;
+                tz = (double)q4.z + (double)f4.z;
             }
         };
         if (mine && !valid && kk == 0) {
@@ -586,9 +594,14 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 const int32_t o0 = (int32_t)floor(0.5 * (mn0 + mx0));
                 const int32_t o1 = (int32_t)floor(0.5 * (mn1 + mx1));
                 const int32_t o2 = (int32_t)floor(0.5 * (mn2 + mx2));
-                const float pix = (float)(qxi - o0) + fxi;
-                const float piy = (float)(qyi - o1) + fyi;
-                const float piz = (float)(qzi - o2) + fzi;
+                float pix = 0.f, piy = 0.f, piz = 0.f;
+                if (PREC == SPH_FP32C) {
+                    const int4 q4 = own_q[l];
+                    const float4 f4 = own_f[l];
+                    pix = (float)(q4.x - o0) + f4.x;
+                    piy = (float)(q4.y - o1) + f4.y;
+                    piz = (float)(q4.z - o2) + f4.z;
+                }
 
                 // region of the sub-tile: its particles' bounding box (exactly
                 // the coordinates its pair tests use) widened by Hm.  A
@@ -780,25 +793,38 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                     __syncthreads();
                     if (pass) {
                         const int slot = (int)mbcnt(pm);
-                        rg_start[slot] = c_st;
+                        rg_so[slot] = make_int2(c_st - (incl - cnt), code);
                         rg_excl[slot] = incl - cnt;
-                        rg_code[slot] = code;
                     }
                     __syncthreads();
+                    // stream position at which range l starts (past the end for l >= nr)
+                    const int rstart = l < nr ? rg_excl[l] : INT_MAX;
+                    int rcarry = 0;  // range of the stream position before the round
                     for (int cbase = 0; cbase < total; cbase += 64) {
                         // load round: each lane takes one candidate of the
                         // region's cells and keeps it if it lies within Hm of
                         // the sub-tile's bounding box; the kept ones are
                         // appended to the staging buffer (ballot slots)
                         const int gidx = cbase + l;
+                        // range of each slot: the ranges starting inside the round
+                        // mark their first slot, a wave max-scan carries each mark
+                        // forward, and slots before the first mark keep the range
+                        // running at the end of the previous round
+                        rg_mark[l] = -1;
+                        const int pos = rstart - cbase;
+                        if (pos >= 0 && pos < 64) rg_mark[pos] = l;
+                        __builtin_amdgcn_wave_barrier();
+                        int rr = wave_max_scan(rg_mark[l]);
+                        rr = rr > rcarry ? rr : rcarry;
+                        rcarry = __builtin_amdgcn_readlane(rr, 63);
                         bool keep = false;
                         float4 cf = make_float4(0.f, 0.f, 0.f, 0.f);
                         double4 cdv = make_double4(0.0, 0.0, 0.0, 0.0);
                         double csx = 0.0, csy = 0.0, csz = 0.0;
                         if (gidx < total) {
-                            const int lo = range_of(rg_excl, nr, gidx);
-                            const int64_t j = (int64_t)rg_start[lo] + (gidx - rg_excl[lo]);
-                            const int cc = rg_code[lo];
+                            const int2 so = rg_so[rr];
+                            const int64_t j = (int64_t)(so.x + gidx);
+                            const int cc = so.y;
                             const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1,
                                       sh2 = ((cc >> 4) & 3) - 1;
                             if (PREC == SPH_FP64) {

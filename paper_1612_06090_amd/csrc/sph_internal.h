@@ -300,6 +300,27 @@ __device__ inline int range_of(const int32_t *excl, int nr, int g) {
     return r;
 }
 
+// Inclusive max-scan across the wave: Hillis-Steele within each row of 16
+// lanes by DPP row shifts of 1, 2, 4 and 8, then the GFX9 row broadcasts of
+// lane 15 (into rows 1 and 3) and lane 31 (into rows 2 and 3).  Lanes without
+// a DPP source take INT_MIN.
+__device__ inline int wave_max_scan(int v) {
+    int t;
+    t = __builtin_amdgcn_update_dpp(INT_MIN, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v = v > t ? v : t;
+    t = __builtin_amdgcn_update_dpp(INT_MIN, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v = v > t ? v : t;
+    t = __builtin_amdgcn_update_dpp(INT_MIN, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v = v > t ? v : t;
+    t = __builtin_amdgcn_update_dpp(INT_MIN, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v = v > t ? v : t;
+    t = __builtin_amdgcn_update_dpp(INT_MIN, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v = v > t ? v : t;
+    t = __builtin_amdgcn_update_dpp(INT_MIN, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    v = v > t ? v : t;
+    return v;
+}
+
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace sph
