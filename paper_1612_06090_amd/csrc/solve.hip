@@ -384,8 +384,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     using HeapT = typename std::conditional<PREC == SPH_FP64, double, float>::type;
     __shared__ HeapT selheap[SEL ? 64 * CAP : 1];
     constexpr int S = 64 / P;
-    __shared__ double act_t[3][64];
-    __shared__ double act_H[64];
+    __shared__ double act_t[3][P];
+    __shared__ double act_H[P];
     // candidate ranges of the current cell batch: (sorted slot minus the
     // range's first stream position, image code) and the stream positions at
     // which ranges start; rg_mark maps a load round's slots to range starts
@@ -393,15 +393,18 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     __shared__ int32_t rg_excl[64], rg_mark[64];
     __shared__ CandLDS<PREC> cd;
     __shared__ float4 regbox[2];  // FP32C region of the current sub-tile
-    // FP32C: the h iteration's bracket and counters wait in LDS during a pass
-    // (only h is needed there), and each lane's own particle (grid cell,
-    // fraction) is read from LDS where needed, which keeps the kernel within
-    // 128 VGPRs
-    constexpr bool kPark = PREC == SPH_FP32C;
-    __shared__ int4 own_q[kPark ? 64 : 1];
-    __shared__ float4 own_f[kPark ? 64 : 1];
-    __shared__ double park_d[kPark ? 3 : 1][64];
-    __shared__ int32_t park_i[kPark ? 4 : 1][64];
+    __shared__ double4 regbox_d[PREC == SPH_FP64 ? 2 : 1];  // FP64 region
+    // Per particle of the tile, in LDS rather than registers (the kernel
+    // stays within 128 VGPRs): its position (FP64: x, y, z; FP32C: grid cell
+    // and fraction), the h iteration's bracket and counters while a pass runs
+    // (only h is needed there), and the pass's sums
+    __shared__ double4 own_x[PREC == SPH_FP64 ? P : 1];
+    __shared__ int4 own_q[PREC == SPH_FP32C ? P : 1];
+    __shared__ float4 own_f[PREC == SPH_FP32C ? P : 1];
+    __shared__ double park_d[4][P];
+    __shared__ int32_t park_i[4][P];
+    __shared__ double acc_d[3][P];
+    __shared__ int32_t acc_n[P];
 
     const int l = threadIdx.x;
     const int p = l & (P - 1);   // particle slot in the tile
@@ -442,7 +445,6 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         const int64_t s = b + p;
         const bool mine = s < e;
         // this lane's particle
-        double xi = 0.0, yi = 0.0, zi = 0.0;  // FP64 absolute position
         HState hs;
         hs.h = mine ? (SEL ? a.knn_h[s] : a.sh0[s]) : 1.0;
         hs.lo = 0.0;
@@ -464,23 +466,26 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         if (mine) {
             if (PREC == SPH_FP64) {
                 const double4 p4 = a.sp[s];
-                xi = p4.x; yi = p4.y; zi = p4.z;
-                valid = !isnan(xi);
+                if (kk == 0) own_x[p] = p4;
+                valid = !isnan(p4.x);
             } else {
                 const int4 q4 = a.qp[s];
                 const float4 f4 = a.fp[s];
-                own_q[l] = q4;
-                own_f[l] = f4;
+                if (kk == 0) {
+                    own_q[p] = q4;
+                    own_f[p] = f4;
+                }
                 valid = !isnan(f4.x);
             }
         }
         // grid-unit position (culling), recomputed where needed
         auto grid_pos = [&](double &tx, double &ty, double &tz) {
             if (PREC == SPH_FP64) {
-                tx = (xi - org0) * sc; ty = (yi - org1) * sc; tz = (zi - org2) * sc;
+                const double4 o4 = own_x[p];
+                tx = (o4.x - org0) * sc; ty = (o4.y - org1) * sc; tz = (o4.z - org2) * sc;
             } else {
-                const int4 q4 = own_q[l];
-                const float4 f4 = own_f[l];
+                const int4 q4 = own_q[p];
+                const float4 f4 = own_f[p];
                 tx = (double)q4.x + (double)f4.x;
                 ty = (double)q4.y + (double)f4.y;
                 tz = (double)q4.z + (double)f4.z;
@@ -520,21 +525,15 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 act_t[2][p] = tz;
                 act_H[p] = done ? -1.0 : Hs;
             }
-            const double h2 = hs.h * hs.h;
-            const float ih2 = (float)(1.0 / (hq * hq));
-            const float h2f = (float)(hq * hq);
-            Sums sm;
-            sm.d0 = sm.d1 = sm.dr = 0.0;
-            sm.f0 = sm.f1 = sm.fr = sm.c0 = sm.c1 = sm.cr = 0.f;
-            sm.n = 0;
-            float pa0 = 0.f, pa1 = 0.f, par = 0.f;  // FP32C plain partial sums
-            int pchunks = 0;                        // chunks since the last fold
             uint64_t pass_cands = 0;   // wave total: candidates tested x particles
             uint64_t pass_region = 0;  // wave total: candidates tested against a region
-            if (kPark) {
-                park_d[0][l] = hs.lo; park_d[1][l] = hs.hi; park_d[2][l] = hs.wprev;
-                park_i[0][l] = hs.it; park_i[1][l] = hs.flags;
-                park_i[2][l] = hs.nlo; park_i[3][l] = hs.nhi;
+            if (kk == 0) {
+                park_d[0][p] = hs.lo; park_d[1][p] = hs.hi; park_d[2][p] = hs.wprev;
+                park_d[3][p] = hs.h;
+                park_i[0][p] = hs.it; park_i[1][p] = hs.flags;
+                park_i[2][p] = hs.nlo; park_i[3][p] = hs.nhi;
+                acc_d[0][p] = 0.0; acc_d[1][p] = 0.0; acc_d[2][p] = 0.0;
+                acc_n[p] = 0;
             }
             __syncthreads();
 
@@ -594,14 +593,48 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 const int32_t o0 = (int32_t)floor(0.5 * (mn0 + mx0));
                 const int32_t o1 = (int32_t)floor(0.5 * (mn1 + mx1));
                 const int32_t o2 = (int32_t)floor(0.5 * (mn2 + mx2));
+                // lanes of the sub-tile: its A particles get all 64 lanes, Sp
+                // copies each (Pp = A rounded up to a power of two particle
+                // slots; lane l serves slot l mod Pp, copy l / Pp), so lanes
+                // of converged particles or of other sub-tiles never idle.
+                // The selection stage keeps the tile's own mapping (its heaps
+                // are per lane).
+                const int A = __popcll(sub);
+                int lgPp = 0;
+                while ((1 << lgPp) < A) ++lgPp;
+                if (SEL) lgPp = __builtin_ctz(P);
+                const int Pp = 1 << lgPp, Sp = 64 >> lgPp;
+                if (!SEL && kk == 0 && in_sub)
+                    rg_mark[__popcll(sub & ((1ull << p) - 1ull))] = p;  // slot of own particle
+                __builtin_amdgcn_wave_barrier();
+                const int slot = l & (Pp - 1);
+                const int kk2 = l >> lgPp;
+                const bool in2 = SEL ? in_sub : slot < A;
+                const int pv = SEL ? p : (in2 ? rg_mark[slot] : p);
+                // the served particle's h and position (its copy-0 lane holds them)
+                const double h_l = park_d[3][pv];
+                const double hq_l = h_l * sc;
+                const double h2 = h_l * h_l;
+                const float ih2 = (float)(1.0 / (hq_l * hq_l));
+                const float h2f = (float)(hq_l * hq_l);
+                double x2 = 0.0, y2 = 0.0, z2 = 0.0;
                 float pix = 0.f, piy = 0.f, piz = 0.f;
-                if (PREC == SPH_FP32C) {
-                    const int4 q4 = own_q[l];
-                    const float4 f4 = own_f[l];
+                if (PREC == SPH_FP64) {
+                    const double4 o4 = own_x[pv];
+                    x2 = o4.x; y2 = o4.y; z2 = o4.z;
+                } else {
+                    const int4 q4 = own_q[pv];
+                    const float4 f4 = own_f[pv];
                     pix = (float)(q4.x - o0) + f4.x;
                     piy = (float)(q4.y - o1) + f4.y;
                     piz = (float)(q4.z - o2) + f4.z;
                 }
+                Sums sm;
+                sm.d0 = sm.d1 = sm.dr = 0.0;
+                sm.f0 = sm.f1 = sm.fr = sm.c0 = sm.c1 = sm.cr = 0.f;
+                sm.n = 0;
+                float pa0 = 0.f, pa1 = 0.f, par = 0.f;  // FP32C plain partial sums
+                int pterms = 0;                         // terms per lane since the last fold
 
                 // region of the sub-tile: its particles' bounding box (exactly
                 // the coordinates its pair tests use) widened by Hm.  A
@@ -609,25 +642,27 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 // sphere: the margin 2^-16 of Hm^2 on top of Hm's own covers
                 // the rounding of both tests
                 const int nsub = __popcll(sub);
-                double bx0 = 0.0, bx1 = 0.0, by0 = 0.0, by1 = 0.0, bz0 = 0.0, bz1 = 0.0, Hc2 = 0.0;
+                // (kept in LDS: the scalar registers are taken by the cell
+                // enumeration, and these are read once per load round)
                 if (PREC == SPH_FP64) {
-                    bx0 = uniform_d(wave_min(in_sub ? xi : INFINITY));
-                    by0 = uniform_d(wave_min(in_sub ? yi : INFINITY));
-                    bz0 = uniform_d(wave_min(in_sub ? zi : INFINITY));
-                    bx1 = uniform_d(wave_max(in_sub ? xi : -INFINITY));
-                    by1 = uniform_d(wave_max(in_sub ? yi : -INFINITY));
-                    bz1 = uniform_d(wave_max(in_sub ? zi : -INFINITY));
+                    const double a0 = wave_min(in2 ? x2 : INFINITY);
+                    const double a1 = wave_min(in2 ? y2 : INFINITY);
+                    const double a2 = wave_min(in2 ? z2 : INFINITY);
+                    const double b0 = wave_max(in2 ? x2 : -INFINITY);
+                    const double b1 = wave_max(in2 ? y2 : -INFINITY);
+                    const double b2 = wave_max(in2 ? z2 : -INFINITY);
                     const double Ha = Hm / sc;
-                    Hc2 = Ha * Ha * (1.0 + 0x1p-16);
+                    if (l == 0) {
+                        regbox_d[0] = make_double4(a0, a1, a2, Ha * Ha * (1.0 + 0x1p-16));
+                        regbox_d[1] = make_double4(b0, b1, b2, 0.0);
+                    }
                 } else {
-                    // kept in LDS: the scalar registers are taken by the cell
-                    // enumeration, and these are read once per load round
-                    const float a0 = wave_min(in_sub ? pix : INFINITY);
-                    const float a1 = wave_min(in_sub ? piy : INFINITY);
-                    const float a2 = wave_min(in_sub ? piz : INFINITY);
-                    const float b0 = wave_max(in_sub ? pix : -INFINITY);
-                    const float b1 = wave_max(in_sub ? piy : -INFINITY);
-                    const float b2 = wave_max(in_sub ? piz : -INFINITY);
+                    const float a0 = wave_min(in2 ? pix : INFINITY);
+                    const float a1 = wave_min(in2 ? piy : INFINITY);
+                    const float a2 = wave_min(in2 ? piz : INFINITY);
+                    const float b0 = wave_max(in2 ? pix : -INFINITY);
+                    const float b1 = wave_max(in2 ? piy : -INFINITY);
+                    const float b2 = wave_max(in2 ? piz : -INFINITY);
                     if (l == 0) {
                         regbox[0] = make_float4(a0, a1, a2, (float)(Hm * Hm * (1.0 + 0x1p-16)));
                         regbox[1] = make_float4(b0, b1, b2, 0.f);
@@ -638,17 +673,25 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 // one test round: every particle of the sub-tile against the
                 // first mc staged candidates (mc <= 64; slots mc..63 padded)
                 auto test_round = [&](const int mc) {
-                        // candidates per copy, rounded up to the unroll of 4: the slots
-                        // past mc hold padding, and 4 * ceil(mc / 4S) * S <= 64
-                        const int nu = (((mc + S - 1) / S) + 3) & ~3;
+                        // candidates per copy: the slots past mc hold padding, and
+                        // ceil(mc / Sp) * Sp <= 64 (Sp divides 64)
+                        const int nu = (mc + Sp - 1) >> (6 - lgPp);
+                        if (PREC == SPH_FP32C && pterms + nu > 64) {
+                            kahan(sm.f0, sm.c0, pa0);
+                            kahan(sm.f1, sm.c1, pa1);
+                            kahan(sm.fr, sm.cr, par);
+                            pa0 = pa1 = par = 0.f;
+                            pterms = 0;
+                        }
+                        pterms += nu;
                         if (SEL && in_sub) {
                             // selection: squared distances inside h into the heap
                             if (PREC == SPH_FP64) {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
                                 for (int t = kk; t < mc; t += S) {
-                                    const double dx = (c.x[t] - xi) + c.shx[t];
-                                    const double dy = (c.y[t] - yi) + c.shy[t];
-                                    const double dz = (c.z[t] - zi) + c.shz[t];
+                                    const double dx = (c.x[t] - x2) + c.shx[t];
+                                    const double dy = (c.y[t] - y2) + c.shy[t];
+                                    const double dz = (c.z[t] - z2) + c.shz[t];
                                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                                     if (r2 < h2) {
                                         ++sel_n;
@@ -663,7 +706,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                 // rounding stays below 2^-21 of r^2): the list then
                                 // holds at least K, and its order is the binary64 one
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
-                                const double hq2 = hq * hq * (1.0 + 0x1p-18);
+                                const double hq2 = hq_l * hq_l * (1.0 + 0x1p-18);
                                 for (int t = kk; t < mc; t += S) {
                                     const float4 cj = c.c[t];
                                     const double dx = (double)cj.x - (double)pix;
@@ -676,7 +719,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                     }
                                 }
                             }
-                        } else if (in_sub) {
+                        } else if (in2) {
                             // binary32: branch free.  With one particle-candidate
                             // pair per lane a wave almost always holds an in-range
                             // pair, so a branch would not skip the pair terms, only
@@ -690,13 +733,13 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                 // binary64 square root among them) need more
                                 // registers than a branch-free unrolled loop leaves
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
-                                const double hinv = 1.0 / hs.h;
+                                const double hinv = 1.0 / h_l;
 #pragma unroll 4
                                 for (int u = 0; u < nu; ++u) {
-                                    const int t = u * S + kk;
-                                    const double dx = (c.x[t] - xi) + c.shx[t];
-                                    const double dy = (c.y[t] - yi) + c.shy[t];
-                                    const double dz = (c.z[t] - zi) + c.shz[t];
+                                    const int t = u * Sp + kk2;
+                                    const double dx = (c.x[t] - x2) + c.shx[t];
+                                    const double dy = (c.y[t] - y2) + c.shy[t];
+                                    const double dz = (c.z[t] - z2) + c.shz[t];
                                     const double r2 = (dx * dx + dy * dy) + dz * dz;
                                     if (r2 < h2) {
                                         // the exact-K count stage needs the count only
@@ -715,35 +758,33 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                             } else {
                                 auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
                                 // cascade summation: up to 64 terms per lane in plain
-                                // binary32 (S chunks), then Kahan-compensated into the totals
+                                // binary32, then Kahan-compensated into the totals.
+                                // The stride between a copy's candidates is Sp; when
+                                // the sub-tile fills the tile it is the constant S,
+                                // and the LDS offsets become immediates
+                                auto eval32 = [&](auto stride) {
 #pragma unroll 4
-                                for (int u = 0; u < nu; ++u) {
-                                    const float4 cj = c.c[u * S + kk];
-                                    const float dx = cj.x - pix;
-                                    const float dy = cj.y - piy;
-                                    const float dz = cj.z - piz;
-                                    const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                                    const bool in = r2 < h2f;
-                                    if (STAGE != 1) {
-                                        // scaled pair terms (factors applied to the totals)
-                                        const float q2 = in ? r2 * ih2 : 1.0f;
-                                        const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
-                                        float fh, gs;
-                                        KT::template terms<float>(q, q2, fh, gs);
-                                        pa0 += fh;
-                                        pa1 += gs;
-                                        par = __builtin_fmaf(cj.w, fh, par);
+                                    for (int u = 0; u < nu; ++u) {
+                                        const float4 cj = c.c[u * stride + kk2];
+                                        const float dx = cj.x - pix;
+                                        const float dy = cj.y - piy;
+                                        const float dz = cj.z - piz;
+                                        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                                        const bool in = r2 < h2f;
+                                        if (STAGE != 1) {
+                                            // scaled pair terms (factors applied to the
+                                            // totals), q^2 clamped to 1: out of range, or
+                                            // within rounding of the edge, every term is 0
+                                            const float q2 = __builtin_fminf(__builtin_fmaxf(r2 * ih2, 0.0f), 1.0f);
+                                            const float q = __builtin_amdgcn_sqrtf(q2);  // 1 ulp
+                                            KT::accum(q, q2, cj.w, pa0, pa1, par);
+                                        }
+                                        sm.n += in ? 1 : 0;
                                     }
-                                    sm.n += in ? 1 : 0;
-                                }
+                                };
+                                if (Sp == S) eval32(std::integral_constant<int, S>{});
+                                else eval32(Sp);
                             }
-                        }
-                        if (PREC == SPH_FP32C && ++pchunks == S) {
-                            kahan(sm.f0, sm.c0, pa0);
-                            kahan(sm.f1, sm.c1, pa1);
-                            kahan(sm.fr, sm.cr, par);
-                            pa0 = pa1 = par = 0.f;
-                            pchunks = 0;
                         }
                 };
 
@@ -832,11 +873,18 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                 csx = (double)sh0 * a.box;
                                 csy = (double)sh1 * a.box;
                                 csz = (double)sh2 * a.box;
-                                const double px = cdv.x + csx, py = cdv.y + csy, pz = cdv.z + csz;
-                                const double ex = px - fmin(fmax(px, bx0), bx1);
-                                const double ey = py - fmin(fmax(py, by0), by1);
-                                const double ez = pz - fmin(fmax(pz, bz0), bz1);
-                                keep = (ex * ex + ey * ey) + ez * ez <= Hc2;
+                                // axis by axis, so that few binary64 values are live
+                                const double *rb = reinterpret_cast<const double *>(regbox_d);
+                                double px = cdv.x + csx;
+                                double e = px - fmin(fmax(px, rb[0]), rb[4]);
+                                double d2 = e * e;
+                                px = cdv.y + csy;
+                                e = px - fmin(fmax(px, rb[1]), rb[5]);
+                                d2 += e * e;
+                                px = cdv.z + csz;
+                                e = px - fmin(fmax(px, rb[2]), rb[6]);
+                                d2 += e * e;
+                                keep = d2 <= rb[3];
                             } else {
                                 const int32_t W = 1 << B;
                                 const int4 q4 = a.qp[j];
@@ -913,31 +961,39 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                     __syncthreads();
                     staged = 0;
                 }
+                if (!SEL) {
+                    // the sub-tile's sums: each served slot's copies combined by a
+                    // butterfly of commutative adds (every copy ends with the same
+                    // bits), then moved to the lanes that hold that particle
+                    double v0, v1, vr;
+                    if (PREC == SPH_FP64) {
+                        v0 = sm.d0; v1 = sm.d1; vr = sm.dr;
+                    } else {
+                        kahan(sm.f0, sm.c0, pa0);
+                        kahan(sm.f1, sm.c1, pa1);
+                        kahan(sm.fr, sm.cr, par);
+                        v0 = (double)sm.f0 - (double)sm.c0;
+                        v1 = (double)sm.f1 - (double)sm.c1;
+                        vr = (double)sm.fr - (double)sm.cr;
+                    }
+                    int32_t vn = sm.n;
+                    for (int o = Pp; o < 64; o <<= 1) {
+                        v0 += __shfl_xor(v0, o, 64);
+                        v1 += __shfl_xor(v1, o, 64);
+                        vr += __shfl_xor(vr, o, 64);
+                        vn += __shfl_xor(vn, o, 64);
+                    }
+                    if (in2 && kk2 == 0) {
+                        acc_d[0][pv] += v0; acc_d[1][pv] += v1; acc_d[2][pv] += vr;
+                        acc_n[pv] += vn;
+                    }
+                }
             }
 
-            if (PREC == SPH_FP32C) {
-                kahan(sm.f0, sm.c0, pa0);
-                kahan(sm.f1, sm.c1, pa1);
-                kahan(sm.fr, sm.cr, par);
-            }
-            double S0, S1, R;
-            if (PREC == SPH_FP64) {
-                S0 = KT::fscale * sm.d0; S1 = KT::gscale * sm.d1; R = KT::fscale * sm.dr;
-            } else {
-                S0 = KT::fscale * ((double)sm.f0 - (double)sm.c0);
-                S1 = KT::gscale * ((double)sm.f1 - (double)sm.c1);
-                R = KT::fscale * ((double)sm.fr - (double)sm.cr);
-            }
-            int32_t npair = sm.n;
-            // combine the S copies of each particle: a butterfly of commutative
-            // adds, so every copy ends with bit-identical sums (and h updates)
-#pragma unroll
-            for (int o = P; o < 64; o <<= 1) {
-                S0 += __shfl_xor(S0, o, 64);
-                S1 += __shfl_xor(S1, o, 64);
-                R += __shfl_xor(R, o, 64);
-                npair += __shfl_xor(npair, o, 64);
-            }
+            __builtin_amdgcn_wave_barrier();
+            const double S0 = KT::fscale * acc_d[0][p], S1 = KT::gscale * acc_d[1][p];
+            const double R = KT::fscale * acc_d[2][p];
+            const int32_t npair = acc_n[p];
             if (a.stats) {
                 cnt_pairs += uniform_u64(wave_sum<uint64_t>(!done && kk == 0 ? (uint64_t)npair : 0));
                 cnt_cands += pass_cands;
@@ -979,11 +1035,10 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 }
                 done = true;
             }
-            if (kPark) {
-                hs.lo = park_d[0][l]; hs.hi = park_d[1][l]; hs.wprev = park_d[2][l];
-                hs.it = park_i[0][l]; hs.flags = park_i[1][l];
-                hs.nlo = park_i[2][l]; hs.nhi = park_i[3][l];
-            }
+            hs.lo = park_d[0][p]; hs.hi = park_d[1][p]; hs.wprev = park_d[2][p];
+            hs.h = park_d[3][p];
+            hs.it = park_i[0][p]; hs.flags = park_i[1][p];
+            hs.nlo = park_i[2][p]; hs.nhi = park_i[3][p];
             if (!SEL && !done) {
                 const double nwv = KT::count * S0;
                 const double dndh = -KT::count * S1 / hs.h;

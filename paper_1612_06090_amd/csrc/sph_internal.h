@@ -36,6 +36,21 @@ struct Kern<SPH_KERNEL_M4> {
         fh = fma(T(-4) * v, v2, u2 * u);
         gs = q * fma(T(4), v2, -u2);
     }
+    // Binary32 sums of the scaled terms, added in place: s0 += f/2, s1 += q f'/6,
+    // sr += m f/2, for q in [0, 1] (q = 1 gives exact zeros).  With
+    // w = 4^(1/3) v, 4 v^3 = w^3 and 4 v^2 = 4^(1/3) w^2, so the factor 4 costs
+    // no instruction, and q f'/6 = q (4^(1/3) w^2 - u^2) is fused into its sum.
+    __device__ static void accum(float q, float /*q2*/, float m, float &s0, float &s1,
+                                 float &sr) {
+        constexpr float c = 1.587401051968199f;  // 4^(1/3)
+        const float u = 1.0f - q;
+        const float w = __builtin_fminf(__builtin_fmaxf(__builtin_fmaf(-c, q, 0.5f * c), 0.0f), 1.0f);
+        const float u2 = u * u, w2 = w * w;
+        const float fh = __builtin_fmaf(-w2, w, u2 * u);
+        s0 += fh;
+        s1 = __builtin_fmaf(q, __builtin_fmaf(c, w2, -u2), s1);
+        sr = __builtin_fmaf(m, fh, sr);
+    }
     // f and f'
     template <typename T>
     __device__ static void fd(T q, T &f, T &fp) {
@@ -62,6 +77,19 @@ struct Kern<SPH_KERNEL_WENDLAND_C6> {
         const T Q = fma(q, fma(T(16), q, T(7)), T(1));
         fh = (u7 * u) * P;
         gs = (q2 * u7) * Q;
+    }
+    // binary32 sums of the scaled terms, added in place (q = 1 gives zeros)
+    __device__ static void accum(float q, float q2, float m, float &s0, float &s1,
+                                 float &sr) {
+        const float u = 1.0f - q;
+        const float u2 = u * u, u4 = u2 * u2;
+        const float u7 = u4 * (u2 * u);
+        const float P = __builtin_fmaf(q, __builtin_fmaf(q, __builtin_fmaf(32.0f, q, 25.0f), 8.0f), 1.0f);
+        const float Q = __builtin_fmaf(q, __builtin_fmaf(16.0f, q, 7.0f), 1.0f);
+        const float fh = (u7 * u) * P;
+        s0 += fh;
+        s1 = __builtin_fmaf(q2 * u7, Q, s1);
+        sr = __builtin_fmaf(m, fh, sr);
     }
     template <typename T>
     __device__ static void fd(T q, T &f, T &fp) {
@@ -243,6 +271,14 @@ __device__ inline double readlane_d(double v, int l) {
 
 __device__ inline float readlane_f(float v, int l) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+// Value of v in lane `src` (a per-lane index), by bpermute.
+__device__ inline double readlane_bperm_d(double v, int src) {
+    int2 a = __builtin_bit_cast(int2, v);
+    a.x = __shfl(a.x, src, 64);
+    a.y = __shfl(a.y, src, 64);
+    return __builtin_bit_cast(double, a);
 }
 
 template <typename T>
