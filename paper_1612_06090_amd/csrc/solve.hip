@@ -390,10 +390,10 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     // range's first stream position, image code) and the stream positions at
     // which ranges start; rg_mark maps a load round's slots to range starts
     __shared__ int2 rg_so[64];
-    __shared__ int32_t rg_excl[64], rg_mark[64];
+    __shared__ int32_t rg_mark[64];
     __shared__ CandLDS<PREC> cd;
     __shared__ float4 regbox[2];  // FP32C region of the current sub-tile
-    __shared__ double4 regbox_d[PREC == SPH_FP64 ? 2 : 1];  // FP64 region
+    __shared__ double4 regbox_d[1];  // FP64 region: the box centre
     // Per particle of the tile, in LDS rather than registers (the kernel
     // stays within 128 VGPRs): its position (FP64: x, y, z; FP32C: grid cell
     // and fraction), the h iteration's bracket and counters while a pass runs
@@ -651,10 +651,18 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                     const double b0 = wave_max(in2 ? x2 : -INFINITY);
                     const double b1 = wave_max(in2 ? y2 : -INFINITY);
                     const double b2 = wave_max(in2 ? z2 : -INFINITY);
+                    // tested in binary32 relative to the box centre: the
+                    // half-extents rounded up and a relative margin of 2^-8 on
+                    // Hm^2 cover the binary32 rounding of the offsets (at most
+                    // 2^-24 of an offset no larger than ~600 Hm within the
+                    // split limit on the region's cells)
                     const double Ha = Hm / sc;
                     if (l == 0) {
-                        regbox_d[0] = make_double4(a0, a1, a2, Ha * Ha * (1.0 + 0x1p-16));
-                        regbox_d[1] = make_double4(b0, b1, b2, 0.0);
+                        regbox_d[0] = make_double4(0.5 * (a0 + b0), 0.5 * (a1 + b1), 0.5 * (a2 + b2), 0.0);
+                        regbox[0] = make_float4((float)(0.5 * (b0 - a0) * (1.0 + 0x1p-20)),
+                                                (float)(0.5 * (b1 - a1) * (1.0 + 0x1p-20)),
+                                                (float)(0.5 * (b2 - a2) * (1.0 + 0x1p-20)),
+                                                (float)(Ha * Ha * (1.0 + 0x1p-8)));
                     }
                 } else {
                     const float a0 = wave_min(in2 ? pix : INFINITY);
@@ -835,11 +843,13 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                     if (pass) {
                         const int slot = (int)mbcnt(pm);
                         rg_so[slot] = make_int2(c_st - (incl - cnt), code);
-                        rg_excl[slot] = incl - cnt;
+                        rg_mark[slot] = l;  // the lane that found range `slot`
                     }
                     __syncthreads();
                     // stream position at which range l starts (past the end for l >= nr)
-                    const int rstart = l < nr ? rg_excl[l] : INT_MAX;
+                    const int rsrc = l < nr ? rg_mark[l] : 0;
+                    const int rstart0 = __shfl(incl - cnt, rsrc, 64);
+                    const int rstart = l < nr ? rstart0 : INT_MAX;
                     int rcarry = 0;  // range of the stream position before the round
                     for (int cbase = 0; cbase < total; cbase += 64) {
                         // load round: each lane takes one candidate of the
@@ -873,18 +883,12 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                 csx = (double)sh0 * a.box;
                                 csy = (double)sh1 * a.box;
                                 csz = (double)sh2 * a.box;
-                                // axis by axis, so that few binary64 values are live
-                                const double *rb = reinterpret_cast<const double *>(regbox_d);
-                                double px = cdv.x + csx;
-                                double e = px - fmin(fmax(px, rb[0]), rb[4]);
-                                double d2 = e * e;
-                                px = cdv.y + csy;
-                                e = px - fmin(fmax(px, rb[1]), rb[5]);
-                                d2 += e * e;
-                                px = cdv.z + csz;
-                                e = px - fmin(fmax(px, rb[2]), rb[6]);
-                                d2 += e * e;
-                                keep = d2 <= rb[3];
+                                const double4 rc = regbox_d[0];
+                                const float4 rh = regbox[0];
+                                const float ex = __builtin_fmaxf(__builtin_fabsf((float)((cdv.x + csx) - rc.x)) - rh.x, 0.0f);
+                                const float ey = __builtin_fmaxf(__builtin_fabsf((float)((cdv.y + csy) - rc.y)) - rh.y, 0.0f);
+                                const float ez = __builtin_fmaxf(__builtin_fabsf((float)((cdv.z + csz) - rc.z)) - rh.z, 0.0f);
+                                keep = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)) <= rh.w;
                             } else {
                                 const int32_t W = 1 << B;
                                 const int4 q4 = a.qp[j];
