@@ -36,7 +36,10 @@
 namespace sph {
 
 constexpr int kLeafMax = 16;   // a walk node with at most this many particles is a leaf
-constexpr int kWorkCap = 256;  // walk stack capacity (overflowing nodes become leaves)
+// walk stack capacity (overflowing nodes become leaves); the binary32 form
+// gives half of it to the candidate staging buffer
+template <int PREC>
+constexpr int kWorkCap = PREC == SPH_FP32C ? 128 : 256;
 constexpr float kSplitExtent = 4.0f;  // split particle ranges wider than this many radii
 constexpr int kAdjP = kAdjTile;       // particles per wave tile
 constexpr int kAdjS = 64 / kAdjP;     // lanes per particle
@@ -108,12 +111,30 @@ struct AdjCand<SPH_FP32C> {
     float g;       // gamma
 };
 
+// Candidates waiting to be evaluated.  Binary64: one chunk of 64 as streamed.
+// Binary32: the candidates that passed the range's region test (its box
+// widened by the larger of the range's radius and the candidate's own),
+// appended in load rounds of 64 and evaluated 64 at a time, so up to 127 wait.
+template <int PREC>
+struct AdjStage {
+    AdjCand<PREC> cand[64];
+};
+
+template <>
+struct AdjStage<SPH_FP32C> {
+    float4 p[128];  // x, y, z (grid units, range origin), m
+    float4 h[128];  // h, 1/h (grid units), alpha, beta
+    float g[128];   // gamma
+};
+
 template <int PREC>
 struct AdjLDS {
-    int32_t wk_st[kWorkCap], wk_en[kWorkCap], wk_c[kWorkCap][3], wk_L[kWorkCap];
-    int32_t rg_start[64], rg_excl[64], rg_code[64];
+    int32_t wk_st[kWorkCap<PREC>], wk_en[kWorkCap<PREC>], wk_c[kWorkCap<PREC>][3],
+        wk_L[kWorkCap<PREC>];
+    int32_t rg_start[64], rg_excl[64], rg_code[64], rg_mark[64];
     float sp[4][kAdjP];   // the tile's spheres: x, y, z (grid units, range origin), radius
-    AdjCand<PREC> cand[64];
+    float4 box[2];        // binary32: the range's box (min, max) and Ht^2
+    AdjStage<PREC> st;
 };
 
 template <int PREC, bool GROUPED, int KERNEL>
@@ -245,6 +266,10 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 S.sp[2][p] = pk2;
                 S.sp[3][p] = Hk;
             }
+            if (l == 0) {
+                S.box[0] = make_float4(mn0, mn1, mn2, Ht * Ht);
+                S.box[1] = make_float4(mx0, mx1, mx2, 0.f);
+            }
             __syncthreads();
 
             int wsz = 0;   // work stack size (uniform)
@@ -295,12 +320,38 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 }
             };
 
+            // binary32 candidate at stream position gidx of range rr
+            auto load_cand_r = [&](int gidx, int rr, AdjCand<PREC> &c) {
+                const int64_t j = (int64_t)S.rg_start[rr] + (gidx - S.rg_excl[rr]);
+                const int cc = S.rg_code[rr];
+                const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1, sh2 = ((cc >> 4) & 3) - 1;
+                if constexpr (PREC == SPH_FP32C) {
+                    const int32_t W = 1 << B;
+                    const int4 q4 = a.qp[j];
+                    const float4 f4 = a.fp[j];
+                    c.p = make_float4((float)(q4.x + sh0 * W - t0) + f4.x,
+                                      (float)(q4.y + sh1 * W - t1) + f4.y,
+                                      (float)(q4.z + sh2 * W - t2) + f4.z,
+                                      __int_as_float(q4.w));
+                    if (a.phase >= 2) {
+                        const double hqj = a.sh[j] * sc;
+                        const double aj = a.phase == 2 ? a.alpha[j] : 0.0;
+                        const double bj = a.phase == 2 ? a.beta[j] : 0.0;
+                        c.h = make_float4((float)hqj, (float)(1.0 / hqj), (float)aj, (float)bj);
+                        c.g = (float)a.gamma[j];
+                    } else {
+                        c.h = make_float4(1.f, 1.f, 0.f, 0.f);
+                        c.g = 0.f;
+                    }
+                }
+            };
+
             // the pair terms of one LDS chunk for this lane's share of it
             auto eval_chunk = [&](int mc) {
                 const int nu = (mc + kAdjS - 1) / kAdjS;
                 if constexpr (PREC == SPH_FP64) {
                     for (int u = 0; u < nu; ++u) {
-                        const AdjCand<SPH_FP64> c = S.cand[u * kAdjS + kk];
+                        const AdjCand<SPH_FP64> c = S.st.cand[u * kAdjS + kk];
                         const double dx = (c.p.x - xk) + c.s.x;
                         const double dy = (c.p.y - yk) + c.s.y;
                         const double dz = (c.p.z - zk) + c.s.z;
@@ -345,52 +396,70 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                         }
                     }
                 } else {
-                    // chunk partial sums in binary32, folded into binary64
+                    // round partial sums in binary32 (at most 16 terms per lane),
+                    // folded into binary64.  Branch free: with one particle-candidate
+                    // pair per lane a wave almost always holds an in-range pair, so
+                    // a branch would skip nothing; out of range, q is clamped to 1,
+                    // where f and f' vanish, and the selects give exact zeros
                     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-                    for (int u = 0; u < nu; ++u) {
-                        const AdjCand<SPH_FP32C> c = S.cand[u * kAdjS + kk];
-                        const float dx = c.p.x - pk0;
-                        const float dy = c.p.y - pk1;
-                        const float dz = c.p.z - pk2;
-                        const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
-                        const bool in1 = r2 < hk2f;
-                        if (a.phase == 1) {
-                            if (in1) {
-                                const float q = fminf(__builtin_amdgcn_sqrtf(r2) * hkinvf, 1.0f);
-                                float f, fp;
-                                KT::template fd<float>(q, f, fp);
-                                const float qfp = q * fp;
-                                s0 += qfp;
-                                s1 = __builtin_fmaf(c.p.w, f, s1);
-                                s2 = __builtin_fmaf(c.p.w, qfp, s2);
-                            }
-                        } else if (a.phase == 3) {
-                            const bool in2 = r2 < c.h.x * c.h.x;
-                            if (in1 || in2) {
-                                const float r = __builtin_amdgcn_sqrtf(r2);
-                                float f1, fp1, f2, fp2;
-                                KT::template fd<float>(fminf(r * hkinvf, 1.0f), f1, fp1);
-                                KT::template fd<float>(fminf(r * c.h.y, 1.0f), f2, fp2);
-                                s0 = __builtin_fmaf(in1 ? c.p.w : 0.f, f1, s0);
-                                s1 = __builtin_fmaf(in2 ? c.g : 0.f, f2, s1);
-                                s2 += in2 ? 1.f : 0.f;
-                            }
-                        } else {
-                            const bool in2 = r2 < c.h.x * c.h.x;
-                            if (in1 || in2) {
-                                const float r = __builtin_amdgcn_sqrtf(r2);
-                                const float rinv = r > 0.f ? __builtin_amdgcn_rcpf(r) : 0.f;
-                                float f1, fp1, f2, fp2;
-                                KT::template fd<float>(fminf(r * hkinvf, 1.0f), f1, fp1);
-                                KT::template fd<float>(fminf(r * c.h.y, 1.0f), f2, fp2);
-                                const float c1 = in1 ? fp1 * __builtin_fmaf(akf, c.p.w, bkf) : 0.f;
-                                const float c2 = in2 ? fp2 * __builtin_fmaf(c.h.z, mkf, c.h.w) : 0.f;
-                                s3 = __builtin_fmaf(in2 ? c.g : 0.f, f2, s3);
-                                const float w = (c1 + c2) * rinv;
-                                s0 = __builtin_fmaf(-w, dx, s0);
-                                s1 = __builtin_fmaf(-w, dy, s1);
-                                s2 = __builtin_fmaf(-w, dz, s2);
-                            }
+                    if (a.phase == 1) {
+#pragma unroll 4
+                        for (int u = 0; u < nu; ++u) {
+                            const float4 cp = S.st.p[u * kAdjS + kk];
+                            const float dx = cp.x - pk0, dy = cp.y - pk1, dz = cp.z - pk2;
+                            const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                            const bool in1 = r2 < hk2f;
+                            const float q = fminf(__builtin_amdgcn_sqrtf(r2) * hkinvf, 1.0f);
+                            float f, fp;
+                            KT::template fd<float>(q, f, fp);
+                            const float qfp = in1 ? q * fp : 0.f;
+                            const float fs = in1 ? f : 0.f;
+                            s0 += qfp;
+                            s1 = __builtin_fmaf(cp.w, fs, s1);
+                            s2 = __builtin_fmaf(cp.w, qfp, s2);
+                        }
+                    } else if (a.phase == 3) {
+#pragma unroll 2
+                        for (int u = 0; u < nu; ++u) {
+                            const int t = u * kAdjS + kk;
+                            const float4 cp = S.st.p[t];
+                            const float4 ch = S.st.h[t];
+                            const float cg = S.st.g[t];
+                            const float dx = cp.x - pk0, dy = cp.y - pk1, dz = cp.z - pk2;
+                            const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                            const bool in1 = r2 < hk2f;
+                            const bool in2 = r2 < ch.x * ch.x;
+                            const float r = __builtin_amdgcn_sqrtf(r2);
+                            float f1, fp1, f2, fp2;
+                            KT::template fd<float>(fminf(r * hkinvf, 1.0f), f1, fp1);
+                            KT::template fd<float>(fminf(r * ch.y, 1.0f), f2, fp2);
+                            s0 = __builtin_fmaf(in1 ? cp.w : 0.f, f1, s0);
+                            s1 = __builtin_fmaf(in2 ? cg : 0.f, f2, s1);
+                            s2 += in2 ? 1.f : 0.f;
+                        }
+                    } else {
+#pragma unroll 2
+                        for (int u = 0; u < nu; ++u) {
+                            const int t = u * kAdjS + kk;
+                            const float4 cp = S.st.p[t];
+                            const float4 ch = S.st.h[t];
+                            const float cg = S.st.g[t];
+                            const float dx = cp.x - pk0, dy = cp.y - pk1, dz = cp.z - pk2;
+                            const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                            const bool in1 = r2 < hk2f;
+                            const bool in2 = r2 < ch.x * ch.x;
+                            const float r = __builtin_amdgcn_sqrtf(r2);
+                            const float rinv = r > 0.f ? __builtin_amdgcn_rcpf(r) : 0.f;
+                            float f1, fp1, f2, fp2;
+                            KT::template fd<float>(fminf(r * hkinvf, 1.0f), f1, fp1);
+                            KT::template fd<float>(fminf(r * ch.y, 1.0f), f2, fp2);
+                            const float c1 = in1 ? fp1 * __builtin_fmaf(akf, cp.w, bkf) : 0.f;
+                            const float c2 = in2 ? fp2 * __builtin_fmaf(ch.z, mkf, ch.w) : 0.f;
+                            s3 = __builtin_fmaf(in2 ? cg : 0.f, f2, s3);
+                            const float w = (c1 + c2) * rinv;
+                            s0 = __builtin_fmaf(-w, dx, s0);
+                            s1 = __builtin_fmaf(-w, dy, s1);
+                            s2 = __builtin_fmaf(-w, dz, s2);
                         }
                     }
                     acc0 += (double)s0;
@@ -400,8 +469,28 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 }
             };
 
-            // stream the collected leaves (ranges) through LDS, one chunk of 64
-            // candidates ahead in registers
+            // stream the collected leaves (ranges) through LDS.  Binary64: one
+            // chunk of 64 candidates ahead in registers.  Binary32: load rounds of
+            // 64; a candidate farther than max(Ht, its own h) from the range's
+            // box (the exact binary32 coordinates of its spheres) reaches no
+            // sphere of the range and no sphere of the range reaches it, so only
+            // the others are staged (ballot slots) and evaluated 64 at a time
+            int staged = 0;  // binary32: candidates waiting in the staging buffer
+            auto eval_staged = [&]() {
+                __syncthreads();
+                if (in_sub) eval_chunk(64);
+                __syncthreads();
+                // the entries past the round move to the front
+                if constexpr (PREC == SPH_FP32C) {
+                    if (l < staged - 64) {
+                        const float4 tp = S.st.p[64 + l], th = S.st.h[64 + l];
+                        const float tg = S.st.g[64 + l];
+                        S.st.p[l] = tp; S.st.h[l] = th; S.st.g[l] = tg;
+                    }
+                }
+                staged -= 64;
+                __syncthreads();
+            };
             auto stream_leaves = [&](int nleaf) {
                 const int cnt = l < nleaf ? S.rg_excl[l] : 0;  // rg_excl holds counts here
                 const int incl = wave_incl_scan(cnt);
@@ -409,15 +498,72 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 __syncthreads();
                 if (l < nleaf) S.rg_excl[l] = incl - cnt;
                 __syncthreads();
-                AdjCand<PREC> nxt;
-                load_cand(l, total, nleaf, nxt);
-                for (int cbase = 0; cbase < total; cbase += 64) {
+                if constexpr (PREC == SPH_FP64) {
+                    AdjCand<PREC> nxt;
+                    load_cand(l, total, nleaf, nxt);
+                    for (int cbase = 0; cbase < total; cbase += 64) {
+                        __syncthreads();
+                        S.st.cand[l] = nxt;
+                        __syncthreads();
+                        if (cbase + 64 < total) load_cand(cbase + 64 + l, total, nleaf, nxt);
+                        const int mc = total - cbase < 64 ? total - cbase : 64;
+                        if (in_sub) eval_chunk(mc);
+                    }
+                } else {
+                    const int rstart = l < nleaf ? S.rg_excl[l] : INT_MAX;
+                    int rcarry = 0;
+                    for (int cbase = 0; cbase < total; cbase += 64) {
+                        // the range of each slot: marks at range starts, carried
+                        // forward by a wave max-scan
+                        S.rg_mark[l] = -1;
+                        const int pos = rstart - cbase;
+                        if (pos >= 0 && pos < 64) S.rg_mark[pos] = l;
+                        __builtin_amdgcn_wave_barrier();
+                        int rr = wave_max_scan(S.rg_mark[l]);
+                        rr = rr > rcarry ? rr : rcarry;
+                        rcarry = __builtin_amdgcn_readlane(rr, 63);
+                        const int gidx = cbase + l;
+                        bool keep = false;
+                        AdjCand<PREC> c;
+                        if (gidx < total) {
+                            load_cand_r(gidx, rr, c);
+                            const float4 bl = S.box[0], bh = S.box[1];
+                            const float ex = c.p.x - fminf(fmaxf(c.p.x, bl.x), bh.x);
+                            const float ey = c.p.y - fminf(fmaxf(c.p.y, bl.y), bh.y);
+                            const float ez = c.p.z - fminf(fmaxf(c.p.z, bl.z), bh.z);
+                            const float R2 = a.phase >= 2 ? fmaxf(bl.w, c.h.x * c.h.x) : bl.w;
+                            keep = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)) <=
+                                   R2 * (1.0f + 0x1p-12f);
+                        }
+                        const uint64_t km = __ballot(keep);
+                        if (keep) {
+                            const int slot = staged + (int)mbcnt(km);
+                            S.st.p[slot] = c.p;
+                            S.st.h[slot] = c.h;
+                            S.st.g[slot] = c.g;
+                        }
+                        staged += __popcll(km);
+                        if (staged >= 64) eval_staged();
+                    }
+                }
+            };
+            // the range's last, partial round: slots past the staged candidates
+            // hold padding, a candidate so far away (finite, so that the zero
+            // pair weight times its offset stays zero; its r^2 overflows to
+            // infinity) that it is never in range
+            auto flush_staged = [&]() {
+                if (staged > 0) {
+                    if constexpr (PREC == SPH_FP32C) {
+                        if (l >= staged) {
+                            S.st.p[l] = make_float4(1e30f, 1e30f, 1e30f, 0.f);
+                            S.st.h[l] = make_float4(1.f, 1.f, 0.f, 0.f);
+                            S.st.g[l] = 0.f;
+                        }
+                    }
                     __syncthreads();
-                    S.cand[l] = nxt;
+                    if (in_sub) eval_chunk(staged);
                     __syncthreads();
-                    if (cbase + 64 < total) load_cand(cbase + 64 + l, total, nleaf, nxt);
-                    const int mc = total - cbase < 64 ? total - cbase : 64;
-                    if (in_sub) eval_chunk(mc);
+                    staged = 0;
                 }
             };
 
@@ -453,7 +599,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                              int64_t c2, int L) {
                 uint64_t wm = __ballot(pass && !leaf);
                 const int nw = __popcll(wm);
-                if (wsz + nw > kWorkCap) {
+                if (wsz + nw > kWorkCap<PREC>) {
                     leaf = leaf || pass;
                     wm = 0;
                 }
@@ -594,6 +740,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 expand_all();
             }
             if (nl > 0) stream_leaves(nl);
+            if constexpr (PREC == SPH_FP32C) flush_staged();
         }
 
         // fold the copies' partial sums (lanes p, p + 16, p + 32, p + 48)
