@@ -403,6 +403,7 @@ def run_knn(sph, torch, d, ps, steps, dk=14.0):
         torch.cuda.synchronize()
         cands = int(st["stats"][1].item())
         region = int(st["stats"][3].item())
+        passes = int(st["stats"][2].item())
         final_pairs = int(st["nngb"].to(torch.int64).sum().item())
         kms = kernel_ms(HipEvents(), p, lambda: sph.density_solve(
             d["x"], d["y"], d["z"], d["m"], d["h_init"], p, ws=ws), steps)
@@ -414,7 +415,8 @@ def run_knn(sph, torch, d, ps, steps, dk=14.0):
         out[name] = {"ms_per_step": ms, "particles_per_s": ps.n / (ms * 1e-3),
                      "flagged": flagged, "max_count_updates": iters, "kernel_ms": kms,
                      "candidates_per_step": cands, "final_pairs": final_pairs,
-                     "roofline": {"bound": "alu", "kernel": "k_solve (three exact-K stages)",
+                     "passes_per_step": passes,
+                     "roofline": {"bound": "alu", "kernel": "k_solve (exact-K stages)",
                                   "achieved": flop / (kms * 1e-3) / 1e12,
                                   "peak": peak / 1e12, "unit": "TFLOP/s",
                                   "frac": flop / (kms * 1e-3) / peak,

@@ -74,6 +74,7 @@ struct SolveArgs {
     double *knn_h;
     int32_t sel_cap;  // entries of the selection heap (16, 32 or 64)
     int32_t *knn_st;
+    int32_t *knn_items;
     double *sh_out;
 };
 
@@ -313,9 +314,11 @@ __device__ inline void kahan(float &s, float &c, float x) {
 // copies' sums are combined before the (replicated) h update.  Smaller P
 // means a smaller tile region (fewer candidates per particle) and a shorter
 // sequential stream per wave, at the price of more tiles.
-// Particles per wave tile of the exact-K selection pass (4 lanes per particle,
-// each with its own heap; the heaps are merged at the end of the pass).
-constexpr int kSelTile = 16;
+// Exact-K selection: status bit of a particle that stage 2 leaves to stage 4,
+// and the control word (after the work queue's) that counts the tiles holding
+// one (their items listed in knn_items)
+constexpr int32_t kSelRetry = 1 << 30;
+constexpr int kSelRetrySlot = 8;
 
 // Selection heap of the exact-K mode: per lane, a min-heap of the CAP largest
 // squared distances inside h (binary64 for FP64, binary32 for FP32C: rounding
@@ -373,16 +376,38 @@ __device__ inline void sel_pop(T *H, int l, int &hc) {
 // launches: 1 iterates h on the integer count into the band [K, K + dK]
 // (writes knn_h, knn_st); 2 selects (16-particle tiles, 4 lanes per
 // particle): at the count-stage h of each particle the squared distances
-// inside h go through the lanes' heaps, which copy 0 merges, and the K-th
-// smallest becomes the particle's h (writes sh_out, knn_st); 3 evaluates at
-// that h with the status of knn_st.  The stage is a
-// template argument so that the band-mode kernel carries none of it.
+// inside h are ranked and the K-th smallest becomes the particle's h (writes
+// sh_out, knn_st); 3 evaluates at that h with the status of knn_st.  The
+// stage is a template argument so that the band-mode kernel carries none of
+// it.
+//
+// Selection.  The K-th smallest of the c distances inside h is their
+// (c - K + 1)-th largest, and the count stage hands over only an h whose rank
+// is at most CAP.  Stage 2 keeps, per lane, only the distances of an outer
+// shell r^2 > tau^2 (a volume fraction of the sphere expected to hold about
+// CAP + 8 particles at uniform density) in a list of at most CAP (a full
+// list keeps the CAP largest met), and ranks the union of a particle's lists
+// once at the end of the pass by counting.  Where the shell holds fewer than
+// the rank, it marks the particle (kSelRetry) and counts it; stage 4 then
+// passes over the
+// marked particles only (it returns at once when none is marked), with every
+// distance inside h going through a per-lane heap of the CAP largest, merged
+// by copy 0.  Both return the same element of the same set, so the result
+// does not depend on which one found it.
 template <int PREC, bool GROUPED, int P, int KERNEL, int STAGE = 0, int CAP = 64>
 __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     using KT = Kern<KERNEL>;
-    constexpr bool SEL = STAGE == 2;
+    constexpr bool SEL = STAGE == 2 || STAGE == 4;
+    constexpr bool SEL_LIST = STAGE == 2;
     using HeapT = typename std::conditional<PREC == SPH_FP64, double, float>::type;
+    // per lane: the shell list (stage 2) or the heap (stage 4)
     __shared__ HeapT selheap[SEL ? 64 * CAP : 1];
+    // the selection reads four candidates per copy at a time, up to three
+    // rounds of S slots past the last full one
+    static_assert(!SEL || 64 + 3 * (64 / P) <= kStage, "selection reads past the staging buffer");
+    // stage 4 visits only the tiles stage 2 listed
+    const int32_t n_retry = STAGE == 4 ? uniform_i(a.queue[kSelRetrySlot]) : 0;
+    if (STAGE == 4 && n_retry == 0) return;
     constexpr int S = 64 / P;
     __shared__ double act_t[3][P];
     __shared__ double act_H[P];
@@ -410,6 +435,10 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
     const int p = l & (P - 1);   // particle slot in the tile
     const int kk = l / P;        // copy index of this lane
     const int B = a.bits;
+    // selection shell: r^2 > sel_g h^2 is the outer volume fraction sel_f of
+    // the sphere (sel_g < 0: the whole sphere)
+    const double sel_f = SEL ? (CAP + 8.0) / a.Nt : 1.0;
+    const double sel_g = sel_f < 1.0 ? cbrt((1.0 - sel_f) * (1.0 - sel_f)) : -1.0;
     constexpr uint64_t kTileMask = P == 64 ? ~0ull : ((1ull << P) - 1ull);
     uint64_t cnt_pairs = 0, cnt_cands = 0, cnt_passes = 0, cnt_region = 0;  // wave totals
 
@@ -417,8 +446,10 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         int item = 0;
         if (l == 0) item = atomicAdd(a.queue, 1);
         item = uniform_i(__shfl(item, 0, 64));
-        const int64_t n_items = GROUPED ? (int64_t)a.gitems[a.G] : a.n_items;
+        const int64_t n_items = STAGE == 4 ? (int64_t)n_retry
+                                : GROUPED ? (int64_t)a.gitems[a.G] : a.n_items;
         if (item >= n_items) break;
+        if (STAGE == 4) item = uniform_i(a.knn_items[item]);
 
         int64_t b, e;
         int32_t g = 0;
@@ -455,13 +486,17 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
         hs.wprev = INFINITY;
         hs.fixed = a.max_iter == 0 || STAGE >= 2;
         // exact-K stages 2 and 3 carry the count stage's status
-        const int32_t st_in = (STAGE >= 2 && mine) ? a.knn_st[s] : 0;
+        int32_t st_in = (STAGE >= 2 && mine) ? a.knn_st[s] : 0;
+        // stage 4: particles stage 2 settled are left as they are
+        const bool skip = STAGE == 4 && (st_in & kSelRetry) == 0;
+        st_in &= ~kSelRetry;
         if (STAGE == 3) {
             hs.flags = st_in & ~0xFFFF;
             hs.it = st_in & 0xFFFF;
         }
         int sel_n = 0, sel_hc = 0;  // selection: in-range count, heap size
         HeapT sel_min = 0;          // selection: the heap's root
+        int sel_cnt = 0;            // selection: shell members met (list length)
         bool valid = false;
         if (mine) {
             if (PREC == SPH_FP64) {
@@ -491,7 +526,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 tz = (double)q4.z + (double)f4.z;
             }
         };
-        if (mine && !valid && kk == 0) {
+        if (mine && !valid && kk == 0 && STAGE != 4) {
             if (SEL) a.sh_out[s] = hs.h;
             else write_out(a, a.perm[s], NAN, hs.h, NAN, 0, SPH_ST_BADINPUT);
             if (STAGE == 1) { a.knn_h[s] = hs.h; a.knn_st[s] = SPH_ST_BADINPUT; }
@@ -504,8 +539,8 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
             }
         }
         if (hs.h > hmax) hs.h = hmax;
-        bool done = !(mine && valid);
-        if (SEL && mine && valid && (st_in >> 16) != 0) {
+        bool done = !(mine && valid) || skip;
+        if (SEL && !done && (st_in >> 16) != 0) {
             // flagged by the count stage: h passes through unchanged
             a.sh_out[s] = hs.h;
             done = true;
@@ -693,40 +728,102 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                         }
                         pterms += nu;
                         if (SEL && in_sub) {
-                            // selection: squared distances inside h into the heap
-                            if (PREC == SPH_FP64) {
-                                auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
-                                for (int t = kk; t < mc; t += S) {
-                                    const double dx = (c.x[t] - x2) + c.shx[t];
-                                    const double dy = (c.y[t] - y2) + c.shy[t];
-                                    const double dz = (c.z[t] - z2) + c.shz[t];
-                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                                    if (r2 < h2) {
-                                        ++sel_n;
-                                        sel_insert<CAP>(selheap, l, sel_hc, (HeapT)r2, sel_min);
+                            // selection: squared distances inside h into the
+                            // shell list (first pass) or the heap (second)
+                            // (the shell test in binary32: rounding is monotone,
+                            // so the shell stays a top set of the distances)
+                            auto scan = [&](auto heap) {
+                                auto keep = [&](HeapT r2, float tau2) {
+                                    if (heap) {
+                                        sel_insert<CAP>(selheap, l, sel_hc, r2, sel_min);
+                                    } else if ((float)r2 > tau2) {
+                                        if (sel_cnt < CAP) {
+                                            selheap[sel_cnt * 64 + l] = r2;
+                                            sel_min = sel_cnt == 0 || r2 < sel_min ? r2 : sel_min;
+                                            ++sel_cnt;
+                                        } else if (r2 > sel_min) {
+                                            // a full list keeps the CAP largest
+                                            // met: the new one replaces (one copy
+                                            // of) its minimum
+                                            bool put = false;
+                                            HeapT nm = r2;
+#pragma unroll 1
+                                            for (int i = 0; i < CAP; ++i) {
+                                                const HeapT w = selheap[i * 64 + l];
+                                                if (!put && w == sel_min) {
+                                                    selheap[i * 64 + l] = r2;
+                                                    put = true;
+                                                } else {
+                                                    nm = w < nm ? w : nm;
+                                                }
+                                            }
+                                            sel_min = nm;
+                                            ++sel_cnt;
+                                        }
+                                    }
+                                };
+                                // four candidates per copy at a time: their
+                                // LDS reads and distances issue together, the
+                                // list or heap work follows (slot u * S + kk of
+                                // the round; slots past mc hold padding, and
+                                // the reads stay inside the 128-slot buffer)
+                                if (PREC == SPH_FP64) {
+                                    auto &c = reinterpret_cast<CandLDS<SPH_FP64> &>(cd);
+                                    const float tau2 = (float)(h2 * sel_g);
+                                    for (int u0 = 0; u0 < nu; u0 += 4) {
+                                        HeapT v[4];
+                                        bool in[4];
+#pragma unroll
+                                        for (int q = 0; q < 4; ++q) {
+                                            const int t = (u0 + q) * S + kk;
+                                            const double dx = (c.x[t] - x2) + c.shx[t];
+                                            const double dy = (c.y[t] - y2) + c.shy[t];
+                                            const double dz = (c.z[t] - z2) + c.shz[t];
+                                            const double r2 = (dx * dx + dy * dy) + dz * dz;
+                                            in[q] = r2 < h2 && u0 + q < nu;
+                                            v[q] = (HeapT)r2;
+                                        }
+#pragma unroll
+                                        for (int q = 0; q < 4; ++q)
+                                            if (in[q]) {
+                                                ++sel_n;
+                                                keep(v[q], tau2);
+                                            }
+                                    }
+                                } else {
+                                    // binary32 coordinates, differences and squares
+                                    // (grid units), as in the count stage but about
+                                    // another origin.  The sphere is widened by a
+                                    // relative 2^-18 so that it holds every particle
+                                    // the count stage's test counted inside h (each
+                                    // test's rounding stays below 2^-21 of r^2): the
+                                    // list then holds at least K
+                                    auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
+                                    const float hq2 = (float)(hq_l * hq_l * (1.0 + 0x1p-18));
+                                    const float tau2 = (float)(hq_l * hq_l * sel_g);
+                                    for (int u0 = 0; u0 < nu; u0 += 4) {
+                                        HeapT v[4];
+                                        bool in[4];
+#pragma unroll
+                                        for (int q = 0; q < 4; ++q) {
+                                            const float4 cj = c.c[(u0 + q) * S + kk];
+                                            const float dx = cj.x - pix;
+                                            const float dy = cj.y - piy;
+                                            const float dz = cj.z - piz;
+                                            const float r2 = __builtin_fmaf(dx, dx, __builtin_fmaf(dy, dy, dz * dz));
+                                            in[q] = r2 < hq2 && u0 + q < nu;
+                                            v[q] = r2;
+                                        }
+#pragma unroll
+                                        for (int q = 0; q < 4; ++q)
+                                            if (in[q]) {
+                                                ++sel_n;
+                                                keep(v[q], tau2);
+                                            }
                                     }
                                 }
-                            } else {
-                                // binary32 coordinates, differences and squares in
-                                // binary64 (grid units).  The sphere is widened by a
-                                // relative 2^-19 so that it holds every particle the
-                                // count stage's binary32 test counted inside h (its
-                                // rounding stays below 2^-21 of r^2): the list then
-                                // holds at least K, and its order is the binary64 one
-                                auto &c = reinterpret_cast<CandLDS<SPH_FP32C> &>(cd);
-                                const double hq2 = hq_l * hq_l * (1.0 + 0x1p-18);
-                                for (int t = kk; t < mc; t += S) {
-                                    const float4 cj = c.c[t];
-                                    const double dx = (double)cj.x - (double)pix;
-                                    const double dy = (double)cj.y - (double)piy;
-                                    const double dz = (double)cj.z - (double)piz;
-                                    const double r2 = (dx * dx + dy * dy) + dz * dz;
-                                    if (r2 < hq2) {
-                                        ++sel_n;
-                                        sel_insert<CAP>(selheap, l, sel_hc, (HeapT)r2, sel_min);
-                                    }
-                                }
-                            }
+                            };
+                            scan(std::integral_constant<bool, !SEL_LIST>{});
                         } else if (in2) {
                             // binary32: branch free.  With one particle-candidate
                             // pair per lane a wave almost always holds an in-range
@@ -1004,10 +1101,96 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                 cnt_region += pass_region;
                 cnt_passes += (uint64_t)__popcll(am);
             }
-            if (SEL) {
-                // each copy kept the CAP largest of its share of the distances
-                // inside h; copy 0 takes in the other copies' heaps (the union's
-                // CAP largest contain its rank-th largest for any rank <= CAP)
+            if (SEL_LIST) {
+                // each copy's list holds the CAP largest of its share of the
+                // m shell members (all of them when it met no more than CAP).
+                // When rank <= m the rank-th largest v of the distances inside
+                // h is a shell member, and counting over the union of the
+                // lists, v is the one element e with #(> e) < rank <= #(>= e):
+                // every member above v is in its copy's CAP largest (fewer
+                // than rank <= CAP of them exist), and the lists hold at least
+                // min(CAP, #(>= v)) >= rank members >= v.  Each lane checks
+                // its own list against the union
+                int seln = sel_n;
+#pragma unroll
+                for (int o = P; o < 64; o <<= 1) seln += __shfl_xor(seln, o, 64);
+                // list lengths through LDS (the lane-map words are free now)
+                rg_mark[l] = sel_cnt;
+                __syncthreads();
+                int m = 0;  // shell members met by the copies
+#pragma unroll
+                for (int k = 0; k < S; ++k) m += rg_mark[p + k * P];
+                const int rank = seln - (int)a.Nt + 1;
+                const int own = sel_cnt < CAP ? sel_cnt : CAP;
+                int found = 0;
+                HeapT ans = 0;
+                if (!done && rank >= 1 && rank <= CAP && rank <= m) {
+                    // four own elements at a time against each union element
+                    // (read once per four); counts packed as #(>) + 2^16 #(>=)
+#pragma unroll 1
+                    for (int i0 = 0; i0 < own; i0 += 4) {
+                        HeapT e[4];
+                        int cn[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int i = i0 + q < CAP ? i0 + q : CAP - 1;
+                            e[q] = selheap[i * 64 + l];
+                            cn[q] = 0;
+                        }
+#pragma unroll 1
+                        for (int k = 0; k < S; ++k) {
+                            const int ckr = rg_mark[p + k * P];
+                            const int ck = ckr < CAP ? ckr : CAP;
+                            const HeapT *col = selheap + p + k * P;
+#pragma unroll 2
+                            for (int j = 0; j < ck; ++j) {
+                                const HeapT v = col[j * 64];
+#pragma unroll
+                                for (int q = 0; q < 4; ++q)
+                                    cn[q] += (v > e[q] ? 1 : 0) + (v >= e[q] ? 0x10000 : 0);
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int gt = cn[q] & 0xFFFF, ge = cn[q] >> 16;
+                            if (i0 + q < own && gt < rank && rank <= ge) { found = 1; ans = e[q]; }
+                        }
+                    }
+                }
+                // copy 0 takes the element found by any copy (equal values
+                // where several are found)
+                HeapT ans0 = ans;
+                int found0 = found;
+#pragma unroll
+                for (int k = 1; k < S; ++k) {
+                    const int fk = __shfl(found, p + k * P, 64);
+                    const HeapT ak = __shfl(ans, p + k * P, 64);
+                    if (fk && !found0) { found0 = 1; ans0 = ak; }
+                }
+                int retry = 0;
+                if (!done && kk == 0) {
+                    if (found0) {
+                        const double d2 = (double)ans0;
+                        a.sh_out[b + p] = PREC == SPH_FP64 ? sqrt(d2) : sqrt(d2) / sc;
+                        a.knn_st[b + p] = st_in;
+                    } else if (rank < 1 || rank > CAP) {
+                        // the count stage's h did not hold K within reach
+                        a.sh_out[b + p] = hs.h;
+                        a.knn_st[b + p] = st_in | SPH_ST_NOCONV;
+                    } else {
+                        // shell too thin: stage 4
+                        a.knn_st[b + p] = st_in | kSelRetry;
+                        retry = 1;
+                    }
+                }
+                if (__ballot(retry != 0) != 0 && l == 0)
+                    a.knn_items[atomicAdd(&a.queue[kSelRetrySlot], 1)] = item;
+                done = true;
+            } else if (SEL) {
+                // second pass: each copy kept the CAP largest of its share of
+                // the distances inside h; copy 0 takes in the other copies'
+                // heaps (the union's CAP largest contain its rank-th largest
+                // for any rank <= CAP)
                 int seln = sel_n;
                 int hco[S > 1 ? S - 1 : 1];
 #pragma unroll
@@ -1115,11 +1298,22 @@ static hipError_t launch_solve(const Plan &pl, SolveArgs &a, int seg, int64_t gr
     a.seg = seg;
     const dim3 grid((unsigned)grid_n), block(64);
     const bool f32c = pl.prm.precision == SPH_FP32C;
-    if (stage == 2) {
-        // the selection pass needs distances only: one kernel shape per
-        // precision and heap size
-#define SPH_SEL(PR, GR, CP) \
-    hipLaunchKernelGGL((k_solve<PR, GR, kSelTile, SPH_KERNEL_M4, 2, CP>), grid, block, 0, st, a)
+    if (stage == 2 || stage == 4) {
+        // the selection passes need distances only: one kernel shape per
+        // precision and list/heap size
+        if (stage == 2) {
+            e = run_zero_i32(pl.ctrl + kSelRetrySlot, 1, st);
+            if (e != hipSuccess) return e;
+        }
+#define SPH_SEL(PR, GR, CP)                                                                   \
+    do {                                                                                      \
+        if (stage == 2)                                                                       \
+            hipLaunchKernelGGL((k_solve<PR, GR, kSelTile, SPH_KERNEL_M4, 2, CP>), grid, block, \
+                               0, st, a);                                                     \
+        else                                                                                  \
+            hipLaunchKernelGGL((k_solve<PR, GR, kSelTile, SPH_KERNEL_M4, 4, CP>), grid, block, \
+                               0, st, a);                                                     \
+    } while (0)
 #define SPH_SEL_CAP(PR, GR)                                  \
     do {                                                    \
         if (a.sel_cap == 16) SPH_SEL(PR, GR, 16);           \
@@ -1213,6 +1407,7 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
     // over only while its count stays within the heap
     a.sel_cap = pl.prm.n_tol + 2.0 <= 16.0 ? 16 : (pl.prm.n_tol + 2.0 <= 32.0 ? 32 : 64);
     a.knn_st = pl.knn_st;
+    a.knn_items = pl.knn_items;
     a.sh_out = pl.sh0;
     hipError_t e = hipSuccess;
     if (stats) {
@@ -1247,6 +1442,7 @@ hipError_t run_solve(Plan &pl, const int64_t *goff, void *rho, void *h, void *nw
             a.n_items = ceil_div(pl.n, kSelTile);
             const int64_t g2 = pl.grouped ? full : (a.n_items < full ? a.n_items : full);
             e = launch_solve(pl, a, kSelTile, g2 > 0 ? g2 : 1, 2, st);
+            if (e == hipSuccess) e = launch_solve(pl, a, kSelTile, g2 > 0 ? g2 : 1, 4, st);
         }
         if (e == hipSuccess && pl.grouped) {
             pl.prm.segment = seg;

@@ -111,6 +111,10 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
     if (p->mode == SPH_KNN) {
         pl.knn_h = (double *)take(8 * N);
         pl.knn_st = (int32_t *)take(4 * N);
+        // at most one entry per selection tile, also with groups (each
+        // group's tiles start at its first particle)
+        pl.knn_items = (int32_t *)take(4 * ((size_t)ceil_div((int64_t)N, (int64_t)kSelTile) +
+                                            (size_t)G + 1));
     }
     pl.total = off;
     return SPH_OK;

@@ -10,6 +10,9 @@ namespace sph {
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr int kWave = 64;
+// Particles per wave tile of the exact-K selection passes (4 lanes per
+// particle, each with its own list or heap)
+constexpr int kSelTile = 16;
 
 // Radix sort geometry: one 256-thread block = 4 waves; a wave ranks ROUNDS
 // rounds of 64 consecutive keys, so a block tile holds 4*64*ROUNDS keys.
@@ -152,13 +155,15 @@ struct Plan {
     uint32_t *ghist = nullptr;
     int64_t nb_gsort = 0;        // radix blocks of the group-order sort
     int64_t *goff = nullptr;     // groups: the caller's offsets made well formed (G+1)
-    int32_t *ctrl = nullptr;     // [0] work queue head, [1..] reserved
+    int32_t *ctrl = nullptr;     // [0] work queue head, [8] exact-K tiles left, others reserved
     uint64_t *stats = nullptr;   // 4 x uint64 device counters
     double *adj = nullptr;       // adjoint, sorted order: alpha, beta, gamma, grad_rho, grad_h (5 x n)
     float *rmq = nullptr;        // adjoint: range-max table of h (grid units), rmq_levels x n
     int rmq_levels = 0;
     double *knn_h = nullptr;     // exact-K mode: count-stage h and status, sorted order
     int32_t *knn_st = nullptr;
+    int32_t *knn_items = nullptr;  // exact-K mode: selection tiles left to the heap pass
+
     // after sorting
     uint64_t *skeys = nullptr;
     int32_t *perm = nullptr;

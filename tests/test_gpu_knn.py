@@ -7,11 +7,12 @@ particles (groups smaller than K, periodic sets that cannot supply K below the
 cap, bad inputs) keep the oracle's h.  The low status bits count the count
 stage's updates, which the oracle does not have, so only the flag bits are
 compared.  FP32C selects from binary32 coordinates taken relative to the
-centre of the particle's tile, with binary64 differences: each coordinate
-carries a rounding error of at most 2^-24 of its offset from that centre, a
-few h in the worst case, so |dh|/h stays near 1e-6; the tests ask 1e-5 for
-99.9% of particles and 1e-4 for every one, with rho at the GPU's own h within
-1e-5 of the oracle's sum at that h.
+centre of the particle's tile, with binary32 differences and squares: each
+coordinate carries a rounding error of at most 2^-24 of its offset from that
+centre, a few h in the worst case, and the squared distance a few 2^-24 of
+itself more, so |dh|/h stays near 1e-6; the tests ask 1e-5 for 99.9% of
+particles and 1e-4 for every one, with rho at the GPU's own h within 1e-5 of
+the oracle's sum at that h.
 """
 import numpy as np
 import pytest
