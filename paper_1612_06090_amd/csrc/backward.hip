@@ -67,6 +67,10 @@ struct AdjArgs {
     double box;
     int32_t bits;
     double *alpha, *beta, *gamma;
+    // binary32 form, written by pass 1 for pass 2: each particle's h and 1/h
+    // in grid units, alpha, beta, and gamma, rounded as pass 2 uses them
+    float4 *rec;
+    float *recg;
     const double *grs, *ghs;
     int32_t phase;
     int32_t out_f32;
@@ -132,12 +136,19 @@ struct AdjLDS {
     int32_t wk_st[kWorkCap<PREC>], wk_en[kWorkCap<PREC>], wk_c[kWorkCap<PREC>][3],
         wk_L[kWorkCap<PREC>];
     int32_t rg_start[64], rg_excl[64], rg_code[64], rg_mark[64];
-    float sp[4][kAdjP];   // the tile's spheres: x, y, z (grid units, range origin), radius
+    // the range's spheres: x, y, z (grid units, range origin), radius; slots
+    // of particles outside the range hold a sphere that reaches nothing
+    float4 sp[kAdjP];
+    // each particle of the tile: grid cell and radius bits, fraction (read
+    // once per range rather than held in registers through the walk)
+    int4 oq[kAdjP];
+    float4 of[kAdjP];
     float4 box[2];        // binary32: the range's box (min, max) and Ht^2
     AdjStage<PREC> st;
 };
 
-template <int PREC, bool GROUPED, int KERNEL>
+// PHASE 1 and 2: the two passes of the adjoint; 3: the scatter form
+template <int PREC, bool GROUPED, int KERNEL, int PHASE>
 __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
     using KT = Kern<KERNEL>;
     __shared__ AdjLDS<PREC> S;
@@ -204,8 +215,17 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
         }
         const uint64_t vm = __ballot(valid) & kTileMask;
         double ak = 0.0, bk = 0.0;  // own alpha, beta (phase 2)
-        if (a.phase == 2 && valid) { ak = a.alpha[s]; bk = a.beta[s]; }
-        const float akf = (float)ak, bkf = (float)bk, mkf = (float)mk;
+        float akf = 0.f, bkf = 0.f;
+        if constexpr (PREC == SPH_FP32C) {
+            if (PHASE == 2 && valid) {
+                const float4 r4 = a.rec[s];
+                akf = r4.z;
+                bkf = r4.w;
+            }
+        } else {
+            if (PHASE == 2 && valid) { ak = a.alpha[s]; bk = a.beta[s]; }
+        }
+        const float mkf = (float)mk;
 
         // per-lane partial sums: phase 1 -> S1, R, T ; phase 2 -> gx, gy, gz, gm
         double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
@@ -215,10 +235,15 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
         const float hk2f = (float)(hq * hq);
         const float hkinvf = (float)(1.0 / hq);
         const double hk2 = hk * hk, hkinv = 1.0 / hk;
+        if (kk == 0) {
+            S.oq[p] = make_int4(qxk, qyk, qzk, __float_as_int(Hk));
+            S.of[p] = make_float4(fxk, fyk, fzk, 0.f);
+        }
+        __builtin_amdgcn_wave_barrier();
         const int64_t gbase = GROUPED ? a.goff[g] : 0;
         const int64_t gend = GROUPED ? a.goff[g + 1] : a.n;
         float hall = 0.f;  // largest h of the set (phase 2: any sphere may reach)
-        if (a.phase >= 2 && vm != 0)
+        if (PHASE >= 2 && vm != 0)
             hall = uniform_f(range_hmax(a, (int32_t)gbase, (int32_t)gend));
 
         // Particle ranges of the tile, each walked on its own.  A range whose
@@ -227,21 +252,26 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
         // particles: the walk region stays compact and the binary32
         // coordinates relative to the range's origin keep the precision of the
         // local separation.
-        int rs_a[5], rs_b[5];
-        int rsp = 0;
-        if (vm != 0) { rs_a[0] = 0; rs_b[0] = kAdjP; rsp = 1; }
-        while (rsp > 0) {
-            --rsp;
-            const int la = rs_a[rsp], lb = rs_b[rsp];
+        // The ranges still pending always tile [la, kAdjP) in order (depth
+        // first, lower half first), so they are kept as the bit set of their
+        // first slots.
+        uint32_t starts = vm != 0 ? 1u : 0u;
+        while (starts) {
+            const int la = __builtin_ctz(starts);
+            starts &= starts - 1;
+            const int lb = starts ? __builtin_ctz(starts) : kAdjP;
             const bool in_sub = valid && p >= la && p < lb;
             const uint64_t sm = __ballot(in_sub) & kTileMask;
             if (sm == 0) continue;
             const int first = __ffsll((unsigned long long)sm) - 1;
-            const int32_t t0 = readlane_i(qxk, first), t1 = readlane_i(qyk, first),
-                          t2 = readlane_i(qzk, first);
-            const float pk0 = (float)(qxk - t0) + fxk;
-            const float pk1 = (float)(qyk - t1) + fyk;
-            const float pk2 = (float)(qzk - t2) + fzk;
+            const int4 oq = S.oq[p];
+            const float4 of = S.of[p];
+            const float Hk = __int_as_float(oq.w);
+            const int32_t t0 = readlane_i(oq.x, first), t1 = readlane_i(oq.y, first),
+                          t2 = readlane_i(oq.z, first);
+            const float pk0 = (float)(oq.x - t0) + of.x;
+            const float pk1 = (float)(oq.y - t1) + of.y;
+            const float pk2 = (float)(oq.z - t2) + of.z;
             const float mn0 = uniform_f(wave_min(in_sub ? pk0 : INFINITY));
             const float mx0 = uniform_f(wave_max(in_sub ? pk0 : -INFINITY));
             const float mn1 = uniform_f(wave_min(in_sub ? pk1 : INFINITY));
@@ -255,17 +285,12 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 uint64_t t = sm;
                 for (int k = __popcll(sm) / 2; k > 0; --k) t &= t - 1;
                 const int mid = __ffsll((unsigned long long)t) - 1;
-                rs_a[rsp] = mid; rs_b[rsp] = lb; ++rsp;
-                rs_a[rsp] = la; rs_b[rsp] = mid; ++rsp;
+                starts |= (1u << la) | (1u << mid);
                 continue;
             }
             __syncthreads();
-            if (kk == 0) {
-                S.sp[0][p] = pk0;
-                S.sp[1][p] = pk1;
-                S.sp[2][p] = pk2;
-                S.sp[3][p] = Hk;
-            }
+            if (kk == 0)
+                S.sp[p] = in_sub ? make_float4(pk0, pk1, pk2, Hk) : make_float4(1e30f, 1e30f, 1e30f, 0.f);
             if (l == 0) {
                 S.box[0] = make_float4(mn0, mn1, mn2, Ht * Ht);
                 S.box[1] = make_float4(mx0, mx1, mx2, 0.f);
@@ -274,7 +299,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
 
             int wsz = 0;   // work stack size (uniform)
             int nl = 0;    // leaves collected (uniform)
-            float Rroot = a.phase >= 2 && hall > Ht ? hall : Ht;
+            float Rroot = PHASE >= 2 && hall > Ht ? hall : Ht;
             Rroot = Rroot * (1.0f + 0x1p-12f) + 1.0f;
 
             // one candidate of the leaf list (flat index gidx) into registers
@@ -285,9 +310,9 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                     const int cc = S.rg_code[lo];
                     const int sh0 = (cc & 3) - 1, sh1 = ((cc >> 2) & 3) - 1, sh2 = ((cc >> 4) & 3) - 1;
                     const double hj = a.sh[j];
-                    const double aj = a.phase == 2 ? a.alpha[j] : 0.0;
-                    const double bj = a.phase == 2 ? a.beta[j] : 0.0;
-                    const double gj = a.phase >= 2 ? a.gamma[j] : 0.0;
+                    const double aj = PHASE == 2 ? a.alpha[j] : 0.0;
+                    const double bj = PHASE == 2 ? a.beta[j] : 0.0;
+                    const double gj = PHASE >= 2 ? a.gamma[j] : 0.0;
                     if constexpr (PREC == SPH_FP64) {
                         c.p = a.sp[j];
                         c.s = make_double4((double)sh0 * a.box, (double)sh1 * a.box,
@@ -333,11 +358,13 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                                       (float)(q4.y + sh1 * W - t1) + f4.y,
                                       (float)(q4.z + sh2 * W - t2) + f4.z,
                                       __int_as_float(q4.w));
-                    if (a.phase >= 2) {
+                    if (PHASE == 2) {
+                        const float4 hr = a.rec[j];
+                        c.h = make_float4(hr.x, hr.y, hr.z, hr.w);
+                        c.g = a.recg[j];
+                    } else if (PHASE == 3) {
                         const double hqj = a.sh[j] * sc;
-                        const double aj = a.phase == 2 ? a.alpha[j] : 0.0;
-                        const double bj = a.phase == 2 ? a.beta[j] : 0.0;
-                        c.h = make_float4((float)hqj, (float)(1.0 / hqj), (float)aj, (float)bj);
+                        c.h = make_float4((float)hqj, (float)(1.0 / hqj), 0.f, 0.f);
                         c.g = (float)a.gamma[j];
                     } else {
                         c.h = make_float4(1.f, 1.f, 0.f, 0.f);
@@ -357,7 +384,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                         const double dz = (c.p.z - zk) + c.s.z;
                         const double r2 = (dx * dx + dy * dy) + dz * dz;
                         const bool in1 = r2 < hk2;
-                        if (a.phase == 1) {
+                        if (PHASE == 1) {
                             if (in1) {
                                 const double q = sqrt(r2) * hkinv;
                                 double f, fp;
@@ -366,7 +393,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                                 acc1 += c.p.w * f;
                                 acc2 += c.p.w * q * fp;
                             }
-                        } else if (a.phase == 3) {
+                        } else if (PHASE == 3) {
                             // scatter form: gather sum at h_k, spread sum at h_j
                             const bool in2 = r2 < c.h.x * c.h.x;
                             if (in1 || in2) {
@@ -402,7 +429,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                     // a branch would skip nothing; out of range, q is clamped to 1,
                     // where f and f' vanish, and the selects give exact zeros
                     float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
-                    if (a.phase == 1) {
+                    if (PHASE == 1) {
 #pragma unroll 4
                         for (int u = 0; u < nu; ++u) {
                             const float4 cp = S.st.p[u * kAdjS + kk];
@@ -418,7 +445,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                             s1 = __builtin_fmaf(cp.w, fs, s1);
                             s2 = __builtin_fmaf(cp.w, qfp, s2);
                         }
-                    } else if (a.phase == 3) {
+                    } else if (PHASE == 3) {
 #pragma unroll 2
                         for (int u = 0; u < nu; ++u) {
                             const int t = u * kAdjS + kk;
@@ -438,7 +465,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                             s2 += in2 ? 1.f : 0.f;
                         }
                     } else {
-#pragma unroll 2
+#pragma unroll 1
                         for (int u = 0; u < nu; ++u) {
                             const int t = u * kAdjS + kk;
                             const float4 cp = S.st.p[t];
@@ -524,14 +551,14 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                         rcarry = __builtin_amdgcn_readlane(rr, 63);
                         const int gidx = cbase + l;
                         bool keep = false;
-                        AdjCand<PREC> c;
+                        AdjCand<PREC> c{};
                         if (gidx < total) {
                             load_cand_r(gidx, rr, c);
                             const float4 bl = S.box[0], bh = S.box[1];
                             const float ex = c.p.x - fminf(fmaxf(c.p.x, bl.x), bh.x);
                             const float ey = c.p.y - fminf(fmaxf(c.p.y, bl.y), bh.y);
                             const float ez = c.p.z - fminf(fmaxf(c.p.z, bl.z), bh.z);
-                            const float R2 = a.phase >= 2 ? fmaxf(bl.w, c.h.x * c.h.x) : bl.w;
+                            const float R2 = PHASE >= 2 ? fmaxf(bl.w, c.h.x * c.h.x) : bl.w;
                             keep = __builtin_fmaf(ex, ex, __builtin_fmaf(ey, ey, ez * ez)) <=
                                    R2 * (1.0f + 0x1p-12f);
                         }
@@ -570,33 +597,37 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
             // node test: does the node box (grid units, relative to the range
             // origin) come within the radius of some sphere of the range -- its
             // own h (phase 1), or max(h, the node's largest h) (phase 2)?
-            auto node_pass = [&](int64_t c0, int64_t c1, int64_t c2, int L, int32_t st, int32_t en) {
+            // (cell coordinates at level L, images included, and their corners
+            // in grid units stay within [-2^22, 2^23): 32 bits suffice)
+            auto node_pass = [&](int32_t c0, int32_t c1, int32_t c2, int L, int32_t st, int32_t en) {
                 const int ex = B - L;
-                const int64_t sd = (int64_t)1 << ex;
+                const int32_t sd = 1 << ex;
                 const float side = (float)sd;
                 const float lo0 = (float)(c0 * sd - t0), lo1 = (float)(c1 * sd - t1),
                             lo2 = (float)(c2 * sd - t2);
-                const float hm = a.phase >= 2 ? range_hmax(a, st, en) : 0.f;
+                const float hm = PHASE >= 2 ? range_hmax(a, st, en) : 0.f;
                 // slack covers the binary32 rounding of tile coordinates (up to
                 // 2^-3 grid units at 2^21) and of the node corners
                 const float slack = side * 0x1p-12f + 1.0f;
+                // every slot, unrolled, so that the sphere reads issue together
+                // (a far slot's distance squares to infinity and never passes)
                 bool pass = false;
-                for (uint64_t it = sm; it; it &= it - 1) {
-                    const int i = __ffsll((unsigned long long)it) - 1;
-                    const float x = S.sp[0][i], y = S.sp[1][i], z = S.sp[2][i];
-                    const float H = fmaxf(S.sp[3][i], hm) * (1.0f + 0x1p-12f) + slack;
-                    const float g0 = fmaxf(0.f, fmaxf(lo0 - x, x - (lo0 + side)));
-                    const float g1 = fmaxf(0.f, fmaxf(lo1 - y, y - (lo1 + side)));
-                    const float g2 = fmaxf(0.f, fmaxf(lo2 - z, z - (lo2 + side)));
-                    pass = pass || (g0 * g0 + g1 * g1 + g2 * g2 <= H * H);
+#pragma unroll
+                for (int i = 0; i < kAdjP; ++i) {
+                    const float4 q = S.sp[i];
+                    const float H = fmaxf(q.w, hm) * (1.0f + 0x1p-12f) + slack;
+                    const float g0 = fmaxf(0.f, fmaxf(lo0 - q.x, q.x - (lo0 + side)));
+                    const float g1 = fmaxf(0.f, fmaxf(lo1 - q.y, q.y - (lo1 + side)));
+                    const float g2 = fmaxf(0.f, fmaxf(lo2 - q.z, q.z - (lo2 + side)));
+                    pass = pass | (g0 * g0 + g1 * g1 + g2 * g2 <= H * H);
                 }
                 return pass;
             };
 
             // append passing nodes of this round: leaves to the leaf list, the rest
             // to the work stack (a full stack turns them into leaves)
-            auto place = [&](bool pass, bool leaf, int32_t st, int32_t en, int64_t c0, int64_t c1,
-                             int64_t c2, int L) {
+            auto place = [&](bool pass, bool leaf, int32_t st, int32_t en, int32_t c0, int32_t c1,
+                             int32_t c2, int L) {
                 uint64_t wm = __ballot(pass && !leaf);
                 const int nw = __popcll(wm);
                 if (wsz + nw > kWorkCap<PREC>) {
@@ -614,9 +645,9 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                     const int k = wsz + (int)mbcnt(wm);
                     S.wk_st[k] = st;
                     S.wk_en[k] = en;
-                    S.wk_c[k][0] = (int32_t)c0;
-                    S.wk_c[k][1] = (int32_t)c1;
-                    S.wk_c[k][2] = (int32_t)c2;
+                    S.wk_c[k][0] = c0;
+                    S.wk_c[k][1] = c1;
+                    S.wk_c[k][2] = c2;
                     S.wk_L[k] = L;
                 }
                 if ((lm >> l) & 1ull) {
@@ -645,20 +676,20 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                     const int nd = l >> 3, ch = l & 7;
                     bool pass = false, leaf = false;
                     int32_t st = 0, en = 0, pen = 0;
-                    int64_t c0 = 0, c1 = 0, c2 = 0;
+                    int32_t c0 = 0, c1 = 0, c2 = 0;
                     int L = 0;
                     if (nd < n8) {
                         const int k = base + nd;
                         const int32_t pst = S.wk_st[k];
                         pen = S.wk_en[k];
                         const int pL = S.wk_L[k];
-                        const int64_t p0 = S.wk_c[k][0], p1 = S.wk_c[k][1], p2 = S.wk_c[k][2];
+                        const int32_t p0 = S.wk_c[k][0], p1 = S.wk_c[k][1], p2 = S.wk_c[k][2];
                         L = pL + 1;
                         c0 = 2 * p0 + ((ch >> 2) & 1);
                         c1 = 2 * p1 + ((ch >> 1) & 1);
                         c2 = 2 * p2 + (ch & 1);
                         // key range of the child: its Morton prefix (wrapped) at level L
-                        const int64_t m = ((int64_t)1 << L) - 1;
+                        const int32_t m = (int32_t)((1u << L) - 1u);
                         const uint64_t cm = morton3((uint64_t)(c0 & m), (uint64_t)(c1 & m),
                                                     (uint64_t)(c2 & m));
                         if (!GROUPED && L <= a.Ld) {
@@ -698,21 +729,22 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                 if (Lr > a.Ld) Lr = a.Ld;
                 if (Lr < 1) Lr = 1;
                 ex = B - Lr;
-                const int64_t lo0 = ((int64_t)t0 + (int64_t)floorf(mn0 - Rroot) - 1) >> ex;
-                const int64_t lo1 = ((int64_t)t1 + (int64_t)floorf(mn1 - Rroot) - 1) >> ex;
-                const int64_t lo2 = ((int64_t)t2 + (int64_t)floorf(mn2 - Rroot) - 1) >> ex;
-                const int64_t hi0 = ((int64_t)t0 + (int64_t)floorf(mx0 + Rroot) + 1) >> ex;
-                const int64_t hi1 = ((int64_t)t1 + (int64_t)floorf(mx1 + Rroot) + 1) >> ex;
-                const int64_t hi2 = ((int64_t)t2 + (int64_t)floorf(mx2 + Rroot) + 1) >> ex;
-                const int64_t nx = hi0 - lo0 + 1, ny = hi1 - lo1 + 1, nz = hi2 - lo2 + 1;
-                const int64_t nroot = nx * ny * nz;  // at most 9^3 (6^3 at level 1)
-                const int64_t msk = ((int64_t)1 << Lr) - 1;
+                // (grid coordinates of the region stay within [-2^22, 2^23))
+                const int32_t lo0 = (t0 + (int32_t)floorf(mn0 - Rroot) - 1) >> ex;
+                const int32_t lo1 = (t1 + (int32_t)floorf(mn1 - Rroot) - 1) >> ex;
+                const int32_t lo2 = (t2 + (int32_t)floorf(mn2 - Rroot) - 1) >> ex;
+                const int32_t hi0 = (t0 + (int32_t)floorf(mx0 + Rroot) + 1) >> ex;
+                const int32_t hi1 = (t1 + (int32_t)floorf(mx1 + Rroot) + 1) >> ex;
+                const int32_t hi2 = (t2 + (int32_t)floorf(mx2 + Rroot) + 1) >> ex;
+                const int32_t nx = hi0 - lo0 + 1, ny = hi1 - lo1 + 1, nz = hi2 - lo2 + 1;
+                const int32_t nroot = nx * ny * nz;  // at most 9^3 (6^3 at level 1)
+                const int32_t msk = (int32_t)((1u << Lr) - 1u);
                 const int sh = 3 * (a.Ld - Lr);
-                for (int64_t rb = 0; rb < nroot; rb += 64) {
-                    const int64_t r = rb + l;
+                for (int32_t rb = 0; rb < nroot; rb += 64) {
+                    const int32_t r = rb + l;
                     bool pass = false, leaf = false;
                     int32_t st = 0, en = 0;
-                    int64_t c0 = 0, c1 = 0, c2 = 0;
+                    int32_t c0 = 0, c1 = 0, c2 = 0;
                     if (r < nroot) {
                         c0 = lo0 + r % nx;
                         c1 = lo1 + (r / nx) % ny;
@@ -752,7 +784,7 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
         }
 
         // ---- per-particle results (copy 0 writes)
-        if (a.phase == 1) {
+        if (PHASE == 1) {
             if (mine && kk == 0) {
                 double al = 0.0, be = 0.0, ga = 0.0;
                 if (valid) {
@@ -765,11 +797,17 @@ __global__ __launch_bounds__(64) void k_adjoint(AdjArgs a) {
                     be = lam * KT::count / hk;
                     ga = gr * KT::sigma / (hk * hk * hk);
                 }
-                a.alpha[s] = al;
-                a.beta[s] = be;
-                a.gamma[s] = ga;
+                if constexpr (PREC == SPH_FP32C) {
+                    const double hqs = hk * sc;
+                    a.rec[s] = make_float4((float)hqs, (float)(1.0 / hqs), (float)al, (float)be);
+                    a.recg[s] = (float)ga;
+                } else {
+                    a.alpha[s] = al;
+                    a.beta[s] = be;
+                    a.gamma[s] = ga;
+                }
             }
-        } else if (a.phase == 3) {
+        } else if (PHASE == 3) {
             if (mine && kk == 0) {
                 // gx: rho_s, gy: rho_sym (optional), gz: int32 count (optional)
                 const int64_t oi = a.perm[s];
@@ -872,6 +910,7 @@ static void adj_args(const Plan &pl, const int64_t *goff, AdjArgs &a) {
     a.box = pl.prm.box;
     a.bits = pl.bits;
     a.alpha = pl.adj; a.beta = pl.adj + n; a.gamma = pl.adj + 2 * n;
+    a.rec = pl.adj_rec; a.recg = pl.adj_g;
     a.grs = pl.adj + 3 * n; a.ghs = pl.adj + 4 * n;
     a.out_f32 = pl.prm.io_dtype == SPH_F32;
     a.ost = pl.out_stride;
@@ -887,13 +926,19 @@ static hipError_t launch_adjoint(const Plan &pl, AdjArgs &a, hipStream_t st) {
     const dim3 grid((unsigned)(pl.grouped ? full : (a.n_items < full ? a.n_items : full)));
     const bool f32c = pl.prm.precision == SPH_FP32C;
     const bool wc6 = pl.prm.kernel == SPH_KERNEL_WENDLAND_C6;
-#define SPH_ADJ(PR, GR)                                                                       \
-    do {                                                                                      \
-        if (wc6)                                                                              \
-            hipLaunchKernelGGL((k_adjoint<PR, GR, SPH_KERNEL_WENDLAND_C6>), grid, dim3(64), 0, \
-                               st, a);                                                        \
-        else                                                                                  \
-            hipLaunchKernelGGL((k_adjoint<PR, GR, SPH_KERNEL_M4>), grid, dim3(64), 0, st, a); \
+#define SPH_ADJ_K(PR, GR, K)                                                              \
+    do {                                                                                  \
+        if (a.phase == 1)                                                                 \
+            hipLaunchKernelGGL((k_adjoint<PR, GR, K, 1>), grid, dim3(64), 0, st, a);      \
+        else if (a.phase == 2)                                                            \
+            hipLaunchKernelGGL((k_adjoint<PR, GR, K, 2>), grid, dim3(64), 0, st, a);      \
+        else                                                                              \
+            hipLaunchKernelGGL((k_adjoint<PR, GR, K, 3>), grid, dim3(64), 0, st, a);      \
+    } while (0)
+#define SPH_ADJ(PR, GR)                                                 \
+    do {                                                                \
+        if (wc6) SPH_ADJ_K(PR, GR, SPH_KERNEL_WENDLAND_C6);             \
+        else SPH_ADJ_K(PR, GR, SPH_KERNEL_M4);                          \
     } while (0)
     if (!pl.grouped) {
         if (f32c) SPH_ADJ(SPH_FP32C, false);
@@ -903,6 +948,7 @@ static hipError_t launch_adjoint(const Plan &pl, AdjArgs &a, hipStream_t st) {
         else SPH_ADJ(SPH_FP64, true);
     }
 #undef SPH_ADJ
+#undef SPH_ADJ_K
     return hipGetLastError();
 }
 

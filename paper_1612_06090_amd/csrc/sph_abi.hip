@@ -106,6 +106,8 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
     pl.ctrl = (int32_t *)take(64);
     pl.stats = (uint64_t *)take(64);
     pl.adj = (double *)take(5 * 8 * N);
+    pl.adj_rec = (float4 *)take(16 * N);
+    pl.adj_g = (float *)take(4 * N);
     pl.rmq_levels = ceil_log2_i64((int64_t)N) + 1;
     pl.rmq = (float *)take(4 * N * (size_t)pl.rmq_levels);
     if (p->mode == SPH_KNN) {

@@ -158,6 +158,8 @@ struct Plan {
     int32_t *ctrl = nullptr;     // [0] work queue head, [8] exact-K tiles left, others reserved
     uint64_t *stats = nullptr;   // 4 x uint64 device counters
     double *adj = nullptr;       // adjoint, sorted order: alpha, beta, gamma, grad_rho, grad_h (5 x n)
+    float4 *adj_rec = nullptr;   // adjoint, binary32 form: h, 1/h (grid units), alpha, beta (n)
+    float *adj_g = nullptr;      //   and gamma (n)
     float *rmq = nullptr;        // adjoint: range-max table of h (grid units), rmq_levels x n
     int rmq_levels = 0;
     double *knn_h = nullptr;     // exact-K mode: count-stage h and status, sorted order
