@@ -35,7 +35,7 @@
 
 namespace sph {
 
-constexpr int kLeafMax = 16;   // a walk node with at most this many particles is a leaf
+constexpr int kLeafMax = 32;   // a walk node with at most this many particles is a leaf
 // walk stack capacity (overflowing nodes become leaves); the binary32 form
 // gives half of it to the candidate staging buffer
 template <int PREC>
