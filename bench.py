@@ -118,19 +118,27 @@ FLOP_ADJ_PAIR = 60.0
 SORT_BYTES_PER_PARTICLE = 300.0   # keys 36, 8 radix passes 192, histograms 8, permute 64
 
 
-def _executed(summary, flop, kms):
+def _executed(summary, flop, kms, form="fp32c"):
     """Counter-measured binary32 VALU work of a unit (all 64 lanes of every
     issued instruction) at this run's kernel time, beside the algorithmic
     count, and the VALU lane utilisation: the mean fraction of the 64 lanes
     active per issued VALU instruction (SQ_THREAD_CYCLES_VALU over
     64 x SQ_ACTIVE_INST_VALU), the GPU counterpart of the vector efficiency
     of Sec. IV-C (Eq. 2, speed-up over vector length).  None without a
-    summary for the current source."""
+    summary for the current source.  The FP64 form is counted in binary64
+    FLOP against the binary64 peak (its binary32 work beside it)."""
     if summary is None:
         return None
-    ex = summary["executed_f32_flop_per_launch"]
+    if form == "fp64":
+        ex = summary["executed_f64_flop_per_launch"]
+        peak = PEAK_FP64
+    else:
+        ex = summary["executed_f32_flop_per_launch"]
+        peak = PEAK_FP32
     out = {"flop_per_launch": ex, "achieved": ex / (kms * 1e-3) / 1e12,
-           "frac": ex / (kms * 1e-3) / PEAK_FP32, "algorithmic_over_executed": flop / ex}
+           "frac": ex / (kms * 1e-3) / peak, "algorithmic_over_executed": flop / ex}
+    if form == "fp64":
+        out["f32_flop_per_launch"] = summary["executed_f32_flop_per_launch"]
     c = summary.get("counters_per_launch", {})
     if c.get("SQ_ACTIVE_INST_VALU") and c.get("SQ_THREAD_CYCLES_VALU"):
         out["valu_lane_utilisation"] = c["SQ_THREAD_CYCLES_VALU"] / (
@@ -658,15 +666,17 @@ def measured_traffic():
     return d.get("bytes_per_launch")
 
 
-def profile_run(steps):
-    """FP32C solves plus one plain copy of COPY_MIB MiB (the counter calibration)."""
+def profile_run(steps, fp64=False):
+    """FP32C (or FP64) solves plus one plain copy of COPY_MIB MiB (the counter
+    calibration)."""
     import torch
     import paper_1612_06090_amd as sph
     import sphgen
     ps = sphgen.config("clustered2^20")
     d = {k: torch.tensor(getattr(ps, k), dtype=torch.float64, device="cuda")
          for k in ("x", "y", "z", "m", "h_init")}
-    p = sph.default_params(n_target=ps.n_target, n_tol=ps.n_tol, precision=sph.FP32C)
+    p = sph.default_params(n_target=ps.n_target, n_tol=ps.n_tol,
+                           precision=sph.FP64 if fp64 else sph.FP32C)
     for _ in range(steps):
         sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p)
     src = torch.ones(COPY_MIB << 18, dtype=torch.float32, device="cuda")
@@ -745,6 +755,8 @@ VALU_WEIGHTS = {"f32": {"SQ_INSTS_VALU_ADD_F32": 1, "SQ_INSTS_VALU_MUL_F32": 1,
 VALU_TARGETS = {
     # kernel -> (summary file, source it is tied to, what one unit is)
     "k_solve": (VALU_JSON, SOLVE_SRC, "launch"),
+    "k_solve_fp64": (os.path.join(ROOT, "profiles", "k_solve_fp64_clustered2p20_valu.txt"),
+                     SOLVE_SRC, "launch"),
     "k_adjoint": (os.path.join(ROOT, "profiles", "k_adjoint_clustered2p20_valu.txt"),
                   os.path.join(ROOT, "paper_1612_06090_amd", "csrc", "backward.hip"),
                   "backward call (both passes)"),
@@ -761,11 +773,12 @@ def summarize_valu(cmd, *csvs, kernel="k_solve", calls=None):
     out_path, src, unit = VALU_TARGETS[kernel]
     if kernel == "k_solve":
         out_path = VALU_JSON
+    match = "k_solve" if kernel.startswith("k_solve") else kernel
     per = {}
     for path in csvs:
         acc = {}
         for r in csv.DictReader(open(path)):
-            if kernel not in r["Kernel_Name"]:
+            if match not in r["Kernel_Name"]:
                 continue
             key = (r["Counter_Name"], r["Dispatch_Id"])
             acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
@@ -778,10 +791,11 @@ def summarize_valu(cmd, *csvs, kernel="k_solve", calls=None):
     flop = {t: 64.0 * sum(w * mean.get(c, 0.0) for c, w in ws.items())
             for t, ws in VALU_WEIGHTS.items()}
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    out = {"kernel": ("k_solve (FP32C, 16-particle tiles)" if kernel == "k_solve"
-                      else f"{kernel} (FP32C)"),
+    label = {"k_solve": "k_solve (FP32C, 16-particle tiles)",
+             "k_solve_fp64": "k_solve (FP64, 16-particle tiles)"}.get(kernel, f"{kernel} (FP32C)")
+    out = {"kernel": label,
            "workload": "clustered2^20", "unit": unit,
-           ("solve_hip_sha256" if kernel == "k_solve" else "source_sha256"): sha,
+           ("solve_hip_sha256" if kernel.startswith("k_solve") else "source_sha256"): sha,
            "executed_f32_flop_per_launch": flop["f32"],
            "executed_f64_flop_per_launch": flop["f64"],
            "counters_per_launch": mean,
@@ -806,6 +820,8 @@ def measured_valu(kernel="k_solve"):
     path, src, _ = VALU_TARGETS[kernel]
     if kernel == "k_solve":
         path, key = VALU_JSON, "solve_hip_sha256"
+    elif kernel.startswith("k_solve"):
+        key = "solve_hip_sha256"
     else:
         key = "source_sha256"
     try:
@@ -904,6 +920,7 @@ def measured_sort_traffic():
 
 TRACE_MD = os.path.join(ROOT, "profiles", "k_solve_clustered2p20_kernel_trace.md")
 TRACE_KNN_MD = os.path.join(ROOT, "profiles", "k_solve_exactK295_clustered2p20_kernel_trace.md")
+TRACE_BATCHED_MD = os.path.join(ROOT, "profiles", "k_solve_groups10k_kernel_trace.md")
 
 
 def summarize_trace(stats_csv, cmd, which="headline"):
@@ -911,17 +928,28 @@ def summarize_trace(stats_csv, cmd, which="headline"):
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    if which == "knn":
+    if which == "batched":
+        path = TRACE_BATCHED_MD
+        head = ["# Batched solve on groups10k — rocprofv3 kernel trace", "",
+                "Command (on the GPU host, from the repository root):", "", "    " + cmd, "",
+                "Workload: 10,000 isolated Plummer groups (sizes ~ n^-2 on [32, 131072]), "
+                "2,246,696 particles, N_t = 32 +- 1, FP32C, the autotuned tile size; one "
+                "replay of the HIP graph = group frames and keys, radix sort, permute, "
+                "largest-first group order, group items, density/h solve. Calls include "
+                "the autotuner's trial launches of other tile sizes.", ""]
+    elif which == "knn":
         path = TRACE_KNN_MD
         head = ["# Exact-K stages on clustered2^20 (K = 295, Wendland C6) — rocprofv3 "
                 "kernel trace", "",
                 "Command (on the GPU host, from the repository root):", "", "    " + cmd, "",
                 "Workload: the 2^20-particle clustered set, h = distance of the 295th "
                 "nearest particle (itself first), Wendland C6, count band [K, K + 14]. "
-                "One call = sort + three launches of the density kernel, told apart by "
-                "its last template argument: 1 the count stage (h iterated on the "
-                "integer count), 2 the selection of the K-th distance (16-particle tiles, "
-                "4 lanes per particle, heaps merged), 3 the evaluation at that h. `k_solve<1, ...>` is FP32C, "
+                "One call = sort + four launches of the density kernel, told apart by "
+                "its fifth template argument: 1 the count stage (h iterated on the "
+                "integer count), 2 the selection of the K-th distance from per-lane lists "
+                "of an outer shell (16-particle tiles, 4 lanes per particle), 4 the heap "
+                "selection for the particles whose shell was too thin (only the tiles "
+                "holding one), 3 the evaluation at that h. `k_solve<1, ...>` is FP32C, "
                 "`k_solve<0, ...>` FP64.", ""]
     else:
         path = TRACE_MD
@@ -961,12 +989,16 @@ def main():
                     help="only the exact-K leg (for a kernel trace of its stages)")
     ap.add_argument("--profile-run", action="store_true",
                     help="only FP32C solves + a calibration copy (for rocprofv3 --pmc)")
+    ap.add_argument("--profile-fp64", action="store_true",
+                    help="with --profile-run: FP64 solves instead")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="only the groups10k leg (for a kernel trace of its replays)")
     ap.add_argument("--profile-sort", action="store_true",
                     help="only sph_sort calls at 2^24 + a calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-sort-traffic", nargs="+", metavar="ARG",
                     help="FETCH_CSV WRITE_CSV CMD [CALLS]: write the sph_sort traffic summary")
     ap.add_argument("--summarize-trace", nargs="+", metavar="ARG",
-                    help="STATS_CSV CMD [headline|knn]: write the kernel-trace summary "
+                    help="STATS_CSV CMD [headline|knn|batched]: write the kernel-trace summary "
                          "from rocprofv3 --stats output")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
                     help="write the k_solve traffic summary from two --pmc runs")
@@ -986,7 +1018,7 @@ def main():
         return
     if args.summarize_trace:
         if len(args.summarize_trace) not in (2, 3):
-            ap.error("--summarize-trace takes STATS_CSV CMD [headline|knn]")
+            ap.error("--summarize-trace takes STATS_CSV CMD [headline|knn|batched]")
         summarize_trace(*args.summarize_trace)
         return
     if args.summarize_traffic:
@@ -1003,7 +1035,7 @@ def main():
         summarize_sort_traffic(*args.summarize_sort_traffic)
         return
     if args.profile_run:
-        profile_run(args.steps)
+        profile_run(args.steps, fp64=args.profile_fp64)
         return
     if args.profile_sort:
         profile_sort_run(args.steps)
@@ -1032,6 +1064,10 @@ def main():
     if args.only_knn:
         print(json.dumps({"exact_k": run_knn(sph, torch, d, ps, max(3, args.steps // 2))}),
               flush=True)
+        return
+    if args.only_batched:
+        print(json.dumps({"batched": run_batched(sph, torch, max(3, args.steps), args.warmup,
+                                                 ev)}), flush=True)
         return
     f32 = run_form(sph, torch, d, ps, sph.FP32C, args.steps, args.warmup, ev)
     print(f"[bench] fp32c { {k: v for k, v in f32.items() if k[0] != '_'} }", file=sys.stderr,
@@ -1085,11 +1121,10 @@ def main():
         out = alu_roofline(r["cands"], r["pairs"], r["kernel_ms"], form, region=r["region"])
         out["traffic"] = measured_traffic() if form == "fp32c" else None
         out["kernel_ms_median"] = r["kernel_ms_median"]
-        if form == "fp32c":
-            # counter-measured VALU work of the same launch (all 64 lanes of every
-            # issued instruction, masked lanes included), at this run's kernel time
-            out["executed"] = _executed(measured_valu(), out["flop_per_launch"],
-                                        r["kernel_ms"])
+        # counter-measured VALU work of the same launch (all 64 lanes of every
+        # issued instruction, masked lanes included), at this run's kernel time
+        out["executed"] = _executed(measured_valu("k_solve" if form == "fp32c" else "k_solve_fp64"),
+                                    out["flop_per_launch"], r["kernel_ms"], form)
         return out
 
     value = f32["pairs"] / (f32["ms_per_step"] * 1e-3)

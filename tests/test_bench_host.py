@@ -136,3 +136,21 @@ def test_alu_roofline_weights():
     r = bench.alu_roofline(1e10, 4e9, 10.0, "fp64")
     assert r["flop_per_launch"] == pytest.approx(8e10 + 22 * 4e9)
     assert r["peak"] == pytest.approx(78.6)
+
+
+def test_valu_summary_fp64(tmp_path, monkeypatch):
+    # the FP64 solve: binary64 FLOP against the binary64 peak, binary32 beside it
+    path = str(tmp_path / "fp64.txt")
+    _, src, unit = bench.VALU_TARGETS["k_solve_fp64"]
+    monkeypatch.setitem(bench.VALU_TARGETS, "k_solve_fp64", (path, src, unit))
+    rows = [(1, SOLVE, "SQ_INSTS_VALU_FMA_F64", 100.0), (1, SOLVE, "SQ_INSTS_VALU_ADD_F64", 50.0),
+            (1, SOLVE, "SQ_INSTS_VALU_ADD_F32", 20.0)]
+    a = _csv(tmp_path / "a.csv", rows)
+    bench.summarize_valu("cmd", a, kernel="k_solve_fp64")
+    d = json.load(open(path))
+    assert d["kernel"].startswith("k_solve (FP64")
+    assert d["executed_f64_flop_per_launch"] == pytest.approx(64 * (2 * 100 + 50))
+    ex = bench._executed(bench.measured_valu("k_solve_fp64"), 1.0, 1.0, "fp64")
+    assert ex["flop_per_launch"] == pytest.approx(64 * 250)
+    assert ex["frac"] == pytest.approx(64 * 250 / 1e-3 / bench.PEAK_FP64)
+    assert ex["f32_flop_per_launch"] == pytest.approx(64 * 20)
