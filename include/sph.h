@@ -195,7 +195,8 @@ int sph_workspace_size(const sph_params *params, int64_t n, int32_t n_groups, si
  * Malformed offsets therefore never make a kernel read outside the caller's
  * arrays; the results are those of the corrected groups (the Python binding
  * rejects malformed offsets on the host instead).
- * Any output pointer except keys_out and perm_out may be NULL. */
+ * Any output pointer except keys_out and perm_out may be NULL; no output may
+ * overlap the inputs, the workspace or another output. */
 int sph_sort(const sph_params *params, int64_t n, int32_t n_groups,
              const int64_t *group_offsets,
              const void *x, const void *y, const void *z,

@@ -276,13 +276,16 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_down(int64_t n, const ui
 }
 
 // LSD radix sort of (key, value) pairs over `passes` 8-bit digits; the result
-// ends in the A buffers after an even number of passes.
+// ends in the A buffers after an even number of passes, or in (kfin, vfin)
+// when given (the last pass writes there).
 template <int ROUNDS>
 static hipError_t radix_passes(int64_t n, int64_t nb, int passes, uint64_t *ka, uint64_t *kb,
                                int32_t *va, int32_t *vb, uint32_t *hist, uint32_t *digit_tot,
-                               hipStream_t st, uint64_t **kout, int32_t **vout) {
+                               hipStream_t st, uint64_t **kout, int32_t **vout,
+                               uint64_t *kfin = nullptr, int32_t *vfin = nullptr) {
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
+        if (p == passes - 1 && kfin) { kb = kfin; vb = vfin; }
         hipLaunchKernelGGL(k_radix_up<ROUNDS>, dim3((unsigned)nb), dim3(kSortThreads), 0, st, n,
                            ka, shift, hist, nb);
         hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(kSortThreads), 0, st, hist, nb,
@@ -297,16 +300,18 @@ static hipError_t radix_passes(int64_t n, int64_t nb, int passes, uint64_t *ka, 
     return hipGetLastError();
 }
 
-static hipError_t radix_sort(Plan &pl, int passes, hipStream_t st) {
+static hipError_t radix_sort(Plan &pl, int passes, hipStream_t st, uint64_t *kfin,
+                             int32_t *vfin) {
     if (pl.sort_rounds == 16)
         return radix_passes<16>(pl.n, pl.nb_sort, passes, pl.keysA, pl.keysB, pl.valsA, pl.valsB,
-                                pl.hist, pl.digit_tot, st, &pl.skeys, &pl.perm);
+                                pl.hist, pl.digit_tot, st, &pl.skeys, &pl.perm, kfin, vfin);
     return radix_passes<4>(pl.n, pl.nb_sort, passes, pl.keysA, pl.keysB, pl.valsA, pl.valsB,
-                           pl.hist, pl.digit_tot, st, &pl.skeys, &pl.perm);
+                           pl.hist, pl.digit_tot, st, &pl.skeys, &pl.perm, kfin, vfin);
 }
 
 hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const void *y,
-                             const void *z, hipStream_t st) {
+                             const void *z, hipStream_t st, uint64_t *keys_out,
+                             int32_t *perm_out) {
     const int64_t n = pl.n;
     const unsigned nbk = (unsigned)ceil_div(n, 256);
     const bool f32 = pl.prm.io_dtype == SPH_F32;
@@ -332,7 +337,7 @@ hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return radix_sort(pl, 8, st);
+    return radix_sort(pl, 8, st, keys_out, perm_out);
 }
 
 // ------------------------------------------------------- sorted SoA gather
@@ -568,34 +573,78 @@ static hipError_t scan(const int32_t *in, int32_t *out, int64_t cnt, int32_t *bs
 
 // ------------------------------------------------------------- cell tables
 
-__global__ void k_cell_flags(int64_t n, const uint64_t *skeys, int shift, int32_t *flags) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    flags[s] = (s == 0 || (skeys[s] >> shift) != (skeys[s - 1] >> shift)) ? 1 : 0;
+// Slot s of the sorted keys starts a cell of the level (cell = key >> shift)
+// when it is the first slot or its cell differs from the previous slot's.
+__device__ inline int32_t cell_start_flag(const uint64_t *skeys, int64_t s, int shift) {
+    return (s == 0 || (skeys[s] >> shift) != (skeys[s - 1] >> shift)) ? 1 : 0;
 }
 
-// idx = inclusive scan of the cell-start flags, so the cell of slot s is
-// idx[s] - 1.  Records each cell's id and first slot; tmp gets the first slots.
-__global__ void k_cell_compact(int64_t n, const uint64_t *skeys, int shift, const int32_t *idx,
-                               uint64_t *cell_id, int32_t *cell_start, int32_t *tmp,
-                               int32_t *n_cells) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    const uint64_t c = skeys[s] >> shift;
-    const bool first = s == 0 || c != (skeys[s - 1] >> shift);
-    const int32_t ci = idx[s] - 1;
-    if (first) {
-        tmp[ci] = (int32_t)s;
-        if (cell_id) cell_id[ci] = c;
-        if (cell_start) cell_start[ci] = (int32_t)s;
+// Per scan tile: the number of cell starts (the flags are computed from the
+// keys here and again in k_cell_emit rather than stored).  Slots are taken in
+// rounds of kScanThreads consecutive ones, so that the loads coalesce.
+__global__ __launch_bounds__(kScanThreads) void k_cell_reduce(int64_t n, const uint64_t *skeys,
+                                                             int shift, int32_t *bsum) {
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+    int32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t li = t0 + (int64_t)k * kScanThreads + threadIdx.x;
+        if (li < n) acc += cell_start_flag(skeys, li, shift);
     }
-    if (s == n - 1 && n_cells) *n_cells = idx[s];
+    int32_t tot;
+    block_excl<0, kScanThreads>(acc, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ void k_cell_counts(int64_t n, const int32_t *idx, const int32_t *tmp,
+// With bsum holding the exclusive scan of the tiles' counts, the cell starting
+// at slot s has index ci = the number of starts before s: records its id and
+// first slot (tmp gets the first slots); the last slot stores the number of
+// cells in *nc (and the caller's *n_cells).  The tile is taken in rounds of
+// kScanThreads consecutive slots: a start's index within its round comes from
+// the wave ballots, the rounds' counts are carried.
+__global__ __launch_bounds__(kScanThreads) void k_cell_emit(int64_t n, const uint64_t *skeys,
+                                                           int shift, const int32_t *bsum,
+                                                           uint64_t *cell_id, int32_t *cell_start,
+                                                           int32_t *tmp, int32_t *nc,
+                                                           int32_t *n_cells) {
+    constexpr int NW = kScanThreads / 64;
+    __shared__ int32_t wcnt[kScanItems][NW];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const int64_t t0 = (int64_t)blockIdx.x * kScanTile;
+    int32_t f[kScanItems];
+    uint64_t bm[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t li = t0 + (int64_t)k * kScanThreads + tid;
+        f[k] = li < n ? cell_start_flag(skeys, li, shift) : 0;
+        bm[k] = __ballot(f[k] != 0);
+        if ((tid & 63) == 0) wcnt[k][w] = __popcll(bm[k]);
+    }
+    __syncthreads();
+    int32_t carry = bsum[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        const int64_t li = t0 + (int64_t)k * kScanThreads + tid;
+        int32_t before = carry;
+        for (int v = 0; v < w; ++v) before += wcnt[k][v];
+        const int32_t ci = before + (int32_t)mbcnt(bm[k]);
+        if (f[k]) {
+            tmp[ci] = (int32_t)li;
+            if (cell_id) cell_id[ci] = skeys[li] >> shift;
+            if (cell_start) cell_start[ci] = (int32_t)li;
+        }
+        for (int v = 0; v < NW; ++v) carry += wcnt[k][v];
+        if (li == n - 1) {
+            *nc = ci + f[k];
+            if (n_cells) *n_cells = ci + f[k];
+        }
+    }
+}
+
+__global__ void k_cell_counts(int64_t n, const int32_t *nc_p, const int32_t *tmp,
                               int32_t *cell_count) {
     const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    const int32_t nc = idx[n - 1];
+    const int32_t nc = *nc_p;
     if (c >= nc) return;
     const int32_t e = c + 1 < nc ? tmp[c + 1] : (int32_t)n;
     cell_count[c] = e - tmp[c];
@@ -606,16 +655,18 @@ hipError_t run_contract_cells(Plan &pl, uint64_t *cell_id, int32_t *cell_start,
     const int64_t n = pl.n;
     const int shift = 3 * (pl.bits - pl.Lc);
     const unsigned nbk = (unsigned)ceil_div(n, 256);
-    // the radix sort's second value buffer is free once the sort is done
+    const int64_t nb = ceil_div(n, kScanTile);
+    // the radix sort's second value buffer is free once the sort is done; the
+    // control word 12 holds the number of cells
     int32_t *tmp = pl.perm == pl.valsA ? pl.valsB : pl.valsA;
-    hipLaunchKernelGGL(k_cell_flags, dim3(nbk), dim3(256), 0, st, n, pl.skeys, shift, pl.scan_a);
-    hipError_t e = scan<0, false, true>(pl.scan_a, pl.scan_a, n, pl.bsum, st);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_cell_compact, dim3(nbk), dim3(256), 0, st, n, pl.skeys, shift, pl.scan_a,
-                       cell_id, cell_start, tmp, n_cells);
+    int32_t *nc = pl.ctrl + 12;
+    hipLaunchKernelGGL(k_cell_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, st, n, pl.skeys,
+                       shift, pl.bsum);
+    hipLaunchKernelGGL(k_scan_bsum<0>, dim3(1), dim3(1024), 0, st, pl.bsum, nb);
+    hipLaunchKernelGGL(k_cell_emit, dim3((unsigned)nb), dim3(kScanThreads), 0, st, n, pl.skeys,
+                       shift, pl.bsum, cell_id, cell_start, tmp, nc, n_cells);
     if (cell_count)
-        hipLaunchKernelGGL(k_cell_counts, dim3(nbk), dim3(256), 0, st, n, pl.scan_a, tmp,
-                           cell_count);
+        hipLaunchKernelGGL(k_cell_counts, dim3(nbk), dim3(256), 0, st, n, nc, tmp, cell_count);
     return hipGetLastError();
 }
 
@@ -689,20 +740,6 @@ hipError_t run_group_items(Plan &pl, const int64_t *goff, hipStream_t st) {
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     return scan<0, false, false>(pl.gitems, pl.gitems, cnt, pl.bsum, st);
-}
-
-__global__ void k_copy_sorted(int64_t n, const uint64_t *k, const int32_t *p, uint64_t *ko,
-                              int32_t *po) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
-    ko[s] = k[s];
-    po[s] = p[s];
-}
-
-hipError_t run_copy_sorted(Plan &pl, uint64_t *keys_out, int32_t *perm_out, hipStream_t st) {
-    hipLaunchKernelGGL(k_copy_sorted, dim3((unsigned)ceil_div(pl.n, 256)), dim3(256), 0, st, pl.n,
-                       pl.skeys, pl.perm, keys_out, perm_out);
-    return hipGetLastError();
 }
 
 hipError_t run_zero_u64(uint64_t *p, int64_t cnt, hipStream_t st) {

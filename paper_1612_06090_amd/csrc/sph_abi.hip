@@ -86,7 +86,6 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
     }
     pl.sh0 = (double *)take(8 * N);
     if (pl.table_n > 0) pl.table = (int32_t *)take(4 * (size_t)pl.table_n);
-    pl.scan_a = (int32_t *)take(4 * N);
     int64_t nbs = pl.nb_scan_n;
     if (pl.nb_scan_t > nbs) nbs = pl.nb_scan_t;
     const int64_t nbg = ceil_div((int64_t)G + 1, kScanTile);
@@ -323,8 +322,7 @@ int sph_sort(const sph_params *params, int64_t n, int32_t n_groups, const int64_
     if (rc != SPH_OK) return rc;
     hipError_t e = run_clean_offsets(pl, group_offsets, st);
     const int64_t *goff = pl.goff;
-    if (e == hipSuccess) e = run_keys_and_sort(pl, goff, x, y, z, st);
-    if (e == hipSuccess) e = run_copy_sorted(pl, keys_out, perm_out, st);
+    if (e == hipSuccess) e = run_keys_and_sort(pl, goff, x, y, z, st, keys_out, perm_out);
     if (e == hipSuccess && (cell_id_out || cell_start_out || cell_count_out || n_cells_out))
         e = run_contract_cells(pl, cell_id_out, cell_start_out, cell_count_out, n_cells_out, st);
     if (e != hipSuccess) return hip_fail(e);

@@ -145,7 +145,6 @@ struct Plan {
     int4 *qp = nullptr;
     float4 *fp = nullptr;
     int32_t *table = nullptr;
-    int32_t *scan_a = nullptr;   // n-sized int32 scratch (cell flags / scan)
     int32_t *bsum = nullptr;     // block sums of scans
     double *frame = nullptr;     // per group: lo xyz, ext xyz, scale, pad (8 doubles)
     int32_t *gitems = nullptr;   // per group: first work item (G+1)
@@ -155,7 +154,8 @@ struct Plan {
     uint32_t *ghist = nullptr;
     int64_t nb_gsort = 0;        // radix blocks of the group-order sort
     int64_t *goff = nullptr;     // groups: the caller's offsets made well formed (G+1)
-    int32_t *ctrl = nullptr;     // [0] work queue head, [8] exact-K tiles left, others reserved
+    int32_t *ctrl = nullptr;     // [0] work queue head, [8] exact-K tiles left, [12] cell count
+                                 // of the sort's cell list, others reserved
     uint64_t *stats = nullptr;   // 4 x uint64 device counters
     double *adj = nullptr;       // adjoint, sorted order: alpha, beta, gamma, grad_rho, grad_h (5 x n)
     float4 *adj_rec = nullptr;   // adjoint, binary32 form: h, 1/h (grid units), alpha, beta (n)
@@ -177,8 +177,11 @@ struct Plan {
 int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out);
 
 // sort.hip
+// keys_out, perm_out: where the sorted keys and permutation end (the last
+// radix pass writes there), else in the workspace
 hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const void *y,
-                             const void *z, hipStream_t st);
+                             const void *z, hipStream_t st, uint64_t *keys_out = nullptr,
+                             int32_t *perm_out = nullptr);
 hipError_t run_permute(Plan &pl, const int64_t *goff, const void *x, const void *y,
                        const void *z, const void *m, const void *h0, bool fp32c,
                        hipStream_t st);
@@ -186,7 +189,6 @@ hipError_t run_contract_cells(Plan &pl, uint64_t *cell_id, int32_t *cell_start,
                               int32_t *cell_count, int32_t *n_cells, hipStream_t st);
 hipError_t run_dense_table(Plan &pl, hipStream_t st);
 hipError_t run_group_items(Plan &pl, const int64_t *goff, hipStream_t st);
-hipError_t run_copy_sorted(Plan &pl, uint64_t *keys_out, int32_t *perm_out, hipStream_t st);
 hipError_t run_zero_u64(uint64_t *p, int64_t cnt, hipStream_t st);
 hipError_t run_zero_i32(int32_t *p, int64_t cnt, hipStream_t st);
 hipError_t run_clean_offsets(const Plan &pl, const int64_t *goff, hipStream_t st);
