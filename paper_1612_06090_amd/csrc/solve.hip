@@ -1234,7 +1234,13 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                     const double rho = KT::sigma * R / (hcur * hcur * hcur);
                     const int32_t stout = hs.flags | (hs.it & 0xFFFF);
                     if (kk == 0) {
-                        write_out(a, a.perm[b + p], rho, hcur, nwv, npair, stout);
+                        // The FP32C exact-K count stage writes no outputs (the
+                        // evaluation stage writes every particle's), which
+                        // brings it to 4 waves per SIMD (5.5 -> 5.2 ms at
+                        // K = 295); the binary64 one measured slower at 4
+                        // waves than at 3 (9.8 against 8.7 ms) and keeps them
+                        if (STAGE != 1 || PREC == SPH_FP64)
+                            write_out(a, a.perm[b + p], rho, hcur, nwv, npair, stout);
                         if (STAGE == 1) {
                             // hs.h differs from hcur only where the count
                             // stage hands its upper bracket to the selection
