@@ -109,7 +109,9 @@ struct HState {
 // [K, K + dK].  Until both ends are bracketed it takes the volume-ratio step
 // h (K' / N)^(1/3) (K' the band centre) within [h/8, 2h] (a count far above
 // the band is a reliable measure of how much to shrink; growing is capped
-// harder, a sphere that reaches a clump can overshoot); once bracketed it
+// harder, a sphere that reaches a clump can overshoot), or, where the count
+// has grown (or fallen) more slowly than h^(3/2) since the previous step on
+// the same side, the step of that local power law; once bracketed it
 // interpolates log N linearly in log h between the ends (the count's local
 // power law, which is steep where the sphere reaches a clump and makes the
 // plain volume step oscillate), kept 5% inside the bracket, and bisects
@@ -126,6 +128,9 @@ __device__ inline bool h_step(HState &s, double nwv, double dndh, int32_t ncount
     if (KNN) {
         const double N = (double)ncount;
         if (N >= a.Nt && N <= a.Nt + a.dN) return true;
+        // the previous end on this side (the count's local power law, below)
+        const double h_pv = N < a.Nt ? s.lo : s.hi;
+        const int32_t n_pv = N < a.Nt ? s.nlo : s.nhi;
         if (N < a.Nt) { s.lo = s.h; s.nlo = ncount; } else { s.hi = s.h; s.nhi = ncount; }
         const bool br = s.lo > 0.0 && s.hi < INFINITY;
         const bool narrow = br && s.hi - s.lo <= 0x1p-10 * s.hi &&
@@ -152,7 +157,18 @@ __device__ inline bool h_step(HState &s, double nwv, double dndh, int32_t ncount
             }
             s.wprev = w;
         } else {
-            hn = s.h * cbrt(Kc / fmax(N, 1.0));
+            // where the count follows the volume less than as h^(3/2) since
+            // the previous step on this side (a sphere inside a dense clump
+            // that must reach past it), the volume step would creep: the
+            // step follows that local power law instead (exponent >= 1/4)
+            // (binary32 is ample for a step that is clamped and checked)
+            float ex = 3.f;
+            if (h_pv > 0.0 && h_pv < INFINITY && n_pv > 0 && h_pv != s.h) {
+                const float lr = __logf((float)(N / (double)n_pv)) / __logf((float)(s.h / h_pv));
+                if (lr < 1.5f) ex = fmaxf(lr, 0.25f);
+            }
+            hn = ex == 3.f ? s.h * cbrt(Kc / fmax(N, 1.0))
+                           : s.h * (double)__expf(__logf((float)(Kc / fmax(N, 1.0))) / ex);
             hn = fmin(fmax(hn, 0.125 * s.h), 2.0 * s.h);
         }
         if (hn >= hmax) {

@@ -28,6 +28,24 @@ KNN = sph.KNN
 FLAGS = ~np.int32(0xFFFF)
 
 
+def _clump_in_background():
+    # a dense cube of 2000 particles (side 0.05) inside 2000 uniform ones:
+    # with K = 2100 a clump particle's K-th neighbour lies in the sparse
+    # background, so the outer shell of its count-stage sphere, sized for a
+    # uniform density, holds fewer particles than its rank and the selection
+    # falls back to the heap pass for nearly every clump particle
+    bg = sphgen.uniform(2000, seed=89)
+    cl = sphgen.uniform(2000, seed=90)
+    x = np.concatenate([bg.x, 0.475 + 0.05 * cl.x])
+    y = np.concatenate([bg.y, 0.475 + 0.05 * cl.y])
+    z = np.concatenate([bg.z, 0.475 + 0.05 * cl.z])
+    n = x.shape[0]
+    return sphgen.ParticleSet(x=x, y=y, z=z, m=np.full(n, 1.0 / n),
+                              h_init=np.full(n, sphgen.default_h_init(n, 1.0)), periodic=True,
+                              box=1.0, n_target=2100.0, n_tol=14.0,
+                              meta={"kind": "clump_in_background"})
+
+
 def _cases():
     def groups_mixed():
         # sizes below K, exactly K and far above it, plus empty groups
@@ -53,6 +71,7 @@ def _cases():
         "lattice4096_K5_dK0": (lambda: sphgen.lattice(16, h=0.1), 5, 0, oracle.M4),
         "lattice4096_K7_dK0": (lambda: sphgen.lattice(16, h=0.1), 7, 0, oracle.M4),
         "lattice4096_K20_dK0": (lambda: sphgen.lattice(16, h=0.1), 20, 0, oracle.M4),
+        "clump_in_background_K2100": (_clump_in_background, 2100, 14, oracle.M4),
     }
 
 
