@@ -120,7 +120,7 @@ def test_knn_fp64(name):
 
 @pytest.mark.parametrize("name", ["uniform8192_K64", "clustered32k_K64", "groups_mixed_K32",
                                   "periodic20_K30", "clustered32k_K295_wc6",
-                                  "lattice4096_K20_dK0"])
+                                  "lattice4096_K20_dK0", "clump_in_background_K2100"])
 def test_knn_fp32c(name):
     ps, K, kern, g, o = _run(name, sph.FP32C)
     ok = _check_flags(g, o)
