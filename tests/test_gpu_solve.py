@@ -193,6 +193,42 @@ def _fp32c_bounds(ps, g, sub=None):
     return e
 
 
+def _clump_in_background(seed):
+    # density contrast 8000: a cube of 2000 particles (side 0.05) in 2000
+    # uniform ones; the clump's spheres are ~20 times smaller than the
+    # background's, and background spheres near the clump take it in
+    bg = sphgen.uniform(2000, seed=seed)
+    cl = sphgen.uniform(2000, seed=seed + 1)
+    x = np.concatenate([bg.x, 0.475 + 0.05 * cl.x])
+    y = np.concatenate([bg.y, 0.475 + 0.05 * cl.y])
+    z = np.concatenate([bg.z, 0.475 + 0.05 * cl.z])
+    n = x.shape[0]
+    return sphgen.ParticleSet(x=x, y=y, z=z, m=np.full(n, 1.0 / n),
+                              h_init=np.full(n, sphgen.default_h_init(n, 1.0)), periodic=True,
+                              box=1.0, n_target=64.0, n_tol=2.0,
+                              meta={"kind": "clump_in_background", "seed": seed})
+
+
+def test_fp64_clump_in_background():
+    ps = _clump_in_background(58)
+    say(f"[solve fp64] clump in background n={ps.n}")
+    g = gpu_solve(ps)
+    _check_fp64_against_oracle(ps, g, max_flip_frac=1e-3)
+    assert np.all((g["status"] >> 16) == 0)
+
+
+def test_fp32c_clump_in_background():
+    ps = _clump_in_background(60)
+    say(f"[solve fp32c] clump in background n={ps.n}")
+    g = gpu_solve(ps, precision=sph.FP32C)
+    assert np.all((g["status"] >> 16) == 0)
+    _fp32c_bounds(ps, g)
+    o = oracle.solve(ps)
+    dh = rel(g["h"], o["h"])
+    say(f"  fp32c solve: frac |dh|/h <= 1e-5: {(dh <= 1e-5).mean():.5f}")
+    assert (dh <= 1e-5).mean() >= 0.999
+
+
 def test_fp32c_uniform4096():
     ps = sphgen.config("uniform4096")
     g = gpu_solve(ps, precision=sph.FP32C)
