@@ -34,8 +34,24 @@ def _straddle():
                               box=1.0, n_target=32.0, n_tol=1.0)
 
 
+def _clump_in_background():
+    # density contrast 8000: a cube of 2000 particles (side 0.05) in 2000
+    # uniform ones; background spheres near the clump reach into it, so the
+    # clump's particles have reverse neighbours with ~20 times their radius
+    bg = sphgen.uniform(2000, seed=62)
+    cl = sphgen.uniform(2000, seed=63)
+    x = np.concatenate([bg.x, 0.475 + 0.05 * cl.x])
+    y = np.concatenate([bg.y, 0.475 + 0.05 * cl.y])
+    z = np.concatenate([bg.z, 0.475 + 0.05 * cl.z])
+    n = x.shape[0]
+    return sphgen.ParticleSet(x=x, y=y, z=z, m=np.full(n, 1.0 / n),
+                              h_init=np.full(n, sphgen.default_h_init(n, 1.0)), periodic=True,
+                              box=1.0, n_target=64.0, n_tol=2.0)
+
+
 CASES = {
     "uniform4096": lambda: sphgen.config("uniform4096"),
+    "clump_in_background": _clump_in_background,
     "clustered32k": lambda: sphgen.plummer_mixture(1 << 15, 20, seed=45),
     "groups200": lambda: sphgen.groups(200, seed=47, lo=32, hi=5000),
     "ragged65": lambda: sphgen.uniform(65, seed=15, n_target=16.0, n_tol=1.0),
