@@ -921,6 +921,8 @@ def measured_sort_traffic():
 TRACE_MD = os.path.join(ROOT, "profiles", "k_solve_clustered2p20_kernel_trace.md")
 TRACE_KNN_MD = os.path.join(ROOT, "profiles", "k_solve_exactK295_clustered2p20_kernel_trace.md")
 TRACE_BATCHED_MD = os.path.join(ROOT, "profiles", "k_solve_groups10k_kernel_trace.md")
+TRACE_LARGE_MD = os.path.join(ROOT, "profiles", "k_solve_clustered2p24_kernel_trace.md")
+TRACE_WC6_MD = os.path.join(ROOT, "profiles", "k_solve_wendland295_clustered2p20_kernel_trace.md")
 
 
 def summarize_trace(stats_csv, cmd, which="headline"):
@@ -928,7 +930,21 @@ def summarize_trace(stats_csv, cmd, which="headline"):
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    if which == "batched":
+    if which == "large":
+        path = TRACE_LARGE_MD
+        head = ["# Density solve on clustered2^24 — rocprofv3 kernel trace", "",
+                "Command (on the GPU host, from the repository root):", "", "    " + cmd, "",
+                "Workload: 2^24 particles, 2000 Plummer spheres (contrast <= 1e5) + 30% "
+                "background, N_t = 64 +- 1, FP32C; one call = keys + radix sort (16-round "
+                "tiles) + permute + dense cell table + density/h solve.", ""]
+    elif which == "wendland":
+        path = TRACE_WC6_MD
+        head = ["# Wendland C6 solve on clustered2^20 — rocprofv3 kernel trace", "",
+                "Command (on the GPU host, from the repository root):", "", "    " + cmd, "",
+                "Workload: the 2^20-particle clustered set, Wendland C6 kernel, band "
+                "N_t = 295 +- 2, h_init = 2 N^-1/3; `k_solve<1, ..., 1, ...>` FP32C, "
+                "`k_solve<0, ..., 1, ...>` FP64.", ""]
+    elif which == "batched":
         path = TRACE_BATCHED_MD
         head = ["# Batched solve on groups10k — rocprofv3 kernel trace", "",
                 "Command (on the GPU host, from the repository root):", "", "    " + cmd, "",
@@ -993,12 +1009,17 @@ def main():
                     help="with --profile-run: FP64 solves instead")
     ap.add_argument("--only-batched", action="store_true",
                     help="only the groups10k leg (for a kernel trace of its replays)")
+    ap.add_argument("--only-large", action="store_true",
+                    help="only the clustered 2^24 leg (for a kernel trace)")
+    ap.add_argument("--only-wendland", action="store_true",
+                    help="only the Wendland C6 N_t = 295 leg (for a kernel trace)")
     ap.add_argument("--profile-sort", action="store_true",
                     help="only sph_sort calls at 2^24 + a calibration copy (for rocprofv3 --pmc)")
     ap.add_argument("--summarize-sort-traffic", nargs="+", metavar="ARG",
                     help="FETCH_CSV WRITE_CSV CMD [CALLS]: write the sph_sort traffic summary")
     ap.add_argument("--summarize-trace", nargs="+", metavar="ARG",
-                    help="STATS_CSV CMD [headline|knn|batched]: write the kernel-trace summary "
+                    help="STATS_CSV CMD [headline|knn|batched|large|wendland]: write the "
+                         "kernel-trace summary "
                          "from rocprofv3 --stats output")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
                     help="write the k_solve traffic summary from two --pmc runs")
@@ -1018,7 +1039,7 @@ def main():
         return
     if args.summarize_trace:
         if len(args.summarize_trace) not in (2, 3):
-            ap.error("--summarize-trace takes STATS_CSV CMD [headline|knn|batched]")
+            ap.error("--summarize-trace takes STATS_CSV CMD [headline|knn|batched|large|wendland]")
         summarize_trace(*args.summarize_trace)
         return
     if args.summarize_traffic:
@@ -1068,6 +1089,13 @@ def main():
     if args.only_batched:
         print(json.dumps({"batched": run_batched(sph, torch, max(3, args.steps), args.warmup,
                                                  ev)}), flush=True)
+        return
+    if args.only_large:
+        print(json.dumps({"large": run_large(sph, torch, 3, ev)}), flush=True)
+        return
+    if args.only_wendland:
+        print(json.dumps({"wendland_c6": run_wendland(sph, torch, d, ps,
+                                                      max(3, args.steps // 2), ev)}), flush=True)
         return
     f32 = run_form(sph, torch, d, ps, sph.FP32C, args.steps, args.warmup, ev)
     print(f"[bench] fp32c { {k: v for k, v in f32.items() if k[0] != '_'} }", file=sys.stderr,
