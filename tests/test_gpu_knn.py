@@ -46,6 +46,23 @@ def _clump_in_background():
                               meta={"kind": "clump_in_background"})
 
 
+def _clump_groups():
+    # the clump-in-background set as one isolated group beside a uniform
+    # group of 3000: the heap selection runs on the group items of the batched
+    # form (its retry list holds group items)
+    a = _clump_in_background()
+    b = sphgen.uniform(3000, seed=91)
+    x = np.concatenate([a.x, 2.0 + b.x])
+    y = np.concatenate([a.y, b.y])
+    z = np.concatenate([a.z, b.z])
+    n = x.shape[0]
+    return sphgen.ParticleSet(x=x, y=y, z=z, m=np.full(n, 1.0 / n),
+                              h_init=np.full(n, 0.1), periodic=False, box=1.0,
+                              n_target=2100.0, n_tol=14.0,
+                              offsets=np.array([0, a.n, n], dtype=np.int64),
+                              meta={"kind": "clump_groups"})
+
+
 def _cases():
     def groups_mixed():
         # sizes below K, exactly K and far above it, plus empty groups
@@ -72,6 +89,7 @@ def _cases():
         "lattice4096_K7_dK0": (lambda: sphgen.lattice(16, h=0.1), 7, 0, oracle.M4),
         "lattice4096_K20_dK0": (lambda: sphgen.lattice(16, h=0.1), 20, 0, oracle.M4),
         "clump_in_background_K2100": (_clump_in_background, 2100, 14, oracle.M4),
+        "clump_groups_K2100": (_clump_groups, 2100, 14, oracle.M4),
     }
 
 
@@ -120,7 +138,8 @@ def test_knn_fp64(name):
 
 @pytest.mark.parametrize("name", ["uniform8192_K64", "clustered32k_K64", "groups_mixed_K32",
                                   "periodic20_K30", "clustered32k_K295_wc6",
-                                  "lattice4096_K20_dK0", "clump_in_background_K2100"])
+                                  "lattice4096_K20_dK0", "clump_in_background_K2100",
+                                  "clump_groups_K2100"])
 def test_knn_fp32c(name):
     ps, K, kern, g, o = _run(name, sph.FP32C)
     ok = _check_flags(g, o)
