@@ -866,7 +866,7 @@ __global__ __launch_bounds__(64) void k_solve(SolveArgs a) {
                                         // the exact-K count stage needs the count only
                                         if (STAGE != 1) {
                                             // scaled pair terms (factors applied to the totals)
-                                            const double q = sqrt(r2) * hinv;
+                                            const double q = sqrt_pos(r2) * hinv;
                                             double fh, gs;
                                             KT::template terms<double>(q, q * q, fh, gs);
                                             sm.d0 += fh;

@@ -283,6 +283,24 @@ __device__ inline float readlane_f(float v, int l) {
 }
 
 // Value of v in lane `src` (a per-lane index), by bpermute.
+// Square root of x > 0 (0 for x = 0) to within about an ulp: Goldschmidt's
+// iteration for g ~ sqrt(x) and h ~ 1/(2 sqrt(x)) started from the hardware
+// reciprocal square root (about binary32 accuracy), then one Newton
+// correction of g.  For the pair terms of the binary64 sums, whose bound is
+// 1e-12 relative; values that must match exactly keep sqrt().  x must be 0 or
+// a normal number (squared distances of distinct particles are).
+__device__ inline double sqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y;
+    double h = 0.5 * y;
+    const double r = __builtin_fma(-h, g, 0.5);
+    g = __builtin_fma(g, r, g);
+    h = __builtin_fma(h, r, h);
+    const double d = __builtin_fma(-g, g, x);
+    g = __builtin_fma(d, h, g);
+    return x > 0.0 ? g : 0.0;
+}
+
 __device__ inline double readlane_bperm_d(double v, int src) {
     int2 a = __builtin_bit_cast(int2, v);
     a.x = __shfl(a.x, src, 64);
