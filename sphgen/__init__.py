@@ -31,6 +31,8 @@ __all__ = [
     "group_sizes",
     "group_volume",
     "groups",
+    "doubled",
+    "with_duplicates",
     "cotangent",
     "config",
 ]
@@ -263,6 +265,37 @@ def groups(n_groups: int, seed: int, lo: int = 32, hi: int = 131072,
         x=x, y=y, z=z, m=np.full(n, 1.0 / n), h_init=h0, periodic=False,
         box=1.0, n_target=float(n_target), n_tol=float(n_tol), offsets=offsets,
         meta={"kind": "groups", "seed": seed, "sizes": sizes},
+    )
+
+
+def doubled(ps: ParticleSet) -> ParticleSet:
+    """Every particle twice at the same position (copies 2i and 2i+1 of
+    particle i), each of half the mass, with the target count and its band
+    doubled.  Groups stay contiguous (offsets doubled)."""
+    rep = lambda a: np.ascontiguousarray(np.repeat(np.asarray(a, dtype=np.float64), 2))
+    return ParticleSet(
+        x=rep(ps.x), y=rep(ps.y), z=rep(ps.z), m=rep(ps.m) * 0.5, h_init=rep(ps.h_init),
+        periodic=ps.periodic, box=ps.box, n_target=2.0 * ps.n_target,
+        n_tol=2.0 * ps.n_tol,
+        offsets=None if ps.offsets is None else np.asarray(ps.offsets, dtype=np.int64) * 2,
+        meta={**ps.meta, "doubled": True},
+    )
+
+
+def with_duplicates(ps: ParticleSet, n_dup: int, seed: int) -> ParticleSet:
+    """A periodic set with ``n_dup`` distinct particles, drawn at random, given
+    a second particle at exactly the same position (appended after the
+    originals); all masses 1/N of the new count."""
+    if ps.offsets is not None:
+        raise ValueError("with_duplicates takes one periodic set")
+    src = np.sort(_rng(seed).choice(ps.n, size=n_dup, replace=False))
+    cat = lambda a: np.ascontiguousarray(np.concatenate([a, a[src]]))
+    n = ps.n + n_dup
+    return ParticleSet(
+        x=cat(ps.x), y=cat(ps.y), z=cat(ps.z), m=np.full(n, 1.0 / n),
+        h_init=cat(ps.h_init), periodic=True, box=ps.box, n_target=ps.n_target,
+        n_tol=ps.n_tol, meta={**ps.meta, "duplicates": n_dup, "dup_seed": seed,
+                              "dup_of": src},
     )
 
 

@@ -57,6 +57,10 @@ CASES = {
     "ragged65": lambda: sphgen.uniform(65, seed=15, n_target=16.0, n_tol=1.0),
     "ragged4133": lambda: sphgen.uniform(4133, seed=58),
     "straddle": _straddle,
+    # coincident pairs: r = 0 between distinct particles, where the pair's
+    # direction is undefined and its term vanishes (f'(0) = 0)
+    "coincident4396": lambda: sphgen.with_duplicates(sphgen.uniform(4096, seed=74), 300,
+                                                     seed=75),
 }
 
 

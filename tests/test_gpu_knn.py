@@ -90,6 +90,10 @@ def _cases():
         "lattice4096_K20_dK0": (lambda: sphgen.lattice(16, h=0.1), 20, 0, oracle.M4),
         "clump_in_background_K2100": (_clump_in_background, 2100, 14, oracle.M4),
         "clump_groups_K2100": (_clump_groups, 2100, 14, oracle.M4),
+        # coincident pairs: distance 0 between distinct particles, and every
+        # distance to a duplicated particle tied
+        "coincident4396_K64": (lambda: sphgen.with_duplicates(sphgen.uniform(4096, seed=97),
+                                                               300, seed=98), 64, 4, oracle.M4),
     }
 
 
@@ -132,14 +136,15 @@ def test_knn_fp64(name):
     good = np.isfinite(o["rho"])
     assert np.array_equal(np.isfinite(g["rho"]), good)
     assert rel(g["rho"][good], o["rho"][good]).max(initial=0.0) < 1e-12
-    # K-1 particles lie strictly inside h (K-th at r = h) unless distances tie
-    assert np.all(g["nngb"][ok] <= K)
+    # K-1 particles lie strictly inside h (K when h*h rounds above the K-th
+    # squared distance), one more where the K-th is one of a coincident pair
+    assert np.all(g["nngb"][ok] <= K + (1 if name.startswith("coincident") else 0))
 
 
 @pytest.mark.parametrize("name", ["uniform8192_K64", "clustered32k_K64", "groups_mixed_K32",
                                   "periodic20_K30", "clustered32k_K295_wc6",
                                   "lattice4096_K20_dK0", "clump_in_background_K2100",
-                                  "clump_groups_K2100"])
+                                  "clump_groups_K2100", "coincident4396_K64"])
 def test_knn_fp32c(name):
     ps, K, kern, g, o = _run(name, sph.FP32C)
     ok = _check_flags(g, o)
@@ -151,6 +156,26 @@ def test_knn_fp32c(name):
     e = oracle.eval_at_h(ps, g["h"], search=1, kernel=kern)
     fin = np.isfinite(e["rho"])
     assert rel(g["rho"][fin], e["rho"][fin]).max(initial=0.0) <= 1e-5
+
+
+@pytest.mark.parametrize("precision", [sph.FP64, sph.FP32C])
+def test_knn_doubled_set(precision):
+    # every particle twice: the 2K-th distance of the doubled set is the K-th
+    # of the original one, counts at it doubled (pinned on the oracle too)
+    ps = sphgen.uniform(4096, seed=99)
+    d = sphgen.doubled(ps)
+    K = 48
+    g = gpu_solve(d, precision=precision, mode=KNN, n_target=float(2 * K), n_tol=8.0)
+    o = oracle.knn(ps, K)
+    assert np.all((g["status"] & FLAGS) == 0)
+    for c in (0, 1):
+        if precision == sph.FP64:
+            assert np.array_equal(g["h"][c::2], o["h"])
+            assert np.array_equal(g["nngb"][c::2], 2 * o["nngb"])
+            assert rel(g["rho"][c::2], o["rho"]).max() < 1e-12
+        else:
+            dh = rel(g["h"][c::2], o["h"])
+            assert (dh <= 1e-5).mean() >= 0.999 and dh.max() <= 1e-4
 
 
 def test_knn_float32_io():

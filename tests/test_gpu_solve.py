@@ -229,6 +229,64 @@ def test_fp32c_clump_in_background():
     assert (dh <= 1e-5).mean() >= 0.999
 
 
+def _coincident(seed):
+    # 300 particles get a second particle at exactly their position: r = 0
+    # between distinct particles, and both members of a pair see the same
+    # neighbours, so their h agree to rounding
+    return sphgen.with_duplicates(sphgen.uniform(4096, seed=seed), 300, seed=seed + 1)
+
+
+def _pairs_agree(ps, g, tol):
+    src, cp = ps.meta["dup_of"], np.arange(ps.n - len(ps.meta["dup_of"]), ps.n)
+    d = rel(g["h"][cp], g["h"][src])
+    say(f"  pairs: max |dh|/h {d.max():.2e}")
+    assert (d > tol).sum() <= 1
+
+
+def test_fp64_coincident_pairs():
+    ps = _coincident(64)
+    say(f"[solve fp64] coincident pairs n={ps.n}")
+    g = gpu_solve(ps)
+    _check_fp64_against_oracle(ps, g, max_flip_frac=1e-3)
+    assert np.all((g["status"] >> 16) == 0)
+    _pairs_agree(ps, g, TOL64)
+
+
+def test_fp32c_coincident_pairs():
+    ps = _coincident(66)
+    say(f"[solve fp32c] coincident pairs n={ps.n}")
+    g = gpu_solve(ps, precision=sph.FP32C)
+    assert np.all((g["status"] >> 16) == 0)
+    _fp32c_bounds(ps, g)
+    o = oracle.solve(ps)
+    dh = rel(g["h"], o["h"])
+    assert (dh <= 1e-5).mean() >= 0.999
+    _pairs_agree(ps, g, 1e-5)
+
+
+@pytest.mark.parametrize("precision", [sph.FP64, sph.FP32C])
+def test_doubled_set(precision):
+    # every particle twice at half the mass, target and band doubled: the
+    # sums at any h are the original ones with each count doubled, so the
+    # solve lands on the original set's h (the oracle obeys the same identity)
+    ps = sphgen.uniform(4096, seed=68)
+    d = sphgen.doubled(ps)
+    say(f"[solve] doubled uniform4096 n={d.n} precision={precision}")
+    g = gpu_solve(d, precision=precision)
+    o = oracle.solve(ps)
+    tol = TOL64 if precision == sph.FP64 else 1e-5
+    for c in (0, 1):
+        dh = rel(g["h"][c::2], o["h"])
+        same = dh <= tol
+        say(f"  copy {c}: frac |dh|/h <= {tol:g}: {same.mean():.5f}")
+        assert same.mean() >= 0.999
+        if precision == sph.FP64:
+            assert np.array_equal(g["nngb"][c::2][same], 2 * o["nngb"][same])
+            assert rel(g["rho"][c::2][same], o["rho"][same]).max() < TOL64
+        else:
+            assert rel(g["rho"][c::2][same], o["rho"][same]).max() <= 2e-5
+
+
 def test_fp32c_uniform4096():
     ps = sphgen.config("uniform4096")
     g = gpu_solve(ps, precision=sph.FP32C)

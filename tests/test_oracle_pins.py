@@ -597,6 +597,34 @@ def test_knn_lattice_shells(K, shell):
     np.testing.assert_allclose(o["h"], shell * 0.1, rtol=1e-13)
 
 
+@pytest.mark.parametrize("kind", ["periodic", "groups"])
+def test_doubled_set_identity(kind):
+    # every particle twice at half the mass: at any h each sum over r < h
+    # takes every term twice, so rho is unchanged and the counts double; with
+    # the target and band doubled the solve lands on the same h, and the
+    # 2K-th distance (ties counted) is the original K-th.  Fails if a pair at
+    # r = 0 between distinct particles is dropped or taken for the self term.
+    if kind == "periodic":
+        ps = sphgen.uniform(2000, seed=95)
+    else:
+        ps = sphgen.groups(6, seed=96, sizes=np.array([40, 3, 300, 0, 77, 15]),
+                           n_target=16.0, n_tol=1.0)
+    d = sphgen.doubled(ps)
+    s, s2 = oracle.solve(ps), oracle.solve(d)
+    K = 12
+    o, o2 = oracle.knn(ps, K), oracle.knn(d, 2 * K)
+    for c in (0, 1):
+        np.testing.assert_allclose(s2["h"][c::2], s["h"], rtol=1e-13)
+        np.testing.assert_allclose(s2["rho"][c::2], s["rho"], rtol=1e-13)
+        np.testing.assert_array_equal(s2["nngb"][c::2], 2 * s["nngb"])
+        np.testing.assert_array_equal(s2["status"][c::2], s["status"])
+        np.testing.assert_array_equal(o2["h"][c::2], o["h"])
+        np.testing.assert_array_equal(o2["nngb"][c::2], 2 * o["nngb"])
+        np.testing.assert_array_equal(o2["status"][c::2], o["status"])
+        fin = np.isfinite(o["rho"])
+        np.testing.assert_allclose(o2["rho"][c::2][fin], o["rho"][fin], rtol=1e-13)
+
+
 def test_knn_flags_and_order():
     # periodic: 20 particles cannot supply 30 neighbours below the cap
     small = sphgen.uniform(20, seed=73)
