@@ -115,7 +115,7 @@ def run_form(sph, torch, d, ps, precision, steps, warmup, ev):
 # three sums) and 40 in the gradient pass (both sides of the pair: f' or f,
 # c_ij, c/r and three products each)
 FLOP_ADJ_PAIR = 60.0
-SORT_BYTES_PER_PARTICLE = 300.0   # keys 36, 8 radix passes 192, histograms 8, permute 64
+SORT_BYTES_PER_PARTICLE = 300.0   # keys 36, 8 radix passes 192, digit histograms (one key read) 8, permute 64
 
 
 def _executed(summary, flop, kms, form="fp32c"):
@@ -923,6 +923,7 @@ TRACE_KNN_MD = os.path.join(ROOT, "profiles", "k_solve_exactK295_clustered2p20_k
 TRACE_BATCHED_MD = os.path.join(ROOT, "profiles", "k_solve_groups10k_kernel_trace.md")
 TRACE_LARGE_MD = os.path.join(ROOT, "profiles", "k_solve_clustered2p24_kernel_trace.md")
 TRACE_WC6_MD = os.path.join(ROOT, "profiles", "k_solve_wendland295_clustered2p20_kernel_trace.md")
+TRACE_SORT_MD = os.path.join(ROOT, "profiles", "sph_sort_clustered2p24_kernel_trace.md")
 
 
 def summarize_trace(stats_csv, cmd, which="headline"):
@@ -930,13 +931,26 @@ def summarize_trace(stats_csv, cmd, which="headline"):
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-    if which == "large":
+    src = ("Solve", solve_source_sha())
+    if which == "sort":
+        path = TRACE_SORT_MD
+        src = ("Sort", sort_source_sha())
+        head = ["# sph_sort on clustered2^24 — rocprofv3 kernel trace", "",
+                "Command (on the GPU host, from the repository root):", "", "    " + cmd, "",
+                "Workload: Morton keys, radix sort, permutation and cell list of the "
+                "2^24-particle clustered set (the large leg's sort), four calls, plus "
+                "one plain copy (the counter calibration of the traffic runs; torch's "
+                "kernels below). One call = a clear of the look-back descriptors, the "
+                "digit histograms of all eight passes, eight single-sweep scatter "
+                "passes (16-round tiles), then the cell list.", ""]
+    elif which == "large":
         path = TRACE_LARGE_MD
         head = ["# Density solve on clustered2^24 — rocprofv3 kernel trace", "",
                 "Command (on the GPU host, from the repository root):", "", "    " + cmd, "",
                 "Workload: 2^24 particles, 2000 Plummer spheres (contrast <= 1e5) + 30% "
-                "background, N_t = 64 +- 1, FP32C; one call = keys + radix sort (16-round "
-                "tiles) + permute + dense cell table + density/h solve.", ""]
+                "background, N_t = 64 +- 1, FP32C; one call = keys + digit histograms + "
+                "single-sweep radix sort (16-round tiles) + permute + dense cell table + "
+                "density/h solve.", ""]
     elif which == "wendland":
         path = TRACE_WC6_MD
         head = ["# Wendland C6 solve on clustered2^20 — rocprofv3 kernel trace", "",
@@ -975,7 +989,7 @@ def summarize_trace(stats_csv, cmd, which="headline"):
                 "background), N_t = 64 +- 2; one call = keys + radix sort + permute + dense "
                 "cell table + density/h solve. `k_solve<1, ...>` is the FP32C solve, "
                 "`k_solve<0, ...>` the FP64 one, both with 16-particle tiles.", ""]
-    out = head + [f"Solve source sha256: `{solve_source_sha()}`", "",
+    out = head + [f"{src[0]} source sha256: `{src[1]}`", "",
                   "| Kernel | Calls | Avg (us) | Share |", "|---|---|---|---|"]
     for r in rows[:14]:
         name = r["Name"].split("(")[0]
@@ -1018,7 +1032,7 @@ def main():
     ap.add_argument("--summarize-sort-traffic", nargs="+", metavar="ARG",
                     help="FETCH_CSV WRITE_CSV CMD [CALLS]: write the sph_sort traffic summary")
     ap.add_argument("--summarize-trace", nargs="+", metavar="ARG",
-                    help="STATS_CSV CMD [headline|knn|batched|large|wendland]: write the "
+                    help="STATS_CSV CMD [headline|knn|batched|large|wendland|sort]: write the "
                          "kernel-trace summary "
                          "from rocprofv3 --stats output")
     ap.add_argument("--summarize-traffic", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "CMD"),
@@ -1039,7 +1053,8 @@ def main():
         return
     if args.summarize_trace:
         if len(args.summarize_trace) not in (2, 3):
-            ap.error("--summarize-trace takes STATS_CSV CMD [headline|knn|batched|large|wendland]")
+            ap.error("--summarize-trace takes STATS_CSV CMD "
+                     "[headline|knn|batched|large|wendland|sort]")
         summarize_trace(*args.summarize_trace)
         return
     if args.summarize_traffic:

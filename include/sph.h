@@ -30,8 +30,10 @@
  *  - Outputs of sph_density_solve / sph_density_backward are in the
  *    caller's original particle order.  sph_sort returns sorted order.
  *  - One workspace must not be used by two calls that may run concurrently.
- *    The library holds no other state; calls on different workspaces are
- *    thread-safe.
+ *    Besides the scratch of sph_density_solve_noalloc, the library holds one
+ *    other piece of state: a per-device count of the sort's bounded waits
+ *    that reached their bound (sph_sort_wait_faults).  Calls on different
+ *    workspaces are thread-safe.
  */
 #ifndef SPH_H
 #define SPH_H
@@ -346,6 +348,18 @@ const char *sph_status_string(int code);
  * (0 if none), and its text. */
 int sph_last_hip_error(void);
 const char *sph_last_hip_error_string(void);
+
+/* Host only; synchronises with the current device.  The particle sort
+ * (inside sph_sort and every call that sorts) scatters each radix pass in
+ * tiles that take the output offsets of their digits from the tiles before
+ * them as those publish their counts (a decoupled look-back over a chained
+ * scan).  A tile waits only on tiles that started before it, so every wait
+ * ends; each wait is still bounded, and one that reaches its bound lets the
+ * tile go on with a wrong offset (that sort's outputs are then wrong).
+ * *count receives how many waits reached the bound on the current device
+ * since the last call (0 is the only expected value), and the count is
+ * cleared.  Returns SPH_OK, SPH_E_INVALID (count NULL) or SPH_E_HIP. */
+int sph_sort_wait_faults(uint32_t *count);
 
 #ifdef __cplusplus
 }

@@ -45,6 +45,7 @@ EXPORTS = [
     "sph_last_hip_error",
     "sph_last_hip_error_string",
     "sph_density_solve_noalloc",
+    "sph_sort_wait_faults",
 ]
 
 
@@ -124,12 +125,24 @@ def load():
     L.sph_last_hip_error.restype = C.c_int
     L.sph_last_hip_error_string.argtypes = []
     L.sph_last_hip_error_string.restype = C.c_char_p
+    L.sph_sort_wait_faults.argtypes = [C.POINTER(C.c_uint32)]
+    L.sph_sort_wait_faults.restype = C.c_int
     _lib = L
     return L
 
 
 def status_string(code: int) -> str:
     return load().sph_status_string(int(code)).decode()
+
+
+def sort_wait_faults() -> int:
+    """Look-back waits of the particle sort that reached their bound on the
+    current device since the last call (synchronises; clears the count)."""
+    v = C.c_uint32(0)
+    rc = load().sph_sort_wait_faults(C.byref(v))
+    if rc != OK:
+        raise SPHError(rc, "sph_sort_wait_faults")
+    return int(v.value)
 
 
 def default_params(**kw) -> Params:

@@ -8,12 +8,16 @@
 // follows the SoA redesign of Sec. IV-B (only the fields the density loop
 // reads: positions, mass, smoothing length).
 //
-// Radix sort: least-significant-digit first, 8-bit digits, reduce-then-scan
-// (per-tile digit histograms, a scan of the histograms in digit-major order,
-// then a stable scatter).  Inside a tile each wave ranks 64 consecutive keys
-// per round with 8 ballots (lanes sharing a digit), keeping one running count
-// per digit in LDS, so equal digits keep their input order and every pass is
-// stable.
+// Radix sort: least-significant-digit first, 8-bit digits, stable scatter
+// passes.  Inside a tile each wave ranks 64 consecutive keys per round with 8
+// ballots (lanes sharing a digit), keeping one running count per digit in
+// LDS, so equal digits keep their input order and every pass is stable.  The
+// particle keys of sets above 2^21 take a single sweep per pass: one
+// histogram pass counts the digits of all passes at once, and a tile finds
+// the output offset of each digit from the counts that the tiles before it
+// publish (decoupled look-back).  Smaller sets and the group-order sort keep
+// reduce-then-scan (per-tile histograms, a digit-major scan of them, then
+// the scatter).
 #include "sph_internal.h"
 
 #include <limits.h>
@@ -275,6 +279,254 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_down(int64_t n, const ui
     }
 }
 
+// ------------------------------------------------- single-sweep passes
+//
+// Tiles take their index from a counter in the order their blocks start, so
+// a tile waits only on tiles that started before it.  Each tile first
+// publishes its own count per digit (flag A), then looks back over the
+// tiles before it, adding their counts, until it meets an inclusive prefix
+// (flag P), and publishes its own inclusive prefix.  Since every tile
+// publishes its counts before it waits and the tiles it waits on have
+// started, every wait ends; each one is still bounded (kLookbackSpin loads
+// of descriptors not yet published), and a wait that reaches the bound is
+// counted in sort_wait_faults, which the host reads back.
+//
+// Descriptors: 256 per tile (tile-major), 64 bits: flag in the high half,
+// count in the low half.  Within one sort the flags of pass p are 2p + 1 (A)
+// and 2p + 2 (P), so what earlier passes left reads as not yet published;
+// the descriptors are cleared once per sort.
+
+constexpr uint32_t kLookbackSpin = 1u << 22;
+constexpr int kLookbackWin = 2;
+constexpr int kDigitHistBlocks = 1024;
+
+__device__ uint32_t sort_wait_faults;
+
+// Digit counts of all `passes` passes in one read of the keys:
+// gh[p * 256 + d] += number of keys whose digit p is d.
+__global__ __launch_bounds__(kSortThreads) void k_digit_hist(int64_t n, const uint64_t *keys,
+                                                            int passes, uint32_t *gh) {
+    __shared__ uint32_t h[8][256];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < 8 * 256; k += kSortThreads) (&h[0][0])[k] = 0u;
+    __syncthreads();
+    const int64_t step = (int64_t)gridDim.x * kSortThreads;
+    for (int64_t i = (int64_t)blockIdx.x * kSortThreads + tid; i < n; i += step) {
+        const uint64_t k = keys[i];
+        for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(uint32_t)(k >> (8 * p)) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int k = tid; k < passes * 256; k += kSortThreads) {
+        const uint32_t v = (&h[0][0])[k];
+        if (v) atomicAdd(&gh[k], v);
+    }
+}
+
+// Exclusive scan of 256 per-thread values across a 256-thread block, with
+// its four wave totals in caller-provided LDS.
+__device__ inline uint32_t block_excl_scan_256_at(uint32_t v, uint32_t *wt) {
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    uint32_t inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(inc, o, 64);
+        if (l >= o) inc += t;
+    }
+    if (l == 63) wt[w] = inc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int k = 0; k < w; ++k) off += wt[k];
+    __syncthreads();
+    return off + inc - v;
+}
+
+// One scatter pass: the ranking and the LDS-staged write of k_radix_down,
+// with the tile's output offsets from the global digit counts gh (scanned
+// here) and the look-back over the descriptors.  LDS is held to 52 KiB (the
+// wave counts, the staged keys and values; the scan's wave totals and the
+// tile index live in the value buffer before it is filled) so that three
+// blocks fit on a CU, whose tiles hide each other's look-back.
+template <int ROUNDS>
+__global__ __launch_bounds__(kSortThreads) void k_radix_sweep(int64_t n, const uint64_t *kin,
+                                                             const int32_t *vin, uint64_t *kout,
+                                                             int32_t *vout, int pass,
+                                                             const uint32_t *gh,
+                                                             uint64_t *desc, int32_t *tile_ctr) {
+    constexpr int TILE = 256 * ROUNDS;
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint64_t skey[TILE];
+    __shared__ int32_t sval[TILE];
+    uint32_t *wt = reinterpret_cast<uint32_t *>(sval);   // until the values are staged
+    int32_t *s_tile = sval + 4;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int shift = 8 * pass;
+    for (int k = tid; k < 4 * 256; k += kSortThreads) (&wcnt[0][0])[k] = 0u;
+    if (tid == 0) *s_tile = atomicAdd(tile_ctr + pass, 1);
+    const uint32_t gpre = block_excl_scan_256_at(gh[pass * 256 + tid], wt);
+    const int64_t tile = *s_tile;
+    const int64_t blk0 = tile * TILE;
+    const int64_t base = blk0 + (int64_t)w * 64 * ROUNDS;
+    uint64_t key[ROUNDS];
+    int32_t val[ROUNDS];
+    uint32_t rank[ROUNDS];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = base + r * 64 + l;
+        const bool valid = idx < n;
+        key[r] = valid ? kin[idx] : ~0ull;
+        val[r] = valid ? vin[idx] : 0;
+    }
+    volatile uint32_t *wc = wcnt[w];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = base + r * 64 + l;
+        const bool valid = idx < n;
+        const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+        uint64_t m = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1u;
+            const uint64_t bal = __ballot(bit);
+            m &= bit ? bal : ~bal;
+        }
+        const uint32_t before = mbcnt(m);
+        const uint32_t cnt0 = wc[d];
+        rank[r] = cnt0 + before;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && before == 0) wc[d] = cnt0 + (uint32_t)__popcll(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // thread tid owns digit tid: its count s over the tile, published at
+    // once; the waves' counts become LDS slots (digit runs in digit order)
+    uint32_t s = 0;
+    uint32_t wv[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        wv[k] = s;
+        s += wcnt[k][tid];
+    }
+    const uint64_t flag_a = (uint64_t)(2 * pass + 1) << 32;
+    const uint64_t flag_p = (uint64_t)(2 * pass + 2) << 32;
+    uint64_t *mine = desc + tile * 256 + tid;
+    __hip_atomic_store(mine, (tile == 0 ? flag_p : flag_a) | s, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t lb = block_excl_scan_256_at(s, wt);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wcnt[k][tid] = lb + wv[k];
+    __syncthreads();
+    const int cnt = n - blk0 < TILE ? (int)(n - blk0) : TILE;
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int64_t idx = base + r * 64 + l;
+        if (idx < n) {
+            const uint32_t d = (uint32_t)(key[r] >> shift) & 255u;
+            const uint32_t j = wcnt[w][d] + rank[r];
+            skey[j] = key[r];
+            sval[j] = val[r];
+        }
+    }
+    __syncthreads();
+    // look back kLookbackWin tiles at a time: add the counts (A) in order up
+    // to the first inclusive prefix (P); at a tile not yet published, load
+    // again from there
+    uint32_t excl = 0;
+    if (tile > 0) {
+        int64_t k = tile - 1;
+        uint32_t spins = 0;
+        for (;;) {
+            uint64_t v[kLookbackWin];
+#pragma unroll
+            for (int u = 0; u < kLookbackWin; ++u)
+                v[u] = k - u >= 0 ? __hip_atomic_load(desc + (k - u) * 256 + tid, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                                  : 0ull;
+            int used = kLookbackWin;
+            bool done = false;
+#pragma unroll
+            for (int u = 0; u < kLookbackWin; ++u) {
+                if (used != kLookbackWin || done) continue;
+                const uint32_t f = (uint32_t)(v[u] >> 32);
+                if (k - u < 0 || f < (uint32_t)(2 * pass + 1)) {
+                    used = u;
+                    continue;
+                }
+                excl += (uint32_t)v[u];
+                done = f == (uint32_t)(2 * pass + 2);
+            }
+            if (done) break;
+            k -= used;
+            if (used == 0) {
+                if (++spins >= kLookbackSpin) {
+                    atomicAdd(&sort_wait_faults, 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __hip_atomic_store(mine, flag_p | (uint64_t)(excl + s), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // output slot of LDS slot j of digit d: gpre + excl + (j - lb), kept in
+    // the first row of the wave counts, which the staging no longer needs
+    uint32_t *dbase = wcnt[0];
+    dbase[tid] = gpre + excl - lb;
+    __syncthreads();
+    // the bound on pos matters only after a wait reached its bound: offsets
+    // are then wrong, and no store may leave the arrays
+    for (int j = tid; j < cnt; j += kSortThreads) {
+        const uint64_t k = skey[j];
+        const uint32_t d = (uint32_t)(k >> shift) & 255u;
+        const uint32_t pos = dbase[d] + (uint32_t)j;
+        if ((int64_t)pos < n) {
+            kout[pos] = k;
+            vout[pos] = sval[j];
+        }
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t cnt);
+
+// All `passes` passes over the particle keys in (keysA, valsA); the result
+// ends in the A buffers after an even number of passes, or in (kfin, vfin)
+// when given.
+template <int ROUNDS>
+static hipError_t sweep_passes(Plan &pl, int passes, hipStream_t st, uint64_t *kfin,
+                               int32_t *vfin) {
+    if (passes < 1 || passes > 8) return hipErrorInvalidValue;
+    const int64_t n = pl.n, nb = pl.nb_sort;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(pl.sweep_words, 256)), dim3(256), 0,
+                       st, pl.sweep, 0, pl.sweep_words);
+    const int64_t hb = nb < kDigitHistBlocks ? nb : kDigitHistBlocks;
+    hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)hb), dim3(kSortThreads), 0, st, n, pl.keysA,
+                       passes, pl.sweep_gh);
+    uint64_t *ka = pl.keysA, *kb = pl.keysB;
+    int32_t *va = pl.valsA, *vb = pl.valsB;
+    for (int p = 0; p < passes; ++p) {
+        if (p == passes - 1 && kfin) { kb = kfin; vb = vfin; }
+        hipLaunchKernelGGL(k_radix_sweep<ROUNDS>, dim3((unsigned)nb), dim3(kSortThreads), 0, st,
+                           n, ka, va, kb, vb, p, pl.sweep_gh, pl.sweep_desc, pl.sweep_ctr);
+        uint64_t *tk = ka; ka = kb; kb = tk;
+        int32_t *tv = va; va = vb; vb = tv;
+    }
+    pl.skeys = ka;
+    pl.perm = va;
+    return hipGetLastError();
+}
+
+hipError_t read_sort_wait_faults(uint32_t *count) {
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyFromSymbol(&v, HIP_SYMBOL(sort_wait_faults), sizeof(v), 0,
+                                       hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    const uint32_t zero = 0;
+    e = hipMemcpyToSymbol(HIP_SYMBOL(sort_wait_faults), &zero, sizeof(zero), 0,
+                          hipMemcpyHostToDevice);
+    if (e != hipSuccess) return e;
+    *count = v;
+    return hipSuccess;
+}
+
 // LSD radix sort of (key, value) pairs over `passes` 8-bit digits; the result
 // ends in the A buffers after an even number of passes, or in (kfin, vfin)
 // when given (the last pass writes there).
@@ -300,13 +552,17 @@ static hipError_t radix_passes(int64_t n, int64_t nb, int passes, uint64_t *ka, 
     return hipGetLastError();
 }
 
+// Sets above 2^21 keys take the single sweep.  Smaller ones (1024-key
+// tiles) keep reduce-then-scan: all their tiles are resident at once, so a
+// look-back would cross most of them in every pass (measured at 2^20: 0.38
+// ms per sort against 0.26); their per-tile histograms use the start of the
+// sweep run, which holds twice as many words.
 static hipError_t radix_sort(Plan &pl, int passes, hipStream_t st, uint64_t *kfin,
                              int32_t *vfin) {
-    if (pl.sort_rounds == 16)
-        return radix_passes<16>(pl.n, pl.nb_sort, passes, pl.keysA, pl.keysB, pl.valsA, pl.valsB,
-                                pl.hist, pl.digit_tot, st, &pl.skeys, &pl.perm, kfin, vfin);
+    if (pl.sort_rounds == 16) return sweep_passes<16>(pl, passes, st, kfin, vfin);
     return radix_passes<4>(pl.n, pl.nb_sort, passes, pl.keysA, pl.keysB, pl.valsA, pl.valsB,
-                           pl.hist, pl.digit_tot, st, &pl.skeys, &pl.perm, kfin, vfin);
+                           reinterpret_cast<uint32_t *>(pl.sweep), pl.digit_tot, st, &pl.skeys,
+                           &pl.perm, kfin, vfin);
 }
 
 hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const void *y,

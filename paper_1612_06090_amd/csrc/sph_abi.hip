@@ -76,7 +76,13 @@ int make_plan(const sph_params *p, int64_t n, int32_t G, void *ws, Plan *out) {
     pl.keysB = (uint64_t *)take(8 * N);
     pl.valsA = (int32_t *)take(4 * N);
     pl.valsB = (int32_t *)take(4 * N);
-    pl.hist = (uint32_t *)take(4 * 256 * (size_t)pl.nb_sort);
+    pl.sweep_words = 2 * 256 * pl.nb_sort + 8 * 256 + 16;
+    pl.sweep = (int32_t *)take(4 * (size_t)pl.sweep_words);
+    if (pl.sweep) {
+        pl.sweep_desc = reinterpret_cast<uint64_t *>(pl.sweep);
+        pl.sweep_gh = reinterpret_cast<uint32_t *>(pl.sweep + 2 * 256 * pl.nb_sort);
+        pl.sweep_ctr = pl.sweep + 2 * 256 * pl.nb_sort + 8 * 256;
+    }
     pl.digit_tot = (uint32_t *)take(4 * 256);
     if (!f32c) {
         pl.sp = (double4 *)take(32 * N);
@@ -515,6 +521,13 @@ const char *sph_status_string(int code) {
 }
 
 int sph_last_hip_error(void) { return g_last_hip; }
+
+int sph_sort_wait_faults(uint32_t *count) {
+    if (!count) return SPH_E_INVALID;
+    const hipError_t e = read_sort_wait_faults(count);
+    if (e != hipSuccess) return hip_fail(e);
+    return SPH_OK;
+}
 
 const char *sph_last_hip_error_string(void) {
     return hipGetErrorString((hipError_t)g_last_hip);

@@ -136,7 +136,16 @@ struct Plan {
 
     uint64_t *keysA = nullptr, *keysB = nullptr;
     int32_t *valsA = nullptr, *valsB = nullptr;
-    uint32_t *hist = nullptr, *digit_tot = nullptr;
+    uint32_t *digit_tot = nullptr;  // digit totals of the group-order sort
+    // single-sweep particle sort, one run cleared by one fill per sort:
+    // look-back descriptors (256 per radix block), the digit counts of the
+    // eight passes and the passes' tile counters (reduce-then-scan sorts of
+    // small sets keep their per-tile histograms at its start)
+    int32_t *sweep = nullptr;
+    int64_t sweep_words = 0;     // int32 words of that run
+    uint64_t *sweep_desc = nullptr;
+    uint32_t *sweep_gh = nullptr;
+    int32_t *sweep_ctr = nullptr;
     // sorted structure-of-arrays
     double4 *sp = nullptr;       // FP64: x, y, z, m per particle (one 32-byte record)
     double *sh0 = nullptr;
@@ -191,6 +200,9 @@ hipError_t run_dense_table(Plan &pl, hipStream_t st);
 hipError_t run_group_items(Plan &pl, const int64_t *goff, hipStream_t st);
 hipError_t run_zero_u64(uint64_t *p, int64_t cnt, hipStream_t st);
 hipError_t run_zero_i32(int32_t *p, int64_t cnt, hipStream_t st);
+// Reads and clears the device's count of sort look-back waits that reached
+// their bound (synchronous).
+hipError_t read_sort_wait_faults(uint32_t *count);
 hipError_t run_clean_offsets(const Plan &pl, const int64_t *goff, hipStream_t st);
 
 // solve.hip

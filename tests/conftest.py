@@ -27,3 +27,17 @@ def pytest_collection_modifyitems(config, items):
     for it in items:
         if "gpu" in it.keywords:
             it.add_marker(skip)
+
+
+@pytest.fixture(autouse=True)
+def _sort_waits_within_bound(request):
+    # every GPU test ends by checking that no look-back wait of the particle
+    # sort reached its bound (the count is per device and cleared on read)
+    yield
+    if "gpu" not in request.keywords:
+        return
+    import torch
+    if not torch.cuda.is_available():
+        return
+    import paper_1612_06090_amd as sph
+    assert sph.sort_wait_faults() == 0
