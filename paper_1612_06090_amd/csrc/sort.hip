@@ -39,6 +39,56 @@ __global__ void k_keys_periodic(int64_t n, const void *x, const void *y, const v
     vals[i] = (int32_t)i;
 }
 
+// The periodic keys of the single-sweep sort, with the digit counts of its
+// eight passes taken while the keys are in registers: gh[p * 256 + d] +=
+// number of keys whose digit p is d.  Grid-stride over batches of four
+// keys per thread, their coordinates loaded together.
+template <typename T>
+__global__ __launch_bounds__(kSortThreads) void k_keys_periodic_hist(int64_t n, const void *x,
+                                                                    const void *y,
+                                                                    const void *z, int64_t ins,
+                                                                    double box, uint64_t *keys,
+                                                                    int32_t *vals,
+                                                                    uint32_t *gh) {
+    __shared__ uint32_t h[8][256];
+    const int tid = threadIdx.x;
+    for (int k = tid; k < 8 * 256; k += kSortThreads) (&h[0][0])[k] = 0u;
+    __syncthreads();
+    const double s = 2097152.0 / box;
+    const int64_t step = (int64_t)gridDim.x * kSortThreads * 4;
+    for (int64_t i0 = (int64_t)blockIdx.x * kSortThreads * 4 + tid; i0 < n; i0 += step) {
+        double px[4], py[4], pz[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + (int64_t)u * kSortThreads;
+            if (i < n) {
+                px[u] = ld<T>(x, i, ins);
+                py[u] = ld<T>(y, i, ins);
+                pz[u] = ld<T>(z, i, ins);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = i0 + (int64_t)u * kSortThreads;
+            if (i < n) {
+                const uint64_t k = morton3(quantise(px[u] * s, 1u << 21),
+                                           quantise(py[u] * s, 1u << 21),
+                                           quantise(pz[u] * s, 1u << 21));
+                keys[i] = k;
+                vals[i] = (int32_t)i;
+#pragma unroll
+                for (int p = 0; p < 8; ++p)
+                    atomicAdd(&h[p][(uint32_t)(k >> (8 * p)) & 255u], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = tid; k < 8 * 256; k += kSortThreads) {
+        const uint32_t v = (&h[0][0])[k];
+        if (v) atomicAdd(&gh[k], v);
+    }
+}
+
 // One block per group: bounding box of the group's finite coordinates.
 // frame[8g + 0..2] = lower corner, [3..5] = extents, [6] = 2^16 / largest
 // extent (largest extent 1 when it is 0), [7] = largest extent.
@@ -490,16 +540,20 @@ __global__ void k_fill_i32(int32_t *p, int32_t v, int64_t cnt);
 // All `passes` passes over the particle keys in (keysA, valsA); the result
 // ends in the A buffers after an even number of passes, or in (kfin, vfin)
 // when given.
+// With `counted` the sweep run was cleared and the digit counts taken
+// before the keys were written (k_keys_periodic_hist).
 template <int ROUNDS>
 static hipError_t sweep_passes(Plan &pl, int passes, hipStream_t st, uint64_t *kfin,
-                               int32_t *vfin) {
+                               int32_t *vfin, bool counted) {
     if (passes < 1 || passes > 8) return hipErrorInvalidValue;
     const int64_t n = pl.n, nb = pl.nb_sort;
-    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(pl.sweep_words, 256)), dim3(256), 0,
-                       st, pl.sweep, 0, pl.sweep_words);
-    const int64_t hb = nb < kDigitHistBlocks ? nb : kDigitHistBlocks;
-    hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)hb), dim3(kSortThreads), 0, st, n, pl.keysA,
-                       passes, pl.sweep_gh);
+    if (!counted) {
+        hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(pl.sweep_words, 256)), dim3(256),
+                           0, st, pl.sweep, 0, pl.sweep_words);
+        const int64_t hb = nb < kDigitHistBlocks ? nb : kDigitHistBlocks;
+        hipLaunchKernelGGL(k_digit_hist, dim3((unsigned)hb), dim3(kSortThreads), 0, st, n,
+                           pl.keysA, passes, pl.sweep_gh);
+    }
     uint64_t *ka = pl.keysA, *kb = pl.keysB;
     int32_t *va = pl.valsA, *vb = pl.valsB;
     for (int p = 0; p < passes; ++p) {
@@ -558,8 +612,8 @@ static hipError_t radix_passes(int64_t n, int64_t nb, int passes, uint64_t *ka, 
 // ms per sort against 0.26); their per-tile histograms use the start of the
 // sweep run, which holds twice as many words.
 static hipError_t radix_sort(Plan &pl, int passes, hipStream_t st, uint64_t *kfin,
-                             int32_t *vfin) {
-    if (pl.sort_rounds == 16) return sweep_passes<16>(pl, passes, st, kfin, vfin);
+                             int32_t *vfin, bool counted) {
+    if (pl.sort_rounds == 16) return sweep_passes<16>(pl, passes, st, kfin, vfin, counted);
     return radix_passes<4>(pl.n, pl.nb_sort, passes, pl.keysA, pl.keysB, pl.valsA, pl.valsB,
                            reinterpret_cast<uint32_t *>(pl.sweep), pl.digit_tot, st, &pl.skeys,
                            &pl.perm, kfin, vfin);
@@ -571,7 +625,22 @@ hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const
     const int64_t n = pl.n;
     const unsigned nbk = (unsigned)ceil_div(n, 256);
     const bool f32 = pl.prm.io_dtype == SPH_F32;
-    if (!pl.grouped) {
+    // periodic sets of the single sweep: clear its run, then keys and digit
+    // counts in one kernel
+    const bool counted = !pl.grouped && pl.sort_rounds == 16;
+    if (counted) {
+        hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)ceil_div(pl.sweep_words, 256)), dim3(256),
+                           0, st, pl.sweep, 0, pl.sweep_words);
+        const int64_t hb = pl.nb_sort < kDigitHistBlocks ? pl.nb_sort : kDigitHistBlocks;
+        if (f32)
+            hipLaunchKernelGGL(k_keys_periodic_hist<float>, dim3((unsigned)hb),
+                               dim3(kSortThreads), 0, st, n, x, y, z, pl.in_stride, pl.prm.box,
+                               pl.keysA, pl.valsA, pl.sweep_gh);
+        else
+            hipLaunchKernelGGL(k_keys_periodic_hist<double>, dim3((unsigned)hb),
+                               dim3(kSortThreads), 0, st, n, x, y, z, pl.in_stride, pl.prm.box,
+                               pl.keysA, pl.valsA, pl.sweep_gh);
+    } else if (!pl.grouped) {
         if (f32)
             hipLaunchKernelGGL(k_keys_periodic<float>, dim3(nbk), dim3(256), 0, st, n, x, y, z,
                                pl.in_stride, pl.prm.box, pl.keysA, pl.valsA);
@@ -593,7 +662,7 @@ hipError_t run_keys_and_sort(Plan &pl, const int64_t *goff, const void *x, const
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return radix_sort(pl, 8, st, keys_out, perm_out);
+    return radix_sort(pl, 8, st, keys_out, perm_out, counted);
 }
 
 // ------------------------------------------------------- sorted SoA gather

@@ -6,7 +6,10 @@ with 16 (a 4096-key block tile): the cases above 2^21 (the threshold plus
 one, many duplicated keys, the clustered 2^24 set and both group-size
 readings of the 10,000-group workload) cover that second instantiation,
 where a stability error among equal keys would leave h and rho untouched
-and only the permutation would show it."""
+and only the permutation would show it.  Above 2^21 the scatter passes take
+their offsets by a look-back over the tiles before them; periodic sets count
+the digits of every pass in the key kernel (binary64 and binary32
+coordinates), grouped ones in a histogram pass of their own."""
 import numpy as np
 import pytest
 
@@ -19,8 +22,8 @@ pytestmark = pytest.mark.gpu
 
 def _cases():
     return ["uniform4096", "uniform_ragged", "clustered", "duplicates", "f32io", "groups",
-            "one", "clustered2^20", "threshold+1", "duplicates2^22", "clustered2^24",
-            "groups10k", "groups10k_a1554"]
+            "one", "clustered2^20", "threshold+1", "threshold+1_f32io", "duplicates2^22",
+            "clustered2^24", "groups10k", "groups10k_a1554"]
 
 
 def _make(case):
@@ -51,6 +54,13 @@ def _make(case):
     if case == "threshold+1":
         # one key past the 4-round limit: the last 4096-key tile holds one key
         return sphgen.uniform((1 << 21) + 1, seed=38), "float64"
+    if case == "threshold+1_f32io":
+        # binary32 coordinates in the periodic key kernel of the large sets,
+        # which also counts the digits of every radix pass
+        ps = sphgen.uniform((1 << 21) + 1, seed=40)
+        for k in ("x", "y", "z"):
+            setattr(ps, k, getattr(ps, k).astype(np.float32).astype(np.float64))
+        return ps, "float32"
     if case == "duplicates2^22":
         # 4.2e6 particles on 3000 distinct positions (and a ragged last tile):
         # every key is shared by ~1400 particles spread over many blocks
