@@ -1,8 +1,10 @@
 """HIP-graph capture of the multi-launch entry points: exact K (count stage,
-selection, evaluation), the scatter form, the pressure force and the adjoint
-are captured once and replayed between eager calls of the program's own;
-every replay must equal an eager call bit for bit, also after the inputs are
-changed in place."""
+selection, evaluation), the scatter form, the pressure force, the adjoint,
+and the solve of sets above 2^21 particles (whose sort clears its look-back
+descriptors and tile counters with a fill kernel in every call) are captured
+once and replayed between eager calls of the program's own; every replay
+must equal an eager call bit for bit, also after the inputs are changed in
+place."""
 import numpy as np
 import pytest
 
@@ -77,3 +79,18 @@ def test_graph_scatter_force_adjoint():
     _check_graph(lambda: sph.density_backward(d["x"], d["y"], d["z"], d["m"], h, gr, None, p,
                                               ws=ws),
                  lambda: gr.mul_(-1.0))
+
+
+@pytest.mark.parametrize("grouped", [False, True])
+def test_graph_solve_above_2p21(grouped):
+    # periodic: keys with digit counts in one kernel; groups: a histogram
+    # pass of its own; both then the single-sweep scatter passes
+    ps = (sphgen.config("groups10k") if grouped
+          else sphgen.uniform((1 << 21) + 4096, seed=34, n_target=32.0, n_tol=1.0))
+    p = params_for(ps, precision=sph.FP32C)
+    d = dev_arrays(ps)
+    G = 0 if ps.offsets is None else len(ps.offsets) - 1
+    ws = sph.workspace(p, ps.n, G, d["x"].device)
+    _check_graph(lambda: sph.density_solve(d["x"], d["y"], d["z"], d["m"], d["h_init"], p,
+                                           d["goff"], ws=ws),
+                 lambda: d["x"].mul_(0.5))
