@@ -966,13 +966,18 @@ __global__ __launch_bounds__(kScanThreads) void k_cell_emit(int64_t n, const uin
     }
 }
 
+// Grid-stride over the cells, whose number is known only on the device: a
+// grid sized for n would mostly launch blocks with nothing to do.
+constexpr int kCellCountBlocks = 2048;
+
 __global__ void k_cell_counts(int64_t n, const int32_t *nc_p, const int32_t *tmp,
                               int32_t *cell_count) {
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const int32_t nc = *nc_p;
-    if (c >= nc) return;
-    const int32_t e = c + 1 < nc ? tmp[c + 1] : (int32_t)n;
-    cell_count[c] = e - tmp[c];
+    const int64_t step = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < nc; c += step) {
+        const int32_t e = c + 1 < nc ? tmp[c + 1] : (int32_t)n;
+        cell_count[c] = e - tmp[c];
+    }
 }
 
 hipError_t run_contract_cells(Plan &pl, uint64_t *cell_id, int32_t *cell_start,
@@ -991,7 +996,9 @@ hipError_t run_contract_cells(Plan &pl, uint64_t *cell_id, int32_t *cell_start,
     hipLaunchKernelGGL(k_cell_emit, dim3((unsigned)nb), dim3(kScanThreads), 0, st, n, pl.skeys,
                        shift, pl.bsum, cell_id, cell_start, tmp, nc, n_cells);
     if (cell_count)
-        hipLaunchKernelGGL(k_cell_counts, dim3(nbk), dim3(256), 0, st, n, nc, tmp, cell_count);
+        hipLaunchKernelGGL(k_cell_counts,
+                           dim3(nbk < (unsigned)kCellCountBlocks ? nbk : (unsigned)kCellCountBlocks),
+                           dim3(256), 0, st, n, nc, tmp, cell_count);
     return hipGetLastError();
 }
 
