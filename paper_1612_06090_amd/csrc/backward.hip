@@ -856,17 +856,49 @@ __global__ void k_adj_gather(int64_t n, const int32_t *perm, const void *gr, con
     ghs[s] = gh ? ld<T>(gh, i, ins) : 0.0;
 }
 
-// level 0 of the range-max table: h in grid units, rounded up to binary32
-__global__ void k_rmq_base(int64_t n, const double *sh, const uint64_t *skeys, bool grouped,
-                           double box, const double *frame, float *t) {
-    const int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (s >= n) return;
+// level 0 of the range-max table at slot s: h in grid units, rounded up to
+// binary32
+__device__ inline float rmq_h0(int64_t s, const double *sh, const uint64_t *skeys, bool grouped,
+                               double box, const double *frame) {
     const double sc = grouped ? frame[8 * (int64_t)(uint32_t)(skeys[s] >> 48) + 6] : 2097152.0 / box;
     const double hq = sh[s] * sc;
     float f = (float)hq;
     if (!(hq > 0.0) || !isfinite(hq)) f = 0.f;
     else if ((double)f < hq) f = nextafterf(f, INFINITY);
-    t[s] = f;
+    return f;
+}
+
+// Levels 0 .. kRmqLow in one pass.  Level k at slot s is the largest level-0
+// value over [s, min(s + 2^k - 1, n - 1)], so a block that stages level 0 of
+// 512 slots (past n: slot n - 1 again) derives levels 1 .. 8 of its first
+// 256 slots in LDS.
+constexpr int kRmqLow = 8;
+
+__global__ __launch_bounds__(256) void k_rmq_low(int64_t n, int levels, const double *sh,
+                                                 const uint64_t *skeys, bool grouped, double box,
+                                                 const double *frame, float *t) {
+    __shared__ float w[512];
+    const int tid = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * 256;
+    for (int j = tid; j < 512; j += 256) {
+        const int64_t s = b0 + j;
+        w[j] = rmq_h0(s < n ? s : n - 1, sh, skeys, grouped, box, frame);
+    }
+    __syncthreads();
+    const int64_t s = b0 + tid;
+    if (s < n) t[s] = w[tid];
+    const int top = levels - 1 < kRmqLow ? levels - 1 : kRmqLow;
+    for (int k = 1; k <= top; ++k) {
+        // w[j] holds level k - 1 wherever j + 2^(k-1) <= 512
+        const int h = 1 << (k - 1);
+        const float a0 = fmaxf(w[tid], w[tid + h]);
+        const float a1 = tid + 256 + h < 512 ? fmaxf(w[tid + 256], w[tid + 256 + h]) : w[tid + 256];
+        __syncthreads();
+        w[tid] = a0;
+        w[tid + 256] = a1;
+        __syncthreads();
+        if (s < n) t[(int64_t)k * n + s] = a0;
+    }
 }
 
 __global__ void k_rmq_level(int64_t n, int k, float *t) {
@@ -882,9 +914,9 @@ __global__ void k_rmq_level(int64_t n, int k, float *t) {
 static hipError_t build_rmq(Plan &pl, hipStream_t st) {
     const int64_t n = pl.n;
     const unsigned nbk = (unsigned)ceil_div(n, 256);
-    hipLaunchKernelGGL(k_rmq_base, dim3(nbk), dim3(256), 0, st, n, pl.sh0, pl.skeys, pl.grouped,
-                       pl.prm.box, pl.frame, pl.rmq);
-    for (int k = 1; k < pl.rmq_levels; ++k)
+    hipLaunchKernelGGL(k_rmq_low, dim3(nbk), dim3(256), 0, st, n, pl.rmq_levels, pl.sh0, pl.skeys,
+                       pl.grouped, pl.prm.box, pl.frame, pl.rmq);
+    for (int k = kRmqLow + 1; k < pl.rmq_levels; ++k)
         hipLaunchKernelGGL(k_rmq_level, dim3(nbk), dim3(256), 0, st, n, k, pl.rmq);
     return hipGetLastError();
 }
