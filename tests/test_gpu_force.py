@@ -31,6 +31,10 @@ def _setup(name):
     elif name == "clustered32k_wc6":
         ps = sphgen.plummer_mixture(1 << 15, 20, seed=53, n_target=295.0)
         kern = oracle.WENDLAND_C6
+    elif name == "coincident4396":
+        # twins at r = 0: the pair's direction is undefined and its term
+        # vanishes (f'(0) = 0) on both sides
+        ps = sphgen.with_duplicates(sphgen.uniform(4096, seed=54), 300, seed=55)
     else:
         raise KeyError(name)
     ps.m = rng.uniform(0.5, 2.0, ps.n) / ps.n
@@ -69,7 +73,7 @@ def _cmp(ps, g, o, tol_max, tol_l2=None):
     return G
 
 
-NAMES = ["uniform4096", "clustered32k", "groups60", "clustered32k_wc6"]
+NAMES = ["uniform4096", "clustered32k", "groups60", "clustered32k_wc6", "coincident4396"]
 
 
 @pytest.mark.parametrize("name", NAMES)

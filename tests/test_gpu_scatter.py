@@ -53,11 +53,15 @@ def _case(name):
     if name == "clustered32k_wc6":
         ps = sphgen.plummer_mixture(1 << 15, 20, seed=74, n_target=295.0)
         return ps, gpu_solve(ps, kernel=sph.KERNEL_WENDLAND_C6)["h"], oracle.WENDLAND_C6
+    if name == "coincident4396_solved":
+        # twins at r = 0: each one's sphere holds the other at the centre
+        ps = sphgen.with_duplicates(sphgen.uniform(4096, seed=75), 300, seed=76)
+        return ps, gpu_solve(ps)["h"], oracle.M4
     raise KeyError(name)
 
 
 NAMES = ["uniform4096_solved", "uniform3000_random_h", "clustered32k_solved",
-         "groups60_random_h", "clustered32k_wc6"]
+         "groups60_random_h", "clustered32k_wc6", "coincident4396_solved"]
 
 
 def _kern(k):
